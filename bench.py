@@ -1,0 +1,197 @@
+"""Throughput benchmark of the N-FHMM variational-inference loop on one MI355X.
+
+A step is one complete fit of a batch of J independent jobs of the paper-typical
+shape (S=2 sources, N=40 dictionaries of K=10 elements, F=513 bins, T=1000
+frames, 50 iterations): packing, the default start, every iteration (both
+dictionary contractions, the forward-backward of every chain, Eq. 6 / Eq. 8 and
+the bound) and the separation, with the inputs already resident in HBM.
+
+value = J * T * iterations / seconds per step (frame-iterations/s), FP32
+contraction.  The BF16-contraction form and a single job are measured beside it.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA = 157.3e12     # MI355X dense FP32 matrix, FLOP/s
+PEAK_BF16_MFMA = 2.5e15       # MI355X dense BF16 matrix, FLOP/s
+PEAK_HBM = 8.0e12             # B/s
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1206_6468_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_for(kernel, workload):
+    """Measured HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != _kernel_source_hash():
+        return None
+    e = d.get("kernels", {}).get(kernel, {})
+    if e.get("workload") != workload:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def make_jobs(cfg, n, iters=None):
+    from gen import make_problem
+    probs = []
+    for j in range(n):
+        p = make_problem(cfg, j)
+        if iters is not None:
+            p = dict(p, iters=iters)
+        probs.append(p)
+    return probs
+
+
+def time_batch(L, ctx, jobs, precision, steps, warmup, profile=False):
+    import torch
+    for _ in range(warmup):
+        L.fit_batch_device(ctx, jobs, precision)
+    torch.cuda.synchronize()
+    if profile:
+        L.profile_enable(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        L.fit_batch_device(ctx, jobs, precision)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    prof = None
+    if profile:
+        prof = {k: L.profile_read(ctx, k) for k in ("spectrum", "counts", "chains", "update")}
+        L.profile_enable(ctx, False)
+    return dt, prof
+
+
+def cpu_baseline(seconds_target=15.0):
+    """The FP64 oracle on the host cores: one config-1 job, one warm-up iteration,
+    then iterations until about `seconds_target` seconds have passed."""
+    import numpy as np
+
+    from gen import make_problem
+    from oracle import nfhmm_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    p = make_problem(1, 0)
+    S, N, K = p["S"], p["N"], p["K"]
+    V, beta, A, pi = O.paper_arrays(p)
+    B = O.mask_B(S, N, K)
+    alpha = O.init_alpha(V, beta, B, 1.0, N)
+    alpha = O.one_iteration(alpha, V, beta, A, pi, B, 1.0, S, N, K)["alpha"]   # warm-up
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < seconds_target:
+        alpha = O.one_iteration(alpha, V, beta, A, pi, B, 1.0, S, N, K)["alpha"]
+        n += 1
+    dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(alpha))
+    return {"value": p["T"] * n / dt, "unit": "frame-iterations/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"config-1 job 0 (S=2,N=40,K=10,F=513,T=1000): 1 warm-up + {n} timed FP64 iterations, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--jobs", type=int, default=32, help="concurrent config-1 jobs per step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the BF16 and single-job forms")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (--gpus must be 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1206_6468_amd import nfhmm as L
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    probs = make_jobs(1, args.jobs)
+    S, N, K, F, T, iters = (probs[0][k] for k in ("S", "N", "K", "F", "T", "iters"))
+    M = S * N * K
+    ctx = L.Context(0)
+    jobs = [L.DeviceJob(p) for p in probs]
+    torch.cuda.synchronize()
+
+    dt, prof = time_batch(L, ctx, jobs, "fp32", args.steps, args.warmup, profile=True)
+    J = len(jobs)
+    value = J * T * iters / dt
+
+    # roofline of the dominant kernel (largest summed device time)
+    flops_per_job_launch = {"spectrum": 2.0 * F * M * T, "counts": 2.0 * F * M * T}
+    dom = max(prof, key=lambda k: prof[k][1])
+    rows = {}
+    for k, (n, ms) in prof.items():
+        avg = ms / max(n, 1) * 1e-3
+        rows[k] = {"launches": n, "avg_ms": avg * 1e3}
+        if k in flops_per_job_launch:
+            rows[k]["achieved_tflops"] = flops_per_job_launch[k] * J / avg / 1e12
+    gemm = max(("spectrum", "counts"), key=lambda k: prof[k][1])
+    avg_g = prof[gemm][1] / max(prof[gemm][0], 1) * 1e-3
+    ach = flops_per_job_launch[gemm] * J / avg_g
+    workload = f"config1-x{J}"
+    roofline = {"bound": "mfma", "kernel": f"k_{gemm}", "achieved": ach / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": _traffic_for(f"k_{gemm}", workload),
+                "dominant_by_time": f"k_{dom}", "kernels": rows,
+                "algorithmic_flops_per_launch": flops_per_job_launch[gemm] * J}
+
+    extra = {}
+    if not args.no_extra:
+        dtb, profb = time_batch(L, ctx, jobs, "bf16", args.steps, 1, profile=True)
+        avgb = profb["counts"][1] / max(profb["counts"][0], 1) * 1e-3
+        extra["bf16"] = {"value": J * T * iters / dtb, "ms_per_step": dtb * 1e3,
+                         "k_counts_tflops": flops_per_job_launch["counts"] * J / avgb / 1e12,
+                         "k_counts_frac_of_bf16_peak": flops_per_job_launch["counts"] * J / avgb / PEAK_BF16_MFMA}
+        dt1, _ = time_batch(L, ctx, jobs[:1], "fp32", max(2, args.steps), 1)
+        extra["single_job_fp32"] = {"value": T * iters / dt1, "ms_per_fit": dt1 * 1e3}
+
+    out = {
+        "metric": "VI frame-iterations/s at S=2,N=40,F=513 (FP32 contraction)",
+        "value": value,
+        "unit": "frame-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": workload, "jobs": J, "S": S, "N": N, "K": K, "F": F, "T": T,
+                   "iterations": iters, "contraction": "fp32"},
+        "roofline": roofline,
+    }
+    out.update(extra)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

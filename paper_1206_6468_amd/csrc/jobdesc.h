@@ -1,0 +1,71 @@
+// Per-job descriptor shared by the host runtime and the kernels.
+//
+// Device layouts of one job (all row-major, padded with zeros):
+//   V      [T][Fp]     mixture spectrogram, frame-major (Fp = F rounded up to 32,
+//                      Mp = S*N*K rounded up to 32)
+//   Wfm    [Fp][Mp]    beta_l(k) with k contiguous: the operand of Lambda = beta w
+//   Wmf    [Mp][Fp]    beta_l(k) with l contiguous: the operand of beta^T R
+//   alpha  [T][Mp]     Dirichlet parameters alpha-hat (Eq. 6); the carried state
+//   E      [T][Mp]     expected log weights psi(alpha_k) - psi(alpha_0)
+//   w      [T][Mp]     exp(E) (float32, or bfloat16 in wh)
+//   R      [T][Fp]     V / Lambda (float32, or bfloat16 in Rh)
+//   c      [T][Mp]     expected counts sum_l V z (the first term of Eq. 6)
+//   phi    [S][T][64]  gamma * phi-hat (Eq. 8), one 64-lane row per frame
+//   ev     [S][T][64]  exp(gamma*phi - sh): linear-domain chain evidence
+//   sh     [S][T]      per-frame log shift of ev
+//   fwd    [S][T][64]  scaled forward messages;  bwd: scaled backward messages
+//   nrm    [S][T]      forward scale factors (ln Z = sum sh - sum ln nrm)
+//   post   [S][T][N]   state marginals d-hat
+//   vll    [nlt][T]    per (64-row tile, frame) partials of sum_l V ln Lambda (hi, lo)
+//   elbo   [iters][T]  per-frame bound contributions (hi, lo)
+//   sep    [S][T][Fp]  reconstructions, then masked separations
+//   chainflag [S]      1 if the chain's scaled messages lost posterior mass
+#pragma once
+#include <stdint.h>
+
+namespace nfhmm {
+
+constexpr int kTileM = 64;     // GEMM block tile rows
+constexpr int kTileN = 64;     // GEMM block tile columns (frames)
+constexpr int kLanes = 64;     // states per chain row (wavefront width)
+constexpr int kMaxSources = 8;
+constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
+
+enum Status : int { kOk = 0, kBadV = 1, kBadW = 2, kNonFinite = 4 };
+
+struct JobDesc {
+  int S, N, K, M, Mp, F, Fp, T;
+  int NK;            // N*K
+  int iters;
+  int start_round;   // round in which this job runs its iteration 0
+  int bf16;          // contraction operands in bfloat16
+  float gamma;
+  int nlt;           // ceil(Fp / 64)
+  int pad_;
+  double elbo_const; // T * (lnG(M + gamma S K) - S K lnG(1 + gamma))
+  // inputs in the ABI layouts (device)
+  const float *V_in, *W_in, *A_in, *pi_in, *alpha_init;
+  // working layouts
+  float *V, *Wfm, *Wmf;
+  uint16_t *Wfm_h, *Wmf_h, *wh, *Rh;
+  float *alpha, *E, *w, *R, *c;
+  float *phi, *ev, *sh, *fwd, *bwd, *nrm, *post;
+  float2 *vll, *elbo;
+  float *sep;
+  int *status;
+  int *chainflag;    // [S] set when a chain needs the exact log-space pass
+  // outputs in the ABI layouts (device), any may be null
+  float *out_alpha, *out_post, *out_sep;
+  double *out_elbo;
+};
+
+// Work lists of one launch: block b of a grouped kernel belongs to the job j with
+// start[j] <= b < start[j+1] (start[] is an exclusive prefix sum over the jobs).
+struct WorkList {
+  const JobDesc *jobs;
+  const int *start;
+  int njobs;
+  int total;
+};
+
+}  // namespace nfhmm

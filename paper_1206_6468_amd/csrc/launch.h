@@ -1,0 +1,24 @@
+// Host-side launchers of the kernels in nfhmm_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "jobdesc.h"
+
+namespace nfhmm {
+
+enum UpdateMode : int { kUpdMessages = 0, kUpdUniform = 1, kUpdFromAlpha = 2 };
+
+hipError_t launch_pack(const JobDesc &J, hipStream_t st);
+hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st);
+hipError_t launch_spectrum(const WorkList &wl, bool bf16, hipStream_t st);
+hipError_t launch_counts(const WorkList &wl, bool bf16, hipStream_t st);
+hipError_t launch_chain_fb(const WorkList &wl, int nmax, hipStream_t st);
+// d-hat from the messages (post: one block per source and 4 frames), then the exact
+// log-space pass over flagged chains (chains: one block per source).
+hipError_t launch_posterior(const WorkList &post, const WorkList &chains, int nmax, hipStream_t st);
+hipError_t launch_update(const WorkList &wl, int mode, int round, int mp_max, hipStream_t st);
+hipError_t launch_finish(const WorkList &frames, const WorkList &tiles, const WorkList &iters, hipStream_t st);
+hipError_t launch_special(int64_t n, const float *x, float *psi, float *lg, hipStream_t st);
+hipError_t launch_chain_prep(const JobDesc &J, const float *logev, hipStream_t st);
+
+}  // namespace nfhmm

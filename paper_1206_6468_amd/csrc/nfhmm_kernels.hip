@@ -1,0 +1,1043 @@
+// HIP kernels (gfx950) of variational inference in the Bayesian N-FHMM.
+//
+// One iteration of the loop (Section 3.2 of the paper) is four launches:
+//   k_spectrum   Lambda = beta w,  R = V / Lambda, partials of sum V ln Lambda
+//                (the normaliser kappa = ln Lambda of Eq. 7)            [MFMA]
+//   k_counts     c = w (.) beta^T R: sum_l V z, the first term of Eq. 6 [MFMA]
+//   k_chain_fb   forward and backward recursions of every source chain on the
+//                evidence of Eq. 8 (one wavefront per chain and direction)
+//   k_update     d-hat from the messages, Eq. 6, then psi / E / w / Eq. 8 for
+//                the next iteration, and the per-frame bound contributions
+// k_chain_fb runs on its own stream beside k_spectrum -> k_counts: given the
+// current alpha-hat the chains and the contractions do not depend on each other.
+//
+// Z-hat of Eq. 7 is never formed: z[t,l,k] = beta[l,k] w[t,k] / Lambda[l,t]
+// with w = exp(psi(alpha_tk) - psi(alpha_t0)), so sum_l V z is c[t,k] above.
+#include <hip/hip_runtime.h>
+
+#include "jobdesc.h"
+#include "launch.h"
+#include "special.h"
+
+namespace nfhmm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ int find_job(const int *start, int njobs, int b) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs (block b -> XCD b % 8).  Give each
+// XCD one contiguous range of logical tiles so that tiles sharing a job's
+// dictionary and frame panels share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
+  return x * q + min(x, r) + i;
+}
+
+__device__ __forceinline__ uint16_t f2bf(float f) {       // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ Comp wave_comp(Comp c) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    Comp d;
+    d.hi = __shfl_xor(c.hi, o);
+    d.lo = __shfl_xor(c.lo, o);
+    c = comp_merge(c, d);
+  }
+  return c;
+}
+
+// ------------------------------------------------------------------ packing
+// V_in [T][F] -> V [T][Fp]; checks V finite and >= 0.
+__global__ void k_pack_v(JobDesc J) {
+  const int t = blockIdx.x;
+  int bad = 0;
+  for (int l = threadIdx.x; l < J.Fp; l += blockDim.x) {
+    float v = 0.0f;
+    if (l < J.F) {
+      v = J.V_in[(size_t)t * J.F + l];
+      if (!(v >= 0.0f) || isinf(v)) { bad = 1; v = 0.0f; }
+    }
+    J.V[(size_t)t * J.Fp + l] = v;
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(J.status, kBadV);
+}
+
+// W_in [M][F] -> Wmf [Mp][Fp] (+ bf16); checks rows finite, >= 0, summing to 1.
+__global__ void k_pack_wmf(JobDesc J) {
+  const int k = blockIdx.x;
+  __shared__ float red[256];
+  float s = 0.0f;
+  int bad = 0;
+  for (int l = threadIdx.x; l < J.Fp; l += blockDim.x) {
+    float v = 0.0f;
+    if (k < J.M && l < J.F) {
+      v = J.W_in[(size_t)k * J.F + l];
+      if (!(v >= 0.0f) || isinf(v)) { bad = 1; v = 0.0f; }
+    }
+    s += v;
+    J.Wmf[(size_t)k * J.Fp + l] = v;
+    if (J.bf16) J.Wmf_h[(size_t)k * J.Fp + l] = f2bf(v);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const int anybad = __syncthreads_or(bad);
+  if (threadIdx.x == 0 && k < J.M && (anybad || fabsf(red[0] - 1.0f) > 1e-4f)) atomicOr(J.status, kBadW);
+}
+
+// Wmf [Mp][Fp] -> Wfm [Fp][Mp] (+ bf16), 32x32 tiles through LDS.
+__global__ void k_transpose_w(JobDesc J) {
+  __shared__ float tile[32][33];
+  const int k0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 8 rows per pass
+  for (int r = ty; r < 32; r += 8) tile[r][tx] = J.Wmf[(size_t)(k0 + r) * J.Fp + l0 + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const float v = tile[tx][r];
+    J.Wfm[(size_t)(l0 + r) * J.Mp + k0 + tx] = v;
+    if (J.bf16) J.Wfm_h[(size_t)(l0 + r) * J.Mp + k0 + tx] = f2bf(v);
+  }
+}
+
+// w = 1 on the M real elements (z-hat proportional to beta), 0 on the padding.
+__global__ void k_fill_w_ones(JobDesc J) {
+  const size_t n = (size_t)J.T * J.Mp;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float v = ((int)(i % J.Mp) < J.M) ? 1.0f : 0.0f;
+    if (J.bf16) J.wh[i] = f2bf(v); else J.w[i] = v;
+  }
+}
+
+// ------------------------------------------------------------------ MFMA tiles
+// C[i][j] = sum_k A[i][k] B[j][k] for a 64x64 block tile; 256 threads = 4 waves
+// in a 2x2 grid of 32x32 wave tiles, each 2x2 MFMA 16x16 tiles.  Operand k-slices
+// are staged through LDS.  Within every 16 (f32) or 32 (bf16) wide k-chunk lane
+// (r, q) of a fragment supplies the q-th group of consecutive k; A and B use the
+// same grouping, so every k is summed exactly once.
+struct Frag {
+  int wr, wc, lr, lq;
+};
+__device__ __forceinline__ Frag frag_of(int tid) {
+  const int wave = tid >> 6, lane = tid & 63;
+  Frag f;
+  f.wr = wave >> 1; f.wc = wave & 1; f.lr = lane & 15; f.lq = lane >> 4;
+  return f;
+}
+
+constexpr int kBKf = 32, kLdsF = kBKf + 4;          // f32: 32 k per stage, rows padded
+constexpr int kBKh = 64, kLdsH = kBKh + 8;          // bf16: 64 k per stage
+
+__device__ __forceinline__ void gload_f32(const float *__restrict__ src, int ld, int nrows, int row0, int k,
+                                          int kend, int tid, float4 (&r)[2]) {
+  const int rr = tid >> 3, c = (tid & 7) * 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int row = row0 + rr + 32 * h, kk = k + c;
+    r[h] = (row < nrows && kk < kend) ? *(const float4 *)(src + (size_t)row * ld + kk)
+                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+// k-range [kb, ke) with kb, ke arbitrary: elementwise masked (separation only).
+__device__ __forceinline__ void gload_f32_masked(const float *__restrict__ src, int ld, int nrows, int row0,
+                                                 int k, int kb, int ke, int tid, float4 (&r)[2]) {
+  const int rr = tid >> 3, c = (tid & 7) * 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int row = row0 + rr + 32 * h, kk = k + c;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (row < nrows && kk + 3 >= kb && kk < ke) {
+      v = *(const float4 *)(src + (size_t)row * ld + kk);
+      if (kk + 0 < kb || kk + 0 >= ke) v.x = 0.f;
+      if (kk + 1 < kb || kk + 1 >= ke) v.y = 0.f;
+      if (kk + 2 < kb || kk + 2 >= ke) v.z = 0.f;
+      if (kk + 3 < kb || kk + 3 >= ke) v.w = 0.f;
+    }
+    r[h] = v;
+  }
+}
+
+__device__ __forceinline__ void sstore_f32(float *lds, int tid, const float4 (&r)[2]) {
+  const int rr = tid >> 3, c = (tid & 7) * 4;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) *(float4 *)(lds + (rr + 32 * h) * kLdsF + c) = r[h];
+}
+
+__device__ __forceinline__ void mma_stage_f32(const float *As, const float *Bs, const Frag &f,
+                                              floatx4 (&acc)[2][2]) {
+#pragma unroll
+  for (int kk = 0; kk < kBKf; kk += 16) {
+    float4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *(const float4 *)(As + (f.wr * 32 + i * 16 + f.lr) * kLdsF + kk + f.lq * 4);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *(const float4 *)(Bs + (f.wc * 32 + j * 16 + f.lr) * kLdsF + kk + f.lq * 4);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].y, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, b[j].z, acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, b[j].w, acc[i][j], 0, 0, 0);
+      }
+  }
+}
+
+// Full f32 main loop over k in [kb, ke); masked selects the elementwise loader.
+template <bool kMasked>
+__device__ void gemm_nt_f32(const float *__restrict__ A, int lda, int arows, int row0, const float *__restrict__ B,
+                            int ldb, int bcols, int col0, int kb, int ke, floatx4 (&acc)[2][2]) {
+  __shared__ float As[2][64 * kLdsF];
+  __shared__ float Bs[2][64 * kLdsF];
+  const int tid = threadIdx.x;
+  const Frag f = frag_of(tid);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int k0 = kMasked ? (kb & ~3) : kb;
+  float4 ra[2], rb[2];
+  if (kMasked) {
+    gload_f32_masked(A, lda, arows, row0, k0, kb, ke, tid, ra);
+    gload_f32_masked(B, ldb, bcols, col0, k0, kb, ke, tid, rb);
+  } else {
+    gload_f32(A, lda, arows, row0, k0, ke, tid, ra);
+    gload_f32(B, ldb, bcols, col0, k0, ke, tid, rb);
+  }
+  sstore_f32(As[0], tid, ra);
+  sstore_f32(Bs[0], tid, rb);
+  __syncthreads();
+  int buf = 0;
+  for (int k = k0; k < ke; k += kBKf) {
+    const int kn = k + kBKf;
+    const bool more = kn < ke;
+    if (more) {
+      if (kMasked) {
+        gload_f32_masked(A, lda, arows, row0, kn, kb, ke, tid, ra);
+        gload_f32_masked(B, ldb, bcols, col0, kn, kb, ke, tid, rb);
+      } else {
+        gload_f32(A, lda, arows, row0, kn, ke, tid, ra);
+        gload_f32(B, ldb, bcols, col0, kn, ke, tid, rb);
+      }
+    }
+    mma_stage_f32(As[buf], Bs[buf], f, acc);
+    if (more) {
+      sstore_f32(As[buf ^ 1], tid, ra);
+      sstore_f32(Bs[buf ^ 1], tid, rb);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+__device__ __forceinline__ void gload_bf16(const uint16_t *__restrict__ src, int ld, int nrows, int row0, int k,
+                                           int kend, int tid, uint4 (&r)[2]) {
+  const int rr = tid >> 3, c = (tid & 7) * 8;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int row = row0 + rr + 32 * h, kk = k + c;
+    r[h] = (row < nrows && kk < kend) ? *(const uint4 *)(src + (size_t)row * ld + kk) : make_uint4(0, 0, 0, 0);
+  }
+}
+__device__ __forceinline__ void sstore_bf16(uint16_t *lds, int tid, const uint4 (&r)[2]) {
+  const int rr = tid >> 3, c = (tid & 7) * 8;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) *(uint4 *)(lds + (rr + 32 * h) * kLdsH + c) = r[h];
+}
+__device__ __forceinline__ void mma_stage_bf16(const uint16_t *As, const uint16_t *Bs, const Frag &f,
+                                               floatx4 (&acc)[2][2]) {
+#pragma unroll
+  for (int kk = 0; kk < kBKh; kk += 32) {
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      a[i] = *(const bf16x8 *)(As + (f.wr * 32 + i * 16 + f.lr) * kLdsH + kk + f.lq * 8);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      b[j] = *(const bf16x8 *)(Bs + (f.wc * 32 + j * 16 + f.lr) * kLdsH + kk + f.lq * 8);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+}
+
+__device__ void gemm_nt_bf16(const uint16_t *__restrict__ A, int lda, int arows, int row0,
+                             const uint16_t *__restrict__ B, int ldb, int bcols, int col0, int kend,
+                             floatx4 (&acc)[2][2]) {
+  __shared__ uint16_t As[2][64 * kLdsH];
+  __shared__ uint16_t Bs[2][64 * kLdsH];
+  const int tid = threadIdx.x;
+  const Frag f = frag_of(tid);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra[2], rb[2];
+  gload_bf16(A, lda, arows, row0, 0, kend, tid, ra);
+  gload_bf16(B, ldb, bcols, col0, 0, kend, tid, rb);
+  sstore_bf16(As[0], tid, ra);
+  sstore_bf16(Bs[0], tid, rb);
+  __syncthreads();
+  int buf = 0;
+  for (int k = 0; k < kend; k += kBKh) {
+    const int kn = k + kBKh;
+    const bool more = kn < kend;
+    if (more) {
+      gload_bf16(A, lda, arows, row0, kn, kend, tid, ra);
+      gload_bf16(B, ldb, bcols, col0, kn, kend, tid, rb);
+    }
+    mma_stage_bf16(As[buf], Bs[buf], f, acc);
+    if (more) {
+      sstore_bf16(As[buf ^ 1], tid, ra);
+      sstore_bf16(Bs[buf ^ 1], tid, rb);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// ------------------------------------------------------------------ Eq. 7: Lambda, R
+// Rows l (frequency), columns t (frames), k over all M elements.
+// Output tile element (row, col) lives in lane (lr, lq) of wave (wr, wc) at
+// acc[i][j][r] with row = wr*32 + i*16 + 4*lq + r and col = wc*32 + j*16 + lr.
+template <bool kBF16>
+__global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
+  const int b = xcd_remap(blockIdx.x, wl.total);
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int tile = b - wl.start[jb];
+  const int nrt = J.nlt;
+  const int rt = tile % nrt, ct = tile / nrt;
+  const int row0 = rt * 64, col0 = ct * 64;
+  floatx4 acc[2][2];
+  if constexpr (kBF16) gemm_nt_bf16(J.Wfm_h, J.Mp, J.Fp, row0, J.wh, J.Mp, J.T, col0, J.Mp, acc);
+  else gemm_nt_f32<false>(J.Wfm, J.Mp, J.Fp, row0, J.w, J.Mp, J.T, col0, 0, J.Mp, acc);
+
+  const Frag f = frag_of(threadIdx.x);
+  __shared__ Comp part[2][64];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int t = col0 + f.wc * 32 + j * 16 + f.lr;
+    Comp cs = comp_zero();
+    if (t < J.T) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int l = row0 + f.wr * 32 + i * 16 + 4 * f.lq;
+        if (l < J.Fp) {
+          const float4 v = *(const float4 *)(J.V + (size_t)t * J.Fp + l);
+          const float lam[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
+          const float vv[4] = {v.x, v.y, v.z, v.w};
+          float rr[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            rr[r] = vv[r] > 0.0f ? vv[r] / lam[r] : 0.0f;
+            if (vv[r] > 0.0f) comp_add(cs, vv[r] * logf(lam[r]));
+          }
+          if constexpr (kBF16) {
+            uint2 h;
+            h.x = (uint32_t)f2bf(rr[0]) | ((uint32_t)f2bf(rr[1]) << 16);
+            h.y = (uint32_t)f2bf(rr[2]) | ((uint32_t)f2bf(rr[3]) << 16);
+            *(uint2 *)(J.Rh + (size_t)t * J.Fp + l) = h;
+          } else {
+            *(float4 *)(J.R + (size_t)t * J.Fp + l) = make_float4(rr[0], rr[1], rr[2], rr[3]);
+          }
+        }
+      }
+    }
+    // reduce over the 4 lane groups that share column t
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+      Comp d;
+      d.hi = __shfl_xor(cs.hi, o);
+      d.lo = __shfl_xor(cs.lo, o);
+      cs = comp_merge(cs, d);
+    }
+    if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
+    __syncthreads();
+    if (f.lq == 0 && f.wr == 0 && t < J.T) {
+      const Comp tot = comp_merge(cs, part[f.wc][j * 16 + f.lr]);
+      J.vll[(size_t)rt * J.T + t] = make_float2(tot.hi, tot.lo);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ Eq. 6 first term: c
+template <bool kBF16>
+__global__ __launch_bounds__(256) void k_counts(WorkList wl) {
+  const int b = xcd_remap(blockIdx.x, wl.total);
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int tile = b - wl.start[jb];
+  const int nrt = (J.Mp + 63) / 64;
+  const int rt = tile % nrt, ct = tile / nrt;
+  const int row0 = rt * 64, col0 = ct * 64;
+  floatx4 acc[2][2];
+  if constexpr (kBF16) gemm_nt_bf16(J.Wmf_h, J.Fp, J.Mp, row0, J.Rh, J.Fp, J.T, col0, J.Fp, acc);
+  else gemm_nt_f32<false>(J.Wmf, J.Fp, J.Mp, row0, J.R, J.Fp, J.T, col0, 0, J.Fp, acc);
+  const Frag f = frag_of(threadIdx.x);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int t = col0 + f.wc * 32 + j * 16 + f.lr;
+    if (t >= J.T) continue;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int k = row0 + f.wr * 32 + i * 16 + 4 * f.lq;
+      if (k >= J.Mp) continue;
+      float4 w;
+      if constexpr (kBF16) {
+        const uint2 h = *(const uint2 *)(J.wh + (size_t)t * J.Mp + k);
+        w = make_float4(bf2f((uint16_t)(h.x & 0xffff)), bf2f((uint16_t)(h.x >> 16)), bf2f((uint16_t)(h.y & 0xffff)),
+                        bf2f((uint16_t)(h.y >> 16)));
+      } else {
+        w = *(const float4 *)(J.w + (size_t)t * J.Mp + k);
+      }
+      *(float4 *)(J.c + (size_t)t * J.Mp + k) =
+          make_float4(w.x * acc[i][j][0], w.y * acc[i][j][1], w.z * acc[i][j][2], w.w * acc[i][j][3]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ forward-backward
+// One 64-lane wavefront per (job, source, direction).  Lane n < N owns state n.
+// Messages are linear vectors with per-frame log offsets (the scaled recursion of
+// Rabiner's tutorial, which the paper cites): the evidence row of frame t is
+// ev = exp(gamma*phi - sh_t) <= 2^64, and ln Z = sum_t sh_t - sum_t ln nrm_t.
+// Lane N (the first unused lane) holds one extra row of the transition
+// operator so that the normaliser comes out of the same FMA pass: all ones in
+// the forward direction (sum of the incoming message), the column sums of A in
+// the backward direction (sum of the outgoing message).  For N = 64 a shuffle
+// reduction is used instead.
+// The largest entry of every forward message and of every backward message times
+// the evidence is kept above 2^-20: a frame where all of them would fall below is
+// redone in log space with its own shift (recorded in sh for the forward
+// direction).  States that end up more than ~100 nats below a frame's best are
+// flushed to zero; k_posterior detects the frames where that could matter and
+// k_chain_exact then recomputes the chain entirely in log space.
+constexpr float kRescue = 9.5367431640625e-07f;   // 2^-20
+
+template <int NR>
+__global__ __launch_bounds__(64) void k_chain_fb(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int local = b - wl.start[jb];
+  const int s = local >> 1, dir = local & 1;
+  const int lane = threadIdx.x;
+  const int N = J.N, T = J.T;
+  const bool sumlane = N < 64;
+  const float *A = J.A_in + (size_t)s * N * N;
+  const float *ev = J.ev + (size_t)s * T * 64;
+  const float *phi = J.phi + (size_t)s * T * 64;
+  __shared__ __attribute__((aligned(16))) float buf[2][NR];
+  float coef[NR];
+#pragma unroll
+  for (int m = 0; m < NR; ++m) {
+    float v = 0.0f;
+    if (m < N) {
+      if (lane < N) {
+        v = dir == 0 ? A[(size_t)m * N + lane] : A[(size_t)lane * N + m];
+      } else if (lane == N) {
+        if (dir == 0) {
+          v = 1.0f;
+        } else {
+          for (int i = 0; i < N; ++i) v += A[(size_t)i * N + m];
+        }
+      }
+    }
+    coef[m] = v;
+  }
+  const bool live = lane < N;
+  if (dir == 0 && lane == 0) J.chainflag[s] = 0;
+
+  auto matvec = [&](int p) -> float {
+    float y0 = 0.0f, y1 = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NR / 4; ++q) {
+      const float4 v = *(const float4 *)(&buf[p][4 * q]);
+      y0 = fmaf(v.x, coef[4 * q + 0], y0);
+      y1 = fmaf(v.y, coef[4 * q + 1], y1);
+      y0 = fmaf(v.z, coef[4 * q + 2], y0);
+      y1 = fmaf(v.w, coef[4 * q + 3], y1);
+    }
+    return y0 + y1;
+  };
+  // value of lane N's row (sum-lane mode) or the same sum by reduction of x
+  auto total_of = [&](float y, float x) -> float {
+    if (sumlane) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), N));
+    return wave_sum(live ? x : 0.0f);
+  };
+
+  if (dir == 0) {
+    float *fwd = J.fwd + (size_t)s * T * 64;
+    float *nrm = J.nrm + (size_t)s * T;
+    float *sh = J.sh + (size_t)s * T;
+    const float *pi = J.pi_in + (size_t)s * N;
+    float u;
+    {
+      const float p0 = live ? pi[lane] : 0.0f;
+      u = p0 * ev[lane];
+      if (__ballot(live && u > kRescue) == 0) {   // frame 0 in log space
+        const float x = live ? logf(p0) + phi[lane] : -INFINITY;
+        const float mx = wave_max(x);
+        u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+        if (lane == 0) sh[0] = mx - kEvHeadroomLog;
+      }
+      fwd[lane] = u;
+    }
+    float ering[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ering[i] = (1 + i < T) ? ev[(size_t)(1 + i) * 64 + lane] : 0.0f;
+    int p = 0;
+    for (int t0 = 1; t0 < T; t0 += 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int t = t0 + i;
+        if (t < T) {
+          const float e = ering[i];
+          ering[i] = (t + 8 < T) ? ev[(size_t)(t + 8) * 64 + lane] : 0.0f;
+          if (lane < NR) buf[p][lane] = u;
+          __syncthreads();
+          const float y = matvec(p);
+          const float tot = total_of(y, u);
+          const float r = 1.0f / tot;
+          if (lane == 0) nrm[t - 1] = r;
+          const float yr = y * r;
+          u = yr * e;
+          if (__ballot(live && u > kRescue) == 0) {
+            const float x = live ? logf(yr) + phi[(size_t)t * 64 + lane] : -INFINITY;
+            const float mx = wave_max(x);
+            u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+            if (lane == 0) sh[t] = mx - kEvHeadroomLog;
+          }
+          fwd[(size_t)t * 64 + lane] = u;
+          p ^= 1;
+        }
+      }
+    }
+    const float last = wave_sum(live ? u : 0.0f);
+    if (lane == 0) nrm[T - 1] = 1.0f / last;
+  } else {
+    float *bwd = J.bwd + (size_t)s * T * 64;
+    // b_{T-1} = 1; q = e_{T-1} * b_{T-1}
+    const float bcur = live ? 1.0f : 0.0f;
+    bwd[(size_t)(T - 1) * 64 + lane] = bcur;
+    float q = bcur * ev[(size_t)(T - 1) * 64 + lane];
+    if (__ballot(live && q > kRescue) == 0) {
+      const float x = live ? phi[(size_t)(T - 1) * 64 + lane] : -INFINITY;
+      const float mx = wave_max(x);
+      q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+    }
+    float ering[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ering[i] = (T - 2 - i >= 0) ? ev[(size_t)(T - 2 - i) * 64 + lane] : 0.0f;
+    int p = 0;
+    for (int t0 = T - 2; t0 >= 0; t0 -= 8) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int t = t0 - i;
+        if (t >= 0) {
+          const float e = ering[i];
+          ering[i] = (t - 8 >= 0) ? ev[(size_t)(t - 8) * 64 + lane] : 0.0f;
+          if (lane < NR) buf[p][lane] = q;
+          __syncthreads();
+          const float y = matvec(p);
+          const float tot = total_of(y, y);   // sum of the outgoing message
+          const float bb = y * (1.0f / tot);
+          bwd[(size_t)t * 64 + lane] = bb;
+          q = bb * e;
+          if (__ballot(live && q > kRescue) == 0) {
+            const float x = live ? logf(bb) + phi[(size_t)t * 64 + lane] : -INFINITY;
+            const float mx = wave_max(x);
+            q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+          }
+          p ^= 1;
+        }
+      }
+    }
+  }
+}
+
+// d-hat of every (job, source, frame) from the scaled messages: one wavefront per
+// (source, frame), four per block.  A chain is flagged for the exact log-space
+// pass when at some frame the best forward x backward product falls more than
+// 40 nats below (best forward) x (best backward), or is not finite: only then can
+// states flushed by the scaled recursion carry posterior mass.
+constexpr float kAgreeNats = 40.0f;
+
+__global__ __launch_bounds__(256) void k_posterior(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int local = b - wl.start[jb];
+  const int groups = (J.T + 3) >> 2;
+  const int s = local / groups;
+  const int t = (local - s * groups) * 4 + (threadIdx.x >> 6);
+  if (t >= J.T) return;
+  const int lane = threadIdx.x & 63;
+  const bool live = lane < J.N;
+  const size_t o = ((size_t)s * J.T + t) * 64 + lane;
+  const float lf = live ? logf(J.fwd[o]) : -INFINITY;
+  const float lb = live ? logf(J.bwd[o]) : -INFINITY;
+  const float x = lf + lb;
+  const float mx = wave_max(x);
+  const float e = live ? expf(x - mx) : 0.0f;
+  const float d = e / wave_sum(e);
+  if (live) J.post[((size_t)s * J.T + t) * J.N + lane] = d;
+  const float agree = mx - wave_max(lf) - wave_max(lb);
+  if (lane == 0 && !(agree >= -kAgreeNats)) atomicOr(J.chainflag + s, 1);
+}
+
+// Exact log-space forward-backward of a flagged chain (one wavefront per chain;
+// returns at once for unflagged chains).  Each lane n evaluates
+//   l_t(n) = gamma*phi_t(n) + lse_m( la_{t-1}(m) + ln A[m][n] )
+// with its own maximum, so no value is flushed; messages are kept log-normalised
+// and the increments of ln Z go to sh (with nrm = 1).  The backward sweep then
+// forms d-hat = exp(la + lb - lse(la + lb)) directly.
+template <int NR>
+__global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int s = b - wl.start[jb];
+  if (J.chainflag[s] == 0) return;
+  const int lane = threadIdx.x;
+  const int N = J.N, T = J.T;
+  const bool live = lane < N;
+  const float *A = J.A_in + (size_t)s * N * N;
+  const float *phi = J.phi + (size_t)s * T * 64;
+  float *la = J.fwd + (size_t)s * T * 64;     // log forward messages (overwrites the scaled ones)
+  float *sh = J.sh + (size_t)s * T;
+  float *nrm = J.nrm + (size_t)s * T;
+  __shared__ float buf[NR];
+  float lac[NR];
+  // forward: column n of ln A
+#pragma unroll
+  for (int m = 0; m < NR; ++m) lac[m] = (live && m < N) ? logf(A[(size_t)m * N + lane]) : -INFINITY;
+  const float *pi = J.pi_in + (size_t)s * N;
+  float cur = live ? logf(pi[lane]) + phi[lane] : -INFINITY;
+  auto lse_lanes = [&](float x) -> float {
+    const float mx = wave_max(x);
+    if (!(mx > -INFINITY)) return mx;
+    return mx + logf(wave_sum(live ? expf(x - mx) : 0.0f));
+  };
+  float c = lse_lanes(cur);
+  cur = live ? cur - c : -INFINITY;
+  la[lane] = cur;
+  if (lane == 0) { sh[0] = c; nrm[0] = 1.0f; }
+  for (int t = 1; t < T; ++t) {
+    if (lane < NR) buf[lane] = cur;
+    __syncthreads();
+    float mx = -INFINITY;
+#pragma unroll
+    for (int m = 0; m < NR; ++m) mx = fmaxf(mx, buf[m] + lac[m]);
+    float acc = 0.0f;
+    if (mx > -INFINITY) {
+#pragma unroll
+      for (int m = 0; m < NR; ++m) acc += expf(buf[m] + lac[m] - mx);
+    }
+    __syncthreads();
+    const float l = (live && mx > -INFINITY) ? phi[(size_t)t * 64 + lane] + mx + logf(acc) : -INFINITY;
+    c = lse_lanes(l);
+    cur = live ? l - c : -INFINITY;
+    la[(size_t)t * 64 + lane] = cur;
+    if (lane == 0) { sh[t] = c; nrm[t] = 1.0f; }
+  }
+  // backward with row m of ln A in lane m; d-hat on the way
+#pragma unroll
+  for (int n = 0; n < NR; ++n) lac[n] = (live && n < N) ? logf(A[(size_t)lane * N + n]) : -INFINITY;
+  float lb = live ? 0.0f : -INFINITY;
+  for (int t = T - 1; t >= 0; --t) {
+    if (t < T - 1) {
+      const float w = live ? lb + phi[(size_t)(t + 1) * 64 + lane] : -INFINITY;
+      if (lane < NR) buf[lane] = w;
+      __syncthreads();
+      float mx = -INFINITY;
+#pragma unroll
+      for (int n = 0; n < NR; ++n) mx = fmaxf(mx, buf[n] + lac[n]);
+      float acc = 0.0f;
+      if (mx > -INFINITY) {
+#pragma unroll
+        for (int n = 0; n < NR; ++n) acc += expf(buf[n] + lac[n] - mx);
+      }
+      __syncthreads();
+      const float l = (live && mx > -INFINITY) ? mx + logf(acc) : -INFINITY;
+      const float cb = lse_lanes(l);
+      lb = (live && cb > -INFINITY) ? l - cb : -INFINITY;
+    }
+    const float x = live ? la[(size_t)t * 64 + lane] + lb : -INFINITY;
+    const float z = lse_lanes(x);
+    if (live) J.post[((size_t)s * T + t) * N + lane] = expf(x - z);
+  }
+}
+
+// ------------------------------------------------------------------ Eq. 6 + Eq. 7/8 inputs
+// One block of 256 threads per (job, frame).  Modes:
+//   kUpdMessages: d-hat from this iteration's messages, alpha = c + gamma B'd + 1,
+//                 and the frame's bound contribution for iteration (round - start);
+//   kUpdUniform:  the default start: alpha = c + gamma/N + 1 (c computed with w = 1);
+//   kUpdFromAlpha: alpha read from alpha_init ([T][M], warm start / resume).
+// Then, in every mode: alpha_0, E = psi(alpha) - psi(alpha_0), w = exp(E), and
+// gamma*phi (Eq. 8) with its shifted exponential for the next chain pass.
+__global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round) {
+  extern __shared__ float sE[];                  // [Mp]
+  __shared__ float sD[kMaxSources * 64];         // d-hat, then gamma*phi
+  __shared__ Comp red[4][4];
+  __shared__ float bcast[4];
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int t = b - wl.start[jb];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int S = J.S, N = J.N, K = J.K, M = J.M, Mp = J.Mp, T = J.T;
+  const float gamma = J.gamma;
+  const size_t row = (size_t)t * Mp;
+
+  Comp chain = comp_zero();
+  // ---- d-hat of every source at frame t (from k_posterior / k_chain_exact)
+  if (mode == kUpdMessages) {
+    for (int s = wave; s < S; s += 4) {
+      const size_t o = ((size_t)s * T + t) * 64 + lane;
+      const bool live = lane < N;
+      const float d = live ? J.post[((size_t)s * T + t) * N + lane] : 0.0f;
+      sD[s * 64 + lane] = d;
+      // -gamma sum_n d phi (phi holds gamma*phi-hat) and this frame's part of ln Z
+      Comp c = comp_zero();
+      if (live) comp_add(c, -d * J.phi[o]);
+      c = wave_comp(c);
+      if (lane == 0) {
+        comp_add(c, J.sh[(size_t)s * T + t]);
+        comp_add(c, -logf(J.nrm[(size_t)s * T + t]));
+        chain = comp_merge(chain, c);
+      }
+    }
+  } else {
+    for (int i = tid; i < S * 64; i += 256) sD[i] = ((i & 63) < N) ? 1.0f / (float)N : 0.0f;
+    for (int i = tid; i < S * N; i += 256) J.post[((size_t)(i / N) * T + t) * N + (i % N)] = 1.0f / (float)N;
+  }
+  __syncthreads();
+
+  // ---- Eq. 6 and the sums over k
+  Comp asum = comp_zero(), lg = comp_zero(), ce = comp_zero();
+  for (int k = tid; k < Mp; k += 256) {
+    float a = 0.0f;
+    if (k < M) {
+      if (mode == kUpdFromAlpha) {
+        a = J.alpha_init[(size_t)t * M + k];
+      } else {
+        const int s = k / J.NK, n = (k / K) % N;
+        const float cc = J.c[row + k];
+        a = cc + gamma * sD[s * 64 + n] + 1.0f;
+        if (mode == kUpdMessages) {
+          comp_add(ce, -cc * J.E[row + k]);
+          comp_add(lg, lgammaf_pos(a));
+        }
+      }
+      comp_add(asum, a);
+    }
+    sE[k] = a;
+    J.alpha[row + k] = a;
+  }
+  // block reduction of (asum, lg, ce)
+  asum = wave_comp(asum);
+  lg = wave_comp(lg);
+  ce = wave_comp(ce);
+  if (lane == 0) { red[wave][0] = asum; red[wave][1] = lg; red[wave][2] = ce; red[wave][3] = chain; }
+  __syncthreads();
+  if (tid == 0) {
+    Comp a = red[0][0];
+    for (int w2 = 1; w2 < 4; ++w2) a = comp_merge(a, red[w2][0]);
+    bcast[0] = a.hi + a.lo;
+  }
+  __syncthreads();
+  const float a0 = bcast[0];
+  const float psi0 = digammaf(a0);
+
+  // ---- E, w
+  for (int k = tid; k < Mp; k += 256) {
+    float e = 0.0f, w = 0.0f;
+    if (k < M) {
+      e = digammaf(sE[k]) - psi0;
+      w = expf(e);
+    }
+    sE[k] = e;
+    J.E[row + k] = e;
+    if (J.bf16) J.wh[row + k] = f2bf(w); else J.w[row + k] = w;
+  }
+  __syncthreads();
+
+  // ---- Eq. 8: gamma * phi-hat, its per-frame shift and linear evidence
+  for (int s = wave; s < S; s += 4) {
+    const bool live = lane < N;
+    float x = -INFINITY;
+    if (live) {
+      float acc = 0.0f;
+      const float *seg = sE + (s * N + lane) * K;
+      for (int j = 0; j < K; ++j) acc += seg[j];
+      x = gamma * acc;
+    }
+    const float mx = wave_max(x);
+    const size_t o = ((size_t)s * T + t) * 64 + lane;
+    J.phi[o] = live ? x : 0.0f;
+    J.ev[o] = live ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+    if (lane == 0) J.sh[(size_t)s * T + t] = mx - kEvHeadroomLog;
+  }
+
+  // ---- bound contribution of frame t
+  if (mode == kUpdMessages && tid == 0) {
+    Comp tot = red[0][1];
+    for (int w2 = 1; w2 < 4; ++w2) tot = comp_merge(tot, red[w2][1]);
+    comp_add(tot, -lgammaf_pos(a0));
+    for (int w2 = 0; w2 < 4; ++w2) tot = comp_merge(tot, red[w2][2]);
+    for (int w2 = 0; w2 < 4; ++w2) tot = comp_merge(tot, red[w2][3]);
+    for (int r = 0; r < J.nlt; ++r) {
+      const float2 v = J.vll[(size_t)r * T + t];
+      Comp d; d.hi = v.x; d.lo = v.y;
+      tot = comp_merge(tot, d);
+    }
+    const int it = round - J.start_round;
+    J.elbo[(size_t)it * T + t] = make_float2(tot.hi, tot.lo);
+  }
+}
+
+// ------------------------------------------------------------------ Section 4
+// E[theta_t] = alpha_t / alpha_t0 into the c buffer (one block per frame).
+__global__ __launch_bounds__(256) void k_theta(WorkList wl) {
+  __shared__ Comp red[4];
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int t = b - wl.start[jb];
+  const size_t row = (size_t)t * J.Mp;
+  Comp s = comp_zero();
+  for (int k = threadIdx.x; k < J.M; k += 256) comp_add(s, J.alpha[row + k]);
+  s = wave_comp(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  Comp a = red[0];
+  for (int w2 = 1; w2 < 4; ++w2) a = comp_merge(a, red[w2]);
+  const float inv = 1.0f / (a.hi + a.lo);
+  for (int k = threadIdx.x; k < J.Mp; k += 256) J.c[row + k] = k < J.M ? J.alpha[row + k] * inv : 0.0f;
+}
+
+// Vhat^(s) = beta_s E[theta]_s, rows l, columns t, k over source s's elements.
+// Work: per job S * nlt * ceil(T/64) tiles.
+__global__ __launch_bounds__(256) void k_reconstruct(WorkList wl) {
+  const int b = xcd_remap(blockIdx.x, wl.total);
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  int tile = b - wl.start[jb];
+  const int nct = (J.T + 63) / 64;
+  const int per_s = J.nlt * nct;
+  const int s = tile / per_s;
+  tile -= s * per_s;
+  const int rt = tile % J.nlt, ct = tile / J.nlt;
+  const int row0 = rt * 64, col0 = ct * 64;
+  const int kb = s * J.NK, ke = kb + J.NK;
+  floatx4 acc[2][2];
+  gemm_nt_f32<true>(J.Wfm, J.Mp, J.Fp, row0, J.c, J.Mp, J.T, col0, kb, ke, acc);
+  const Frag f = frag_of(threadIdx.x);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int t = col0 + f.wc * 32 + j * 16 + f.lr;
+    if (t >= J.T) continue;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int l = row0 + f.wr * 32 + i * 16 + 4 * f.lq;
+      if (l >= J.Fp) continue;
+      *(float4 *)(J.sep + ((size_t)s * J.T + t) * J.Fp + l) =
+          make_float4(acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]);
+    }
+  }
+}
+
+// Ratio mask V* = V Vhat^(s) / sum_s' Vhat^(s') and export of every output in the
+// ABI layouts.  One block per (job, frame).
+__global__ __launch_bounds__(256) void k_mask_export(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int t = b - wl.start[jb];
+  const int S = J.S;
+  for (int l = threadIdx.x; l < J.F; l += 256) {
+    const float v = J.V[(size_t)t * J.Fp + l];
+    float tot = 0.0f;
+    for (int s = 0; s < S; ++s) tot += J.sep[((size_t)s * J.T + t) * J.Fp + l];
+    for (int s = 0; s < S; ++s) {
+      const float vh = J.sep[((size_t)s * J.T + t) * J.Fp + l];
+      const float o = v > 0.0f ? (tot > 0.0f ? v * (vh / tot) : v / (float)S) : 0.0f;
+      if (J.out_sep) J.out_sep[((size_t)s * J.T + t) * J.F + l] = o;
+    }
+  }
+  if (J.out_alpha)
+    for (int k = threadIdx.x; k < J.M; k += 256) J.out_alpha[(size_t)t * J.M + k] = J.alpha[(size_t)t * J.Mp + k];
+  if (J.out_post)
+    for (int i = threadIdx.x; i < S * J.N; i += 256) {
+      const int s = i / J.N, n = i % J.N;
+      J.out_post[((size_t)s * J.T + t) * J.N + n] = J.post[((size_t)s * J.T + t) * J.N + n];
+    }
+}
+
+// Sum of the per-frame contributions of every iteration (fixed order,
+// compensated), plus the constant T * C.  One block per (job, iteration).
+__global__ __launch_bounds__(256) void k_elbo_reduce(WorkList wl) {
+  __shared__ Comp red[4];
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int it = b - wl.start[jb];
+  Comp s = comp_zero();
+  for (int t = threadIdx.x; t < J.T; t += 256) {
+    const float2 v = J.elbo[(size_t)it * J.T + t];
+    Comp d; d.hi = v.x; d.lo = v.y;
+    s = comp_merge(s, d);
+  }
+  s = wave_comp(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Comp a = red[0];
+    for (int w2 = 1; w2 < 4; ++w2) a = comp_merge(a, red[w2]);
+    const double L = (double)a.hi + (double)a.lo + J.elbo_const;
+    if (J.out_elbo) J.out_elbo[it] = L;
+    if (!isfinite(L)) atomicOr(J.status, kNonFinite);
+  }
+}
+
+// ------------------------------------------------------------------ building blocks
+__global__ void k_special(int64_t n, const float *x, float *psi, float *lg) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (psi) psi[i] = digammaf(x[i]);
+    if (lg) lg[i] = lgammaf_pos(x[i]);
+  }
+}
+
+// Chain-only problem: phi <- logev rows (padded to 64), ev / sh as k_update makes them.
+__global__ void k_chain_prep(JobDesc J, const float *logev) {
+  const int t = blockIdx.x, lane = threadIdx.x;
+  const bool live = lane < J.N;
+  const float x = live ? logev[(size_t)t * J.N + lane] : -INFINITY;
+  const float mx = wave_max(x);
+  J.phi[(size_t)t * 64 + lane] = live ? x : 0.0f;
+  J.ev[(size_t)t * 64 + lane] = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+  if (lane == 0) J.sh[t] = mx - kEvHeadroomLog;
+}
+
+// ------------------------------------------------------------------ launchers
+static inline hipError_t last() { return hipGetLastError(); }
+
+hipError_t launch_pack(const JobDesc &J, hipStream_t st) {
+  k_pack_v<<<J.T, 256, 0, st>>>(J);
+  k_pack_wmf<<<J.Mp, 256, 0, st>>>(J);
+  k_transpose_w<<<dim3(J.Mp / 32, J.Fp / 32), 256, 0, st>>>(J);
+  return last();
+}
+
+hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st) {
+  k_fill_w_ones<<<256, 256, 0, st>>>(J);
+  return last();
+}
+
+hipError_t launch_spectrum(const WorkList &wl, bool bf16, hipStream_t st) {
+  if (wl.total <= 0) return last();
+  if (bf16) k_spectrum<true><<<wl.total, 256, 0, st>>>(wl);
+  else k_spectrum<false><<<wl.total, 256, 0, st>>>(wl);
+  return last();
+}
+
+hipError_t launch_counts(const WorkList &wl, bool bf16, hipStream_t st) {
+  if (wl.total <= 0) return last();
+  if (bf16) k_counts<true><<<wl.total, 256, 0, st>>>(wl);
+  else k_counts<false><<<wl.total, 256, 0, st>>>(wl);
+  return last();
+}
+
+hipError_t launch_chain_fb(const WorkList &wl, int nmax, hipStream_t st) {
+  if (wl.total <= 0) return last();
+  const int nr = (nmax + 3) & ~3;
+#define NFHMM_FB_CASE(R) \
+  case R: k_chain_fb<R><<<wl.total, 64, 0, st>>>(wl); break;
+  switch (nr) {
+    NFHMM_FB_CASE(4) NFHMM_FB_CASE(8) NFHMM_FB_CASE(12) NFHMM_FB_CASE(16)
+    NFHMM_FB_CASE(20) NFHMM_FB_CASE(24) NFHMM_FB_CASE(28) NFHMM_FB_CASE(32)
+    NFHMM_FB_CASE(36) NFHMM_FB_CASE(40) NFHMM_FB_CASE(44) NFHMM_FB_CASE(48)
+    NFHMM_FB_CASE(52) NFHMM_FB_CASE(56) NFHMM_FB_CASE(60) NFHMM_FB_CASE(64)
+    default: return hipErrorInvalidValue;
+  }
+#undef NFHMM_FB_CASE
+  return last();
+}
+
+hipError_t launch_posterior(const WorkList &post, const WorkList &chains, int nmax, hipStream_t st) {
+  if (post.total > 0) k_posterior<<<post.total, 256, 0, st>>>(post);
+  if (chains.total <= 0) return last();
+  const int nr = (nmax + 3) & ~3;
+#define NFHMM_EX_CASE(R) \
+  case R: k_chain_exact<R><<<chains.total, 64, 0, st>>>(chains); break;
+  switch (nr) {
+    NFHMM_EX_CASE(4) NFHMM_EX_CASE(8) NFHMM_EX_CASE(12) NFHMM_EX_CASE(16)
+    NFHMM_EX_CASE(20) NFHMM_EX_CASE(24) NFHMM_EX_CASE(28) NFHMM_EX_CASE(32)
+    NFHMM_EX_CASE(36) NFHMM_EX_CASE(40) NFHMM_EX_CASE(44) NFHMM_EX_CASE(48)
+    NFHMM_EX_CASE(52) NFHMM_EX_CASE(56) NFHMM_EX_CASE(60) NFHMM_EX_CASE(64)
+    default: return hipErrorInvalidValue;
+  }
+#undef NFHMM_EX_CASE
+  return last();
+}
+
+hipError_t launch_update(const WorkList &wl, int mode, int round, int mp_max, hipStream_t st) {
+  if (wl.total > 0) k_update<<<wl.total, 256, (size_t)mp_max * sizeof(float), st>>>(wl, mode, round);
+  return last();
+}
+
+hipError_t launch_finish(const WorkList &frames, const WorkList &tiles, const WorkList &iters, hipStream_t st) {
+  if (frames.total > 0) k_theta<<<frames.total, 256, 0, st>>>(frames);
+  if (tiles.total > 0) k_reconstruct<<<tiles.total, 256, 0, st>>>(tiles);
+  if (frames.total > 0) k_mask_export<<<frames.total, 256, 0, st>>>(frames);
+  if (iters.total > 0) k_elbo_reduce<<<iters.total, 256, 0, st>>>(iters);
+  return last();
+}
+
+hipError_t launch_special(int64_t n, const float *x, float *psi, float *lg, hipStream_t st) {
+  const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  if (n > 0) k_special<<<blocks, 256, 0, st>>>(n, x, psi, lg);
+  return last();
+}
+
+hipError_t launch_chain_prep(const JobDesc &J, const float *logev, hipStream_t st) {
+  k_chain_prep<<<J.T, 64, 0, st>>>(J, logev);
+  return last();
+}
+
+
+}  // namespace nfhmm

@@ -1,0 +1,1087 @@
+// Host runtime and C ABI (include/nfhmm.h).
+//
+// A job owns one device allocation (its arena) holding every array of
+// jobdesc.h.  The engine advances a set of resident jobs in rounds: each round
+// is one iteration of every resident job, issued as a handful of grouped
+// launches whose blocks are dealt out over all jobs (work lists).  Blocking
+// fits run rounds until their jobs are done; the serving loop runs the same
+// rounds on a scheduler thread and admits queued jobs between rounds.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/nfhmm.h"
+#include "jobdesc.h"
+#include "launch.h"
+
+using namespace nfhmm;
+
+namespace {
+
+thread_local std::string g_err = "";
+
+nfhmm_status fail(nfhmm_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_OK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(NFHMM_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+inline int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ dims / layout
+struct Dims {
+  int S, N, K, M, Mp, F, Fp, T, iters;
+  bool bf16;
+};
+
+bool dims_ok(const nfhmm_problem *p, std::string *why) {
+  auto bad = [&](const char *m) { if (why) *why = m; return false; };
+  if (!p) return bad("problem is NULL");
+  if (p->S < 1 || p->S > NFHMM_MAX_SOURCES) return bad("S out of range [1, 8]");
+  if (p->N < 1 || p->N > NFHMM_MAX_STATES) return bad("N out of range [1, 64]");
+  if (p->K < 1) return bad("K must be >= 1");
+  if ((int64_t)p->S * p->N * p->K > NFHMM_MAX_ELEMENTS) return bad("S*N*K exceeds NFHMM_MAX_ELEMENTS");
+  if (p->F < 1 || p->F > (1 << 20)) return bad("F out of range");
+  if (p->T < 1 || p->T > (1 << 22)) return bad("T out of range");
+  if (p->iters < 0 || p->iters > (1 << 20)) return bad("iters out of range");
+  if (!(p->gamma >= 0.0f) || !std::isfinite(p->gamma)) return bad("gamma must be finite and >= 0");
+  const int64_t M = (int64_t)p->S * p->N * p->K;
+  const int64_t Mp = rup(M, 32), Fp = rup(p->F, 32);
+  if (p->T * std::max(Mp, Fp) * p->S >= (int64_t)1 << 31) return bad("T * max(M, F) * S too large");
+  if (Fp * Mp >= (int64_t)1 << 31) return bad("F * M too large");
+  if (!p->V || !p->W || !p->A || !p->pi) return bad("V, W, A and pi are required");
+  return true;
+}
+
+Dims dims_of(const nfhmm_problem *p, nfhmm_precision prec) {
+  Dims d;
+  d.S = p->S; d.N = p->N; d.K = p->K; d.M = p->S * p->N * p->K;
+  d.Mp = (int)rup(d.M, 32); d.F = (int)p->F; d.Fp = (int)rup(p->F, 32); d.T = (int)p->T;
+  d.iters = p->iters; d.bf16 = prec == NFHMM_BF16;
+  return d;
+}
+
+// Byte offsets of every array inside a job's arena.
+struct Layout {
+  size_t V_in, W_in, A_in, pi_in, alpha_init;                // host-input copies
+  size_t V, Wfm, Wmf, Wfm_h, Wmf_h, wh, Rh, w, R;
+  size_t alpha, E, c, phi, ev, sh, fwd, bwd, nrm, post, vll, elbo, sep, status, chainflag;
+  size_t out_alpha, out_post, out_sep, out_elbo;              // host-output staging
+  size_t total;
+};
+
+Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
+  const size_t T = d.T, S = d.S, N = d.N, M = d.M, Mp = d.Mp, F = d.F, Fp = d.Fp;
+  const size_t nlt = (Fp + 63) / 64, it = std::max(d.iters, 1);
+  const size_t none = ~size_t(0);
+  L.V_in = host_in ? take(T * F * 4) : none;
+  L.W_in = host_in ? take(M * F * 4) : none;
+  L.A_in = host_in ? take(S * N * N * 4) : none;
+  L.pi_in = host_in ? take(S * N * 4) : none;
+  L.alpha_init = (host_in && has_init) ? take(T * M * 4) : none;
+  L.V = take(T * Fp * 4);
+  L.Wfm = take(Fp * Mp * 4);
+  L.Wmf = take(Fp * Mp * 4);
+  L.Wfm_h = d.bf16 ? take(Fp * Mp * 2) : none;
+  L.Wmf_h = d.bf16 ? take(Fp * Mp * 2) : none;
+  L.wh = d.bf16 ? take(T * Mp * 2) : none;
+  L.Rh = d.bf16 ? take(T * Fp * 2) : none;
+  L.w = d.bf16 ? none : take(T * Mp * 4);
+  L.R = d.bf16 ? none : take(T * Fp * 4);
+  L.alpha = take(T * Mp * 4);
+  L.E = take(T * Mp * 4);
+  L.c = take(T * Mp * 4);
+  L.phi = take(S * T * 64 * 4);
+  L.ev = take(S * T * 64 * 4);
+  L.sh = take(S * T * 4);
+  L.fwd = take(S * T * 64 * 4);
+  L.bwd = take(S * T * 64 * 4);
+  L.nrm = take(S * T * 4);
+  L.post = take(S * T * N * 4);
+  L.vll = take(nlt * T * 8);
+  L.elbo = take(it * T * 8);
+  L.sep = take(S * T * Fp * 4);
+  L.status = take(4);
+  L.chainflag = take(S * 4);
+  L.out_alpha = host_out ? take(T * M * 4) : none;
+  L.out_post = host_out ? take(S * T * N * 4) : none;
+  L.out_sep = host_out ? take(S * T * F * 4) : none;
+  L.out_elbo = host_out ? take(it * 8) : none;
+  L.total = off;
+  return L;
+}
+
+// ------------------------------------------------------------------ host validation
+nfhmm_status validate_host(const nfhmm_problem *p, std::string *msg) {
+  std::string why;
+  if (!dims_ok(p, &why)) { *msg = why; return NFHMM_E_INVALID; }
+  const int64_t S = p->S, N = p->N, K = p->K, M = S * N * K, F = p->F, T = p->T;
+  char buf[256];
+  for (int64_t i = 0; i < T * F; ++i) {
+    const float v = p->V[i];
+    if (!(v >= 0.0f) || !std::isfinite(v)) {
+      snprintf(buf, sizeof buf, "V[%lld][%lld] = %g is not finite and >= 0", (long long)(i / F), (long long)(i % F), v);
+      *msg = buf;
+      return NFHMM_E_INVALID;
+    }
+  }
+  std::vector<char> bin_has(F, 0);
+  for (int64_t k = 0; k < M; ++k) {
+    double s = 0.0;
+    for (int64_t l = 0; l < F; ++l) {
+      const float w = p->W[k * F + l];
+      if (!(w >= 0.0f) || !std::isfinite(w)) {
+        snprintf(buf, sizeof buf, "W[%lld][%lld] = %g is not finite and >= 0", (long long)k, (long long)l, w);
+        *msg = buf;
+        return NFHMM_E_INVALID;
+      }
+      s += w;
+      if (w > 0.0f) bin_has[l] = 1;
+    }
+    if (std::fabs(s - 1.0) > 1e-4) {
+      snprintf(buf, sizeof buf, "dictionary element %lld sums to %.7g, not 1", (long long)k, s);
+      *msg = buf;
+      return NFHMM_E_INVALID;
+    }
+  }
+  for (int64_t l = 0; l < F; ++l) {
+    if (bin_has[l]) continue;
+    for (int64_t t = 0; t < T; ++t)
+      if (p->V[t * F + l] > 0.0f) {
+        snprintf(buf, sizeof buf, "bin %lld has V > 0 but every dictionary element is 0 there", (long long)l);
+        *msg = buf;
+        return NFHMM_E_INVALID;
+      }
+  }
+  for (int64_t s = 0; s < S; ++s) {
+    double ps = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+      const float v = p->pi[s * N + i];
+      if (!(v >= 0.0f) || !std::isfinite(v)) { *msg = "pi has a negative or non-finite entry"; return NFHMM_E_INVALID; }
+      ps += v;
+      double rs = 0.0;
+      for (int64_t j = 0; j < N; ++j) {
+        const float a = p->A[(s * N + i) * N + j];
+        if (!(a >= 0.0f) || !std::isfinite(a)) { *msg = "A has a negative or non-finite entry"; return NFHMM_E_INVALID; }
+        rs += a;
+      }
+      if (std::fabs(rs - 1.0) > 1e-4) {
+        snprintf(buf, sizeof buf, "row %lld of A[%lld] sums to %.7g, not 1", (long long)i, (long long)s, rs);
+        *msg = buf;
+        return NFHMM_E_INVALID;
+      }
+    }
+    if (std::fabs(ps - 1.0) > 1e-4) {
+      snprintf(buf, sizeof buf, "pi[%lld] sums to %.7g, not 1", (long long)s, ps);
+      *msg = buf;
+      return NFHMM_E_INVALID;
+    }
+  }
+  if (p->alpha_init)
+    for (int64_t i = 0; i < T * M; ++i) {
+      const float a = p->alpha_init[i];
+      if (!(a > 0.0f) || !std::isfinite(a)) { *msg = "alpha_init has an entry that is not finite and > 0"; return NFHMM_E_INVALID; }
+    }
+  return NFHMM_OK;
+}
+
+// ------------------------------------------------------------------ jobs
+enum JobState { kQueued, kResident, kDone };
+
+struct Job {
+  uint64_t id = 0;
+  nfhmm_problem prob{};       // pointers: device (device path) or job-owned host copies / user host memory
+  Dims d{};
+  nfhmm_result res{};         // destination of the outputs (host or device)
+  bool host_in = false, host_out = false;
+  Layout L{};
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  JobDesc desc{};
+  nfhmm_status status = NFHMM_OK;
+  std::string error;
+  JobState state = kQueued;
+  bool cancel = false;
+  int start_round = 0;
+  int finish_round = -1;      // round after which the job's outputs were queued
+  double t_submit = 0.0, t_done = 0.0;
+  std::vector<float> hV, hW, hA, hpi, hinit;   // serving: owned host copies of the inputs
+};
+
+void fill_desc(Job &j, float gamma) {
+  JobDesc &D = j.desc;
+  const Dims &d = j.d;
+  const Layout &L = j.L;
+  char *a = j.arena;
+  auto F32 = [&](size_t off) { return off == ~size_t(0) ? nullptr : reinterpret_cast<float *>(a + off); };
+  auto U16 = [&](size_t off) { return off == ~size_t(0) ? nullptr : reinterpret_cast<uint16_t *>(a + off); };
+  D = JobDesc{};
+  D.S = d.S; D.N = d.N; D.K = d.K; D.M = d.M; D.Mp = d.Mp; D.F = d.F; D.Fp = d.Fp; D.T = d.T;
+  D.NK = d.N * d.K; D.iters = d.iters; D.start_round = j.start_round; D.bf16 = d.bf16 ? 1 : 0;
+  D.gamma = gamma; D.nlt = (d.Fp + 63) / 64;
+  const double C = std::lgamma((double)d.M + (double)gamma * d.S * d.K) - (double)d.S * d.K * std::lgamma(1.0 + gamma);
+  D.elbo_const = (double)d.T * C;
+  if (j.host_in) {
+    D.V_in = F32(L.V_in); D.W_in = F32(L.W_in); D.A_in = F32(L.A_in); D.pi_in = F32(L.pi_in);
+    D.alpha_init = j.prob.alpha_init ? F32(L.alpha_init) : nullptr;
+  } else {
+    D.V_in = j.prob.V; D.W_in = j.prob.W; D.A_in = j.prob.A; D.pi_in = j.prob.pi; D.alpha_init = j.prob.alpha_init;
+  }
+  D.V = F32(L.V); D.Wfm = F32(L.Wfm); D.Wmf = F32(L.Wmf);
+  D.Wfm_h = U16(L.Wfm_h); D.Wmf_h = U16(L.Wmf_h); D.wh = U16(L.wh); D.Rh = U16(L.Rh);
+  D.w = F32(L.w); D.R = F32(L.R);
+  D.alpha = F32(L.alpha); D.E = F32(L.E); D.c = F32(L.c);
+  D.phi = F32(L.phi); D.ev = F32(L.ev); D.sh = F32(L.sh); D.fwd = F32(L.fwd); D.bwd = F32(L.bwd);
+  D.nrm = F32(L.nrm); D.post = F32(L.post);
+  D.vll = reinterpret_cast<float2 *>(a + L.vll);
+  D.elbo = reinterpret_cast<float2 *>(a + L.elbo);
+  D.sep = F32(L.sep);
+  D.status = reinterpret_cast<int *>(a + L.status);
+  D.chainflag = reinterpret_cast<int *>(a + L.chainflag);
+  if (j.host_out) {
+    D.out_alpha = j.res.alpha ? F32(L.out_alpha) : nullptr;
+    D.out_post = j.res.post ? F32(L.out_post) : nullptr;
+    D.out_sep = j.res.sep ? F32(L.out_sep) : nullptr;
+    D.out_elbo = j.res.elbo ? reinterpret_cast<double *>(a + L.out_elbo) : nullptr;
+  } else {
+    D.out_alpha = j.res.alpha; D.out_post = j.res.post; D.out_sep = j.res.sep; D.out_elbo = j.res.elbo;
+  }
+}
+
+// ------------------------------------------------------------------ work-list tables
+// One table describes a set of jobs for every launch of a round: the job
+// descriptors and, per launch kind, the prefix sums of blocks per job.
+enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFB, kPost, kChain, kFrames, kRecon, kIters, kNumLists };
+
+struct Table {
+  std::vector<uint64_t> key;
+  WorkList lists[kNumLists];
+  int nmax = 1, mpmax = 32;
+  char *dev = nullptr, *host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ready = nullptr;
+};
+
+int blocks_of(ListKind k, const JobDesc &D, bool bf16) {
+  const int ct = (D.T + 63) / 64;
+  switch (k) {
+    case kSpecF: return bf16 ? 0 : D.nlt * ct;
+    case kSpecH: return bf16 ? D.nlt * ct : 0;
+    case kCntF: return bf16 ? 0 : ((D.Mp + 63) / 64) * ct;
+    case kCntH: return bf16 ? ((D.Mp + 63) / 64) * ct : 0;
+    case kFB: return 2 * D.S;
+    case kPost: return D.S * ((D.T + 3) / 4);
+    case kChain: return D.S;
+    case kFrames: return D.T;
+    case kRecon: return D.S * D.nlt * ct;
+    case kIters: return D.iters;
+    default: return 0;
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct nfhmm_ctx {
+  int device = 0;
+  size_t budget = 0;
+  int max_slots = 64;
+  hipStream_t stream = nullptr, fb_stream = nullptr, io_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<std::unique_ptr<Table>> tables;   // ring
+  size_t table_next = 0;
+  std::map<size_t, std::vector<char *>> arena_cache;   // device path: reusable arenas by size
+
+  // serving state
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::thread sched;
+  bool stop = false;
+  std::atomic<uint64_t> next_id{1};
+  std::deque<Job *> queue;
+  std::vector<Job *> resident;
+  std::map<uint64_t, std::unique_ptr<Job>> jobs;
+  size_t bytes_in_use = 0;
+  int round = 0;
+  std::string sched_error;
+
+  // measurement: (kind, start, end) event triples of timed launches
+  bool profiling = false;
+  struct Rec { int kind; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+uint64_t new_id(nfhmm_ctx *ctx) { return ctx->next_id.fetch_add(1); }
+
+hipError_t table_reserve(Table &t, size_t bytes) {
+  if (t.cap >= bytes) return hipSuccess;
+  if (t.dev) { (void)hipFree(t.dev); t.dev = nullptr; }
+  if (t.host) { (void)hipHostFree(t.host); t.host = nullptr; }
+  size_t cap = std::max<size_t>(bytes * 2, 1 << 16);
+  hipError_t e = hipMalloc(&t.dev, cap);
+  if (e != hipSuccess) return e;
+  e = hipHostMalloc(&t.host, cap, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  t.cap = cap;
+  return hipSuccess;
+}
+
+// Build (or reuse) the table for `jobs`, ordered on `st`.
+nfhmm_status get_table(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st, Table **out) {
+  std::vector<uint64_t> key;
+  for (Job *j : jobs) key.push_back(j->id);
+  for (auto &t : ctx->tables)
+    if (t && t->key == key && !key.empty()) { *out = t.get(); return NFHMM_OK; }
+  if (ctx->tables.size() < 16) ctx->tables.emplace_back(new Table());
+  Table &t = *ctx->tables[ctx->table_next % ctx->tables.size()];
+  ctx->table_next++;
+  if (t.ready) HIP_OK(hipEventSynchronize(t.ready));   // a previous use may still be copying
+  else HIP_OK(hipEventCreateWithFlags(&t.ready, hipEventDisableTiming));
+  const int n = (int)jobs.size();
+  const size_t desc_bytes = rup((int64_t)n * sizeof(JobDesc), 256);
+  const size_t list_bytes = rup((int64_t)(n + 1) * sizeof(int), 256);
+  const size_t total = desc_bytes + kNumLists * list_bytes;
+  HIP_OK(table_reserve(t, total));
+  JobDesc *hd = reinterpret_cast<JobDesc *>(t.host);
+  t.nmax = 1;
+  t.mpmax = 32;
+  for (int i = 0; i < n; ++i) {
+    hd[i] = jobs[i]->desc;
+    t.nmax = std::max(t.nmax, jobs[i]->d.N);
+    t.mpmax = std::max(t.mpmax, jobs[i]->d.Mp);
+  }
+  for (int k = 0; k < kNumLists; ++k) {
+    int *hs = reinterpret_cast<int *>(t.host + desc_bytes + k * list_bytes);
+    int acc = 0;
+    for (int i = 0; i < n; ++i) {
+      hs[i] = acc;
+      acc += blocks_of((ListKind)k, jobs[i]->desc, jobs[i]->d.bf16);
+    }
+    hs[n] = acc;
+    t.lists[k].jobs = reinterpret_cast<const JobDesc *>(t.dev);
+    t.lists[k].start = reinterpret_cast<const int *>(t.dev + desc_bytes + k * list_bytes);
+    t.lists[k].njobs = n;
+    t.lists[k].total = acc;
+  }
+  HIP_OK(hipMemcpyAsync(t.dev, t.host, total, hipMemcpyHostToDevice, st));
+  HIP_OK(hipEventRecord(t.ready, st));
+  t.key = key;
+  *out = &t;
+  return NFHMM_OK;
+}
+
+nfhmm_status arena_alloc(nfhmm_ctx *ctx, Job &j, bool cached) {
+  j.arena_bytes = j.L.total;
+  if (cached) {
+    auto it = ctx->arena_cache.find(j.arena_bytes);
+    if (it != ctx->arena_cache.end() && !it->second.empty()) {
+      j.arena = it->second.back();
+      it->second.pop_back();
+      return NFHMM_OK;
+    }
+  }
+  hipError_t e = hipMalloc(&j.arena, j.arena_bytes);
+  if (e != hipSuccess) {
+    j.arena = nullptr;
+    return fail(e == hipErrorOutOfMemory ? NFHMM_E_NOMEM : NFHMM_E_DEVICE, "hipMalloc(%zu): %s", j.arena_bytes,
+                hipGetErrorString(e));
+  }
+  return NFHMM_OK;
+}
+
+void arena_release(nfhmm_ctx *ctx, Job &j, bool cached) {
+  if (!j.arena) return;
+  if (cached) ctx->arena_cache[j.arena_bytes].push_back(j.arena);
+  else (void)hipFree(j.arena);
+  j.arena = nullptr;
+}
+
+// Copy a host-input job's arrays into its arena.
+nfhmm_status upload_inputs(Job &j, hipStream_t st) {
+  const Dims &d = j.d;
+  char *a = j.arena;
+  HIP_OK(hipMemcpyAsync(a + j.L.V_in, j.prob.V, (size_t)d.T * d.F * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(a + j.L.W_in, j.prob.W, (size_t)d.M * d.F * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(a + j.L.A_in, j.prob.A, (size_t)d.S * d.N * d.N * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(a + j.L.pi_in, j.prob.pi, (size_t)d.S * d.N * 4, hipMemcpyHostToDevice, st));
+  if (j.prob.alpha_init)
+    HIP_OK(hipMemcpyAsync(a + j.L.alpha_init, j.prob.alpha_init, (size_t)d.T * d.M * 4, hipMemcpyHostToDevice, st));
+  return NFHMM_OK;
+}
+
+nfhmm_status download_outputs(Job &j, hipStream_t st) {
+  const Dims &d = j.d;
+  char *a = j.arena;
+  if (j.res.alpha) HIP_OK(hipMemcpyAsync(j.res.alpha, a + j.L.out_alpha, (size_t)d.T * d.M * 4, hipMemcpyDeviceToHost, st));
+  if (j.res.post)
+    HIP_OK(hipMemcpyAsync(j.res.post, a + j.L.out_post, (size_t)d.S * d.T * d.N * 4, hipMemcpyDeviceToHost, st));
+  if (j.res.sep) HIP_OK(hipMemcpyAsync(j.res.sep, a + j.L.out_sep, (size_t)d.S * d.T * d.F * 4, hipMemcpyDeviceToHost, st));
+  if (j.res.elbo && d.iters > 0)
+    HIP_OK(hipMemcpyAsync(j.res.elbo, a + j.L.out_elbo, (size_t)d.iters * 8, hipMemcpyDeviceToHost, st));
+  return NFHMM_OK;
+}
+
+// ------------------------------------------------------------------ engine
+// Start jobs: pack inputs, then the default start (or the warm start).
+nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st) {
+  if (jobs.empty()) return NFHMM_OK;
+  std::vector<Job *> uni, warm;
+  for (Job *j : jobs) {
+    HIP_OK(hipMemsetAsync(j->desc.status, 0, 4, st));
+    HIP_OK(launch_pack(j->desc, st));
+    if (j->desc.alpha_init) warm.push_back(j);
+    else { uni.push_back(j); HIP_OK(launch_fill_w_ones(j->desc, st)); }
+  }
+  if (!uni.empty()) {
+    Table *t;
+    nfhmm_status s = get_table(ctx, uni, st, &t);
+    if (s != NFHMM_OK) return s;
+    HIP_OK(launch_spectrum(t->lists[kSpecF], false, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecH], true, st));
+    HIP_OK(launch_counts(t->lists[kCntF], false, st));
+    HIP_OK(launch_counts(t->lists[kCntH], true, st));
+    HIP_OK(launch_update(t->lists[kFrames], kUpdUniform, 0, t->mpmax, st));
+  }
+  if (!warm.empty()) {
+    Table *t;
+    nfhmm_status s = get_table(ctx, warm, st, &t);
+    if (s != NFHMM_OK) return s;
+    HIP_OK(launch_update(t->lists[kFrames], kUpdFromAlpha, 0, t->mpmax, st));
+  }
+  return NFHMM_OK;
+}
+
+hipEvent_t pooled_event(nfhmm_ctx *ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Brackets one launch with timing events when the context is profiling.
+struct Timed {
+  nfhmm_ctx *ctx;
+  int kind;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Timed(nfhmm_ctx *c, int k, hipStream_t s) : ctx(c), kind(k), st(s) {
+    if (ctx->profiling) {
+      a = pooled_event(ctx);
+      (void)hipEventRecord(a, st);
+    }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = pooled_event(ctx);
+    (void)hipEventRecord(b, st);
+    ctx->recs.push_back({kind, a, b});
+  }
+};
+
+// One iteration of every job in `jobs` (round index `round`).
+nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int round, hipStream_t st) {
+  if (jobs.empty()) return NFHMM_OK;
+  Table *t;
+  nfhmm_status s = get_table(ctx, jobs, st, &t);
+  if (s != NFHMM_OK) return s;
+  HIP_OK(hipEventRecord(ctx->ev_fork, st));
+  HIP_OK(hipStreamWaitEvent(ctx->fb_stream, ctx->ev_fork, 0));
+  {
+    Timed tm(ctx, NFHMM_K_CHAINS, ctx->fb_stream);
+    HIP_OK(launch_chain_fb(t->lists[kFB], t->nmax, ctx->fb_stream));
+  }
+  {
+    Timed tm(ctx, NFHMM_K_POSTERIOR, ctx->fb_stream);
+    HIP_OK(launch_posterior(t->lists[kPost], t->lists[kChain], t->nmax, ctx->fb_stream));
+  }
+  HIP_OK(hipEventRecord(ctx->ev_join, ctx->fb_stream));
+  {
+    Timed tm(ctx, NFHMM_K_SPECTRUM, st);
+    HIP_OK(launch_spectrum(t->lists[kSpecF], false, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecH], true, st));
+  }
+  {
+    Timed tm(ctx, NFHMM_K_COUNTS, st);
+    HIP_OK(launch_counts(t->lists[kCntF], false, st));
+    HIP_OK(launch_counts(t->lists[kCntH], true, st));
+  }
+  HIP_OK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+  {
+    Timed tm(ctx, NFHMM_K_UPDATE, st);
+    HIP_OK(launch_update(t->lists[kFrames], kUpdMessages, round, t->mpmax, st));
+  }
+  return NFHMM_OK;
+}
+
+nfhmm_status engine_finish(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st) {
+  if (jobs.empty()) return NFHMM_OK;
+  Table *t;
+  nfhmm_status s = get_table(ctx, jobs, st, &t);
+  if (s != NFHMM_OK) return s;
+  HIP_OK(launch_finish(t->lists[kFrames], t->lists[kRecon], t->lists[kIters], st));
+  return NFHMM_OK;
+}
+
+// Run a fixed set of jobs to completion (all start at round 0).
+nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t st) {
+  int max_it = 0;
+  for (Job *j : jobs) {
+    j->start_round = 0;
+    fill_desc(*j, j->prob.gamma);
+    max_it = std::max(max_it, j->d.iters);
+  }
+  nfhmm_status s;
+  for (Job *j : jobs)
+    if (j->host_in && (s = upload_inputs(*j, st)) != NFHMM_OK) return s;
+  if ((s = engine_begin(ctx, jobs, st)) != NFHMM_OK) return s;
+  std::vector<Job *> done0;
+  for (Job *j : jobs)
+    if (j->d.iters == 0) done0.push_back(j);
+  if ((s = engine_finish(ctx, done0, st)) != NFHMM_OK) return s;
+  for (int r = 0; r < max_it; ++r) {
+    std::vector<Job *> act, fin;
+    for (Job *j : jobs) {
+      if (r < j->d.iters) act.push_back(j);
+      if (r + 1 == j->d.iters) fin.push_back(j);
+    }
+    if ((s = engine_iterate(ctx, act, r, st)) != NFHMM_OK) return s;
+    if ((s = engine_finish(ctx, fin, st)) != NFHMM_OK) return s;
+  }
+  for (Job *j : jobs)
+    if (j->host_out && (s = download_outputs(*j, st)) != NFHMM_OK) return s;
+  HIP_OK(hipStreamSynchronize(st));
+  nfhmm_status first = NFHMM_OK;
+  for (Job *j : jobs) {
+    int flag = 0;
+    HIP_OK(hipMemcpy(&flag, j->desc.status, 4, hipMemcpyDeviceToHost));
+    if (flag & (kBadV | kBadW)) {
+      j->status = NFHMM_E_INVALID;
+      j->error = (flag & kBadV) ? "V has a negative or non-finite entry" : "a dictionary element is not normalised";
+    } else if (flag & kNonFinite) {
+      j->status = NFHMM_E_NONFINITE;
+      j->error = "the evidence lower bound became non-finite";
+    }
+    if (first == NFHMM_OK && j->status != NFHMM_OK) {
+      first = j->status;
+      g_err = j->error;
+    }
+  }
+  return first;
+}
+
+nfhmm_status make_job(const nfhmm_problem *p, nfhmm_precision prec, const nfhmm_result *r, bool host_in,
+                      bool host_out, Job &j) {
+  std::string why;
+  if (prec != NFHMM_FP32 && prec != NFHMM_BF16) return fail(NFHMM_E_INVALID, "unknown precision %d", (int)prec);
+  if (!dims_ok(p, &why)) return fail(NFHMM_E_INVALID, "%s", why.c_str());
+  if (!r) return fail(NFHMM_E_INVALID, "result is NULL");
+  j.prob = *p;
+  j.d = dims_of(p, prec);
+  j.res = *r;
+  j.host_in = host_in;
+  j.host_out = host_out;
+  j.L = plan(j.d, host_in, host_out, p->alpha_init != nullptr);
+  return NFHMM_OK;
+}
+
+// ------------------------------------------------------------------ serving loop
+void finish_job_locked(nfhmm_ctx *ctx, Job *j, nfhmm_status st, const std::string &err) {
+  j->status = st;
+  j->error = err;
+  j->state = kDone;
+  j->t_done = now_s();
+  ctx->bytes_in_use -= j->arena ? j->arena_bytes : 0;
+}
+
+void scheduler(nfhmm_ctx *ctx) {
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = ctx->stream;
+  struct Pending { Job *job; hipEvent_t ev; };
+  std::vector<Pending> pending;   // finished on the device, outputs in flight
+  for (;;) {
+    std::vector<Job *> admitted, act;
+    {
+      std::unique_lock<std::mutex> lk(ctx->mu);
+      ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || !ctx->resident.empty() || !pending.empty(); });
+      if (ctx->stop && ctx->queue.empty() && ctx->resident.empty() && pending.empty()) return;
+      // drop cancelled queued jobs
+      for (auto it = ctx->queue.begin(); it != ctx->queue.end();) {
+        if ((*it)->cancel) {
+          finish_job_locked(ctx, *it, NFHMM_E_CANCELLED, "cancelled");
+          it = ctx->queue.erase(it);
+        } else ++it;
+      }
+      // admission: first in, first out, within budget and slots
+      std::vector<size_t> fp;
+      for (Job *j : ctx->queue) fp.push_back(j->L.total);
+      std::vector<int> adm(fp.size(), 0);
+      nfhmm_admission_plan((int)fp.size(), fp.data(), ctx->bytes_in_use, ctx->budget, (int)ctx->resident.size(),
+                           ctx->max_slots, adm.data());
+      for (size_t i = 0; i < adm.size(); ++i)
+        if (adm[i] == 1) admitted.push_back(ctx->queue[i]);
+      for (Job *j : admitted) {
+        ctx->queue.erase(std::find(ctx->queue.begin(), ctx->queue.end(), j));
+        ctx->bytes_in_use += j->L.total;
+      }
+    }
+    // allocate and start the admitted jobs
+    std::vector<Job *> started;
+    for (Job *j : admitted) {
+      nfhmm_status s = arena_alloc(ctx, *j, false);
+      if (s == NFHMM_OK) {
+        j->start_round = ctx->round;
+        fill_desc(*j, j->prob.gamma);
+        s = upload_inputs(*j, st);
+      }
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      if (s != NFHMM_OK) {
+        finish_job_locked(ctx, j, s, g_err);
+        arena_release(ctx, *j, false);
+        ctx->cv_done.notify_all();
+      } else {
+        j->state = kResident;
+        started.push_back(j);
+      }
+    }
+    nfhmm_status s = engine_begin(ctx, started, st);
+    std::vector<Job *> zero_iter;
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      for (Job *j : started) {
+        if (j->d.iters == 0) zero_iter.push_back(j);
+        else ctx->resident.push_back(j);
+      }
+      // cancelled resident jobs leave now (their in-flight work is ordered before any reuse)
+      std::vector<Job *> keep;
+      for (Job *j : ctx->resident) {
+        if (j->cancel) {
+          pending.push_back({j, nullptr});
+          j->status = NFHMM_E_CANCELLED;
+        } else keep.push_back(j);
+      }
+      ctx->resident.swap(keep);
+      act = ctx->resident;
+    }
+    const int r = ctx->round;
+    std::vector<Job *> fin = zero_iter;
+    if (s == NFHMM_OK) s = engine_iterate(ctx, act, r, st);
+    for (Job *j : act)
+      if (r - j->start_round + 1 == j->d.iters) fin.push_back(j);
+    if (s == NFHMM_OK) s = engine_finish(ctx, fin, st);
+    for (Job *j : fin) {
+      if (s == NFHMM_OK) s = download_outputs(*j, st);
+      hipEvent_t ev = nullptr;
+      (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      (void)hipEventRecord(ev, st);
+      pending.push_back({j, ev});
+    }
+    {
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      std::vector<Job *> keep;
+      for (Job *j : ctx->resident)
+        if (std::find(fin.begin(), fin.end(), j) == fin.end()) keep.push_back(j);
+      ctx->resident.swap(keep);
+      ctx->round++;
+      if (s != NFHMM_OK) ctx->sched_error = g_err;
+    }
+    // Keep at most about two rounds in flight: wait for the previous round's
+    // completion markers, then retire jobs whose outputs have landed.
+    if (ctx->resident.empty() || pending.size() > 0) (void)hipStreamSynchronize(st);
+    std::vector<Pending> still;
+    for (auto &pd : pending) {
+      bool ready = pd.ev == nullptr || hipEventQuery(pd.ev) == hipSuccess;
+      if (!ready) { still.push_back(pd); continue; }
+      if (pd.ev) (void)hipEventDestroy(pd.ev);
+      Job *j = pd.job;
+      int flag = 0;
+      (void)hipMemcpy(&flag, j->desc.status, 4, hipMemcpyDeviceToHost);
+      nfhmm_status js = j->status == NFHMM_E_CANCELLED ? NFHMM_E_CANCELLED : NFHMM_OK;
+      std::string err;
+      if (js == NFHMM_OK && s != NFHMM_OK) { js = s; err = ctx->sched_error; }
+      else if (js == NFHMM_OK && (flag & (kBadV | kBadW))) { js = NFHMM_E_INVALID; err = "invalid input detected on the device"; }
+      else if (js == NFHMM_OK && (flag & kNonFinite)) { js = NFHMM_E_NONFINITE; err = "the evidence lower bound became non-finite"; }
+      arena_release(ctx, *j, false);
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      finish_job_locked(ctx, j, js, err);
+      j->arena = nullptr;
+      ctx->cv_done.notify_all();
+    }
+    pending.swap(still);
+  }
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+nfhmm_status nfhmm_create(nfhmm_ctx **out, int device, size_t hbm_budget_bytes, int max_slots) {
+  if (!out) return fail(NFHMM_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int n = 0;
+  HIP_OK(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(NFHMM_E_DEVICE, "device %d not present (%d devices)", device, n);
+  HIP_OK(hipSetDevice(device));
+  std::unique_ptr<nfhmm_ctx> c(new nfhmm_ctx());
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  c->max_slots = max_slots > 0 ? max_slots : 64;
+  HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamCreateWithFlags(&c->fb_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamCreateWithFlags(&c->io_stream, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  *out = c.release();
+  return NFHMM_OK;
+}
+
+void nfhmm_destroy(nfhmm_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (Job *j : ctx->queue) j->cancel = true;
+    ctx->stop = true;
+  }
+  ctx->cv.notify_all();
+  if (ctx->sched.joinable()) ctx->sched.join();
+  (void)hipDeviceSynchronize();
+  for (auto &kv : ctx->jobs)
+    if (kv.second->arena) (void)hipFree(kv.second->arena);
+  for (auto &kv : ctx->arena_cache)
+    for (char *a : kv.second) (void)hipFree(a);
+  for (auto &r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  for (auto &t : ctx->tables) {
+    if (!t) continue;
+    if (t->dev) (void)hipFree(t->dev);
+    if (t->host) (void)hipHostFree(t->host);
+    if (t->ready) (void)hipEventDestroy(t->ready);
+  }
+  (void)hipEventDestroy(ctx->ev_fork);
+  (void)hipEventDestroy(ctx->ev_join);
+  (void)hipStreamDestroy(ctx->stream);
+  (void)hipStreamDestroy(ctx->fb_stream);
+  (void)hipStreamDestroy(ctx->io_stream);
+  delete ctx;
+}
+
+const char *nfhmm_last_error(const nfhmm_ctx *) { return g_err.c_str(); }
+
+size_t nfhmm_footprint_bytes(const nfhmm_problem *p, nfhmm_precision prec) {
+  if (!dims_ok(p, nullptr)) return 0;
+  return plan(dims_of(p, prec), true, true, p->alpha_init != nullptr).total;
+}
+
+nfhmm_status nfhmm_validate(const nfhmm_problem *p, char *msg, size_t msglen) {
+  std::string m;
+  nfhmm_status s = validate_host(p, &m);
+  if (msg && msglen) snprintf(msg, msglen, "%s", m.c_str());
+  if (s != NFHMM_OK) g_err = m;
+  return s;
+}
+
+int nfhmm_admission_plan(int n_queued, const size_t *footprints, size_t bytes_in_use, size_t budget, int resident,
+                         int max_slots, int *admit) {
+  int n = 0;
+  bool blocked = false;
+  size_t used = bytes_in_use;
+  for (int i = 0; i < n_queued; ++i) {
+    admit[i] = 0;
+    if (budget && footprints[i] > budget) {
+      admit[i] = -1;
+      continue;
+    }
+    if (blocked) continue;
+    const bool slot = resident + n < max_slots;
+    const bool fits = !budget || used + footprints[i] <= budget;
+    if (slot && fits) {
+      admit[i] = 1;
+      used += footprints[i];
+      ++n;
+    } else {
+      blocked = true;
+    }
+  }
+  return n;
+}
+
+nfhmm_status nfhmm_fit_batch(nfhmm_ctx *ctx, int n, const nfhmm_problem *ps, nfhmm_precision prec,
+                             nfhmm_result *rs) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  if (n < 0 || (n > 0 && (!ps || !rs))) return fail(NFHMM_E_INVALID, "bad batch arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  std::vector<std::unique_ptr<Job>> owned;
+  std::vector<Job *> jobs;
+  for (int i = 0; i < n; ++i) {
+    std::string m;
+    if (validate_host(&ps[i], &m) != NFHMM_OK) return fail(NFHMM_E_INVALID, "job %d: %s", i, m.c_str());
+    owned.emplace_back(new Job());
+    Job &j = *owned.back();
+    j.id = new_id(ctx);
+    nfhmm_status s = make_job(&ps[i], prec, &rs[i], true, true, j);
+    if (s != NFHMM_OK) return s;
+    jobs.push_back(&j);
+  }
+  nfhmm_status s = NFHMM_OK;
+  for (Job *j : jobs)
+    if ((s = arena_alloc(ctx, *j, false)) != NFHMM_OK) break;
+  if (s == NFHMM_OK) s = run_blocking(ctx, jobs, ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (Job *j : jobs) arena_release(ctx, *j, false);
+  return s;
+}
+
+nfhmm_status nfhmm_fit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precision prec, nfhmm_result *r) {
+  return nfhmm_fit_batch(ctx, 1, p, prec, r);
+}
+
+nfhmm_status nfhmm_fit_batch_device(nfhmm_ctx *ctx, int n, const nfhmm_problem *ps, nfhmm_precision prec,
+                                    nfhmm_result *rs, void *hip_stream) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  if (n < 0 || (n > 0 && (!ps || !rs))) return fail(NFHMM_E_INVALID, "bad batch arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
+  std::vector<std::unique_ptr<Job>> owned;
+  std::vector<Job *> jobs;
+  for (int i = 0; i < n; ++i) {
+    owned.emplace_back(new Job());
+    Job &j = *owned.back();
+    j.id = new_id(ctx);
+    nfhmm_status s = make_job(&ps[i], prec, &rs[i], false, false, j);
+    if (s != NFHMM_OK) return fail(s, "job %d: %s", i, g_err.c_str());
+    jobs.push_back(&j);
+  }
+  nfhmm_status s = NFHMM_OK;
+  for (Job *j : jobs)
+    if ((s = arena_alloc(ctx, *j, true)) != NFHMM_OK) break;
+  if (s == NFHMM_OK) s = run_blocking(ctx, jobs, st);
+  (void)hipStreamSynchronize(st);
+  for (Job *j : jobs) arena_release(ctx, *j, true);
+  return s;
+}
+
+nfhmm_status nfhmm_fit_device(nfhmm_ctx *ctx, const nfhmm_problem *dev_p, nfhmm_precision prec,
+                              nfhmm_result *dev_r, void *hip_stream) {
+  return nfhmm_fit_batch_device(ctx, 1, dev_p, prec, dev_r, hip_stream);
+}
+
+nfhmm_status nfhmm_submit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precision prec, nfhmm_result *r,
+                          uint64_t *job_id) {
+  if (!ctx || !job_id) return fail(NFHMM_E_INVALID, "ctx or job_id is NULL");
+  std::string m;
+  if (validate_host(p, &m) != NFHMM_OK) return fail(NFHMM_E_INVALID, "%s", m.c_str());
+  std::unique_ptr<Job> j(new Job());
+  nfhmm_status s = make_job(p, prec, r, true, true, *j);
+  if (s != NFHMM_OK) return s;
+  if (ctx->budget && j->L.total > ctx->budget)
+    return fail(NFHMM_E_NOMEM, "job needs %zu device bytes, budget is %zu", j->L.total, ctx->budget);
+  const Dims &d = j->d;
+  j->hV.assign(p->V, p->V + (size_t)d.T * d.F);
+  j->hW.assign(p->W, p->W + (size_t)d.M * d.F);
+  j->hA.assign(p->A, p->A + (size_t)d.S * d.N * d.N);
+  j->hpi.assign(p->pi, p->pi + (size_t)d.S * d.N);
+  j->prob.V = j->hV.data();
+  j->prob.W = j->hW.data();
+  j->prob.A = j->hA.data();
+  j->prob.pi = j->hpi.data();
+  if (p->alpha_init) {
+    j->hinit.assign(p->alpha_init, p->alpha_init + (size_t)d.T * d.M);
+    j->prob.alpha_init = j->hinit.data();
+  }
+  j->t_submit = now_s();
+  j->id = new_id(ctx);
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  *job_id = j->id;
+  ctx->queue.push_back(j.get());
+  ctx->jobs[j->id] = std::move(j);
+  if (!ctx->sched.joinable()) ctx->sched = std::thread(scheduler, ctx);
+  ctx->cv.notify_all();
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_poll(nfhmm_ctx *ctx, uint64_t job_id, int *done) {
+  if (!ctx || !done) return fail(NFHMM_E_INVALID, "ctx or done is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->jobs.find(job_id);
+  if (it == ctx->jobs.end()) return fail(NFHMM_E_NOTFOUND, "unknown job %llu", (unsigned long long)job_id);
+  *done = it->second->state == kDone;
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_wait(nfhmm_ctx *ctx, uint64_t job_id, double *latency_s) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  std::unique_lock<std::mutex> lk(ctx->mu);
+  auto it = ctx->jobs.find(job_id);
+  if (it == ctx->jobs.end()) return fail(NFHMM_E_NOTFOUND, "unknown job %llu", (unsigned long long)job_id);
+  Job *j = it->second.get();
+  ctx->cv_done.wait(lk, [&] { return j->state == kDone; });
+  if (latency_s) *latency_s = j->t_done - j->t_submit;
+  const nfhmm_status st = j->status;
+  const std::string err = j->error;
+  ctx->jobs.erase(it);
+  if (st != NFHMM_OK) return fail(st, "%s", err.c_str());
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_cancel(nfhmm_ctx *ctx, uint64_t job_id) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->jobs.find(job_id);
+  if (it == ctx->jobs.end()) return fail(NFHMM_E_NOTFOUND, "unknown job %llu", (unsigned long long)job_id);
+  it->second->cancel = true;
+  ctx->cv.notify_all();
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_profile_enable(nfhmm_ctx *ctx, int enable) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  HIP_OK(hipSetDevice(ctx->device));
+  HIP_OK(hipDeviceSynchronize());
+  for (auto &r : ctx->recs) {
+    ctx->event_pool.push_back(r.a);
+    ctx->event_pool.push_back(r.b);
+  }
+  ctx->recs.clear();
+  ctx->profiling = enable != 0;
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_profile_read(nfhmm_ctx *ctx, int kind, int64_t *launches, double *total_ms) {
+  if (!ctx || kind < 0 || kind >= NFHMM_K_COUNT) return fail(NFHMM_E_INVALID, "bad arguments");
+  HIP_OK(hipSetDevice(ctx->device));
+  int64_t n = 0;
+  double ms = 0.0;
+  for (auto &r : ctx->recs) {
+    if (r.kind != kind) continue;
+    HIP_OK(hipEventSynchronize(r.b));
+    float e = 0.0f;
+    HIP_OK(hipEventElapsedTime(&e, r.a, r.b));
+    ms += e;
+    ++n;
+  }
+  if (launches) *launches = n;
+  if (total_ms) *total_ms = ms;
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float *logev, const float *A,
+                                   const float *pi, float *post, double *lnZ) {
+  if (!ctx || !logev || !A || !pi) return fail(NFHMM_E_INVALID, "NULL argument");
+  if (N < 1 || N > NFHMM_MAX_STATES || T < 1 || T > (1 << 24)) return fail(NFHMM_E_INVALID, "bad N or T");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const size_t T_ = (size_t)T;
+  // layout: logev, A, pi, phi, ev, sh, fwd, bwd, nrm, post
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off += (b + 255) / 256 * 256; return o; };
+  const size_t o_lev = take(T_ * N * 4), o_A = take((size_t)N * N * 4), o_pi = take((size_t)N * 4);
+  const size_t o_phi = take(T_ * 64 * 4), o_ev = take(T_ * 64 * 4), o_sh = take(T_ * 4);
+  const size_t o_f = take(T_ * 64 * 4), o_b = take(T_ * 64 * 4), o_n = take(T_ * 4), o_p = take(T_ * N * 4);
+  const size_t o_flag = take(4);
+  const size_t o_desc = take(sizeof(JobDesc)), o_start = take(6 * sizeof(int));
+  char *a = nullptr;
+  HIP_OK(hipMalloc(&a, off));
+  std::unique_ptr<char, void (*)(char *)> guard(a, [](char *p) { (void)hipFree(p); });
+  HIP_OK(hipMemcpyAsync(a + o_lev, logev, T_ * N * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(a + o_A, A, (size_t)N * N * 4, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(a + o_pi, pi, (size_t)N * 4, hipMemcpyHostToDevice, st));
+  JobDesc D{};
+  D.S = 1; D.N = N; D.K = 1; D.M = N; D.T = (int)T; D.iters = 0;
+  D.A_in = reinterpret_cast<const float *>(a + o_A);
+  D.pi_in = reinterpret_cast<const float *>(a + o_pi);
+  D.phi = reinterpret_cast<float *>(a + o_phi);
+  D.ev = reinterpret_cast<float *>(a + o_ev);
+  D.sh = reinterpret_cast<float *>(a + o_sh);
+  D.fwd = reinterpret_cast<float *>(a + o_f);
+  D.bwd = reinterpret_cast<float *>(a + o_b);
+  D.nrm = reinterpret_cast<float *>(a + o_n);
+  D.post = reinterpret_cast<float *>(a + o_p);
+  D.chainflag = reinterpret_cast<int *>(a + o_flag);
+  const int npost = (int)((T_ + 3) / 4);
+  const int start[6] = {0, 2, 0, npost, 0, 1};    // chain_fb, posterior, exact
+  HIP_OK(hipMemcpyAsync(a + o_desc, &D, sizeof D, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(a + o_start, start, sizeof start, hipMemcpyHostToDevice, st));
+  HIP_OK(launch_chain_prep(D, reinterpret_cast<const float *>(a + o_lev), st));
+  WorkList wl[3];
+  for (int i = 0; i < 3; ++i) {
+    wl[i].jobs = reinterpret_cast<const JobDesc *>(a + o_desc);
+    wl[i].start = reinterpret_cast<const int *>(a + o_start) + 2 * i;
+    wl[i].njobs = 1;
+    wl[i].total = start[2 * i + 1];
+  }
+  HIP_OK(launch_chain_fb(wl[0], N, st));
+  HIP_OK(launch_posterior(wl[1], wl[2], N, st));
+  std::vector<float> sh(T_), nrm(T_);
+  if (post) HIP_OK(hipMemcpyAsync(post, a + o_p, T_ * N * 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(sh.data(), a + o_sh, T_ * 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(nrm.data(), a + o_n, T_ * 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  if (lnZ) {
+    double z = 0.0;
+    for (size_t t = 0; t < T_; ++t) z += (double)sh[t] - std::log((double)nrm[t]);
+    *lnZ = z;
+  }
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_special_functions(nfhmm_ctx *ctx, int64_t n, const float *x, float *psi, float *lgam) {
+  if (!ctx || (n > 0 && !x) || n < 0) return fail(NFHMM_E_INVALID, "bad arguments");
+  if (n == 0) return NFHMM_OK;
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  char *a = nullptr;
+  const size_t b = (size_t)n * 4;
+  HIP_OK(hipMalloc(&a, 3 * b));
+  std::unique_ptr<char, void (*)(char *)> guard(a, [](char *p) { (void)hipFree(p); });
+  HIP_OK(hipMemcpyAsync(a, x, b, hipMemcpyHostToDevice, st));
+  HIP_OK(launch_special(n, reinterpret_cast<const float *>(a), psi ? reinterpret_cast<float *>(a + b) : nullptr,
+                        lgam ? reinterpret_cast<float *>(a + 2 * b) : nullptr, st));
+  if (psi) HIP_OK(hipMemcpyAsync(psi, a + b, b, hipMemcpyDeviceToHost, st));
+  if (lgam) HIP_OK(hipMemcpyAsync(lgam, a + 2 * b, b, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return NFHMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances (float32 path against float64 oracle, one step from the same float32
+alpha-hat): d-hat max abs 1e-5, alpha-hat max rel 1e-5, V* max abs / max(V, 1)
+1e-5, bound rel 1e-6.  Full runs are compared at the same bounds where no
+iterate drifts into another basin (checked on the inputs used here).
+"""
+import numpy as np
+import pytest
+
+from gen import make_problem, make_tiny
+from oracle import nfhmm_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL_D, TOL_A, TOL_SEP, TOL_L = 1e-5, 1e-5, 1e-5, 1e-6
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1206_6468_amd import nfhmm
+    return nfhmm
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def _errs(gpu, ref, V_TF):
+    ea = np.max(np.abs(gpu["alpha"] - ref["alpha"]) / ref["alpha"])
+    ed = np.max(np.abs(gpu["post"] - ref["post"]))
+    es = np.max(np.abs(gpu["sep"] - ref["sep"]) / np.maximum(V_TF[None], 1.0))
+    return ea, ed, es
+
+
+def _one_step(L, ctx, p, start_iters, precision="fp32"):
+    """Oracle to `start_iters`, cast alpha-hat to float32, one GPU and one oracle step."""
+    S, N, K = p["S"], p["N"], p["K"]
+    V, beta, A, pi = O.paper_arrays(p)
+    if start_iters > 0:
+        a0 = O.fit(V, beta, A, pi, S, N, K, iters=start_iters)["alpha"]
+    else:
+        a0 = O.init_alpha(V, beta, O.mask_B(S, N, K), 1.0, N)
+    a32 = a0.astype(np.float32)
+    q = dict(p, iters=1, alpha_init=a32)
+    gpu = L.fit(ctx, q, precision)
+    ref = O.fit(V, beta, A, pi, S, N, K, iters=1, alpha_init=a32.astype(np.float64))
+    ref["sep"] = np.transpose(ref["sep"], (0, 2, 1))
+    return gpu, ref
+
+
+# ------------------------------------------------------------------ building blocks
+def test_special_functions_accuracy(L, ctx):
+    """Device digamma / log-gamma against SciPy (float64): absolute error near
+    the zeros (psi ~ 0 at x = 1.4616, lnGamma ~ 0 at 1 and 2), a few float32
+    ulps elsewhere."""
+    from scipy.special import digamma, gammaln
+    x = np.concatenate([np.geomspace(1.0, 1e7, 20000), np.linspace(1, 3, 2001),
+                        np.geomspace(1e-3, 1.0, 500)]).astype(np.float32)
+    psi, lg = L.special_functions(ctx, x)
+    xd = x.astype(np.float64)
+    rp, rl = digamma(xd), gammaln(xd)
+    e_psi, e_lg = np.abs(psi - rp), np.abs(lg - rl)
+    big = xd >= 1.0
+    print(f"\npsi: max abs err {e_psi[big].max():.3e} (x={xd[big][np.argmax(e_psi[big])]:.4g}); "
+          f"lgamma: max abs err on [1,8) {e_lg[(xd >= 1) & (xd < 8)].max():.3e}, "
+          f"max rel err on [8,1e7] {np.max((e_lg / np.abs(rl))[xd >= 8]):.3e}")
+    assert np.all(e_psi[big] <= 1.5e-6 + 4e-7 * np.abs(rp[big]))
+    assert np.all(e_lg[big] <= 1e-5 + 5e-7 * np.abs(rl[big]))
+    small = ~big
+    assert np.all(e_psi[small] <= 4e-7 * np.abs(rp[small]) + 1e-5)
+
+
+def _chain(rng, N, sparse):
+    A = rng.random((N, N)) + 0.02
+    if sparse and N > 3:
+        A[rng.random((N, N)) < 0.8] = 0.0
+        A[np.arange(N), np.arange(N)] = 0.9
+    A /= A.sum(1, keepdims=True)
+    pi = np.full(N, 1.0 / N)
+    return A.astype(np.float32), pi.astype(np.float32)
+
+
+@pytest.mark.parametrize("N,T", [(1, 5), (5, 1), (5, 2), (40, 1000), (60, 400), (64, 300), (40, 4000),
+                                 (63, 50), (3, 77)])
+def test_chain_posterior_matches_oracle(L, ctx, N, T):
+    rng = np.random.default_rng(N * 7919 + T)
+    A, pi = _chain(rng, N, sparse=True)
+    logev = (rng.normal(scale=4.0, size=(T, N))).astype(np.float32)
+    post, lnZ = L.chain_posterior(ctx, logev, A, pi)
+    d, z = O.forward_backward(logev.astype(np.float64), A.astype(np.float64), pi.astype(np.float64))
+    assert np.max(np.abs(post - d)) < TOL_D
+    assert abs(lnZ - z) <= 1e-6 * max(1.0, abs(z)) + 1e-4
+
+
+@pytest.mark.parametrize("N,T,scale", [(40, 300, 150.0), (8, 200, 400.0), (64, 100, 300.0)])
+def test_chain_posterior_extreme_evidence(L, ctx, N, T, scale):
+    """Evidence gaps of hundreds of nats against a sparse chain: frames whose
+    scaled message underflows are redone in log space."""
+    rng = np.random.default_rng(N + T)
+    A, pi = _chain(rng, N, sparse=True)
+    logev = (rng.normal(scale=scale, size=(T, N))).astype(np.float32)
+    post, lnZ = L.chain_posterior(ctx, logev, A, pi)
+    d, z = O.forward_backward(logev.astype(np.float64), A.astype(np.float64), pi.astype(np.float64))
+    assert np.all(np.isfinite(post))
+    assert np.max(np.abs(post - d)) < 1e-4
+    assert abs(lnZ - z) <= 1e-5 * abs(z)
+
+
+# ------------------------------------------------------------------ one VI step
+ONE_STEP_CASES = [
+    ("cfg0", lambda: make_problem(0, 0), 3),
+    ("tiny-ragged", lambda: make_tiny(S=2, N=3, K=3, F=37, T=70, seed=1, quanta=300), 2),
+    ("S1", lambda: make_tiny(S=1, N=4, K=2, F=20, T=33, seed=2, quanta=200), 2),
+    ("S3-N1", lambda: make_tiny(S=3, N=1, K=5, F=65, T=129, seed=3, quanta=500), 2),
+    ("T1", lambda: make_tiny(S=2, N=4, K=2, F=16, T=1, seed=4, quanta=100), 1),
+    ("K1-M-odd", lambda: make_tiny(S=3, N=3, K=1, F=9, T=64, seed=5, quanta=80), 2),
+    ("N64", lambda: make_tiny(S=2, N=64, K=1, F=100, T=90, seed=6, quanta=2000, trans="sparse", diag=0.9), 2),
+]
+
+
+@pytest.mark.parametrize("name,mk,start", ONE_STEP_CASES, ids=[c[0] for c in ONE_STEP_CASES])
+def test_one_step_parity(L, ctx, name, mk, start):
+    p = mk()
+    gpu, ref = _one_step(L, ctx, p, start)
+    V_TF = p["V"].astype(np.float64)
+    ea, ed, es = _errs(gpu, ref, V_TF)
+    el = abs(gpu["elbo"][0] - ref["elbo"][0]) / abs(ref["elbo"][0])
+    print(f"\n{name}: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
+    assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_one_step_parity_full_size(L, ctx, cfg):
+    p = make_problem(cfg, 0)
+    gpu, ref = _one_step(L, ctx, p, 2)
+    ea, ed, es = _errs(gpu, ref, p["V"].astype(np.float64))
+    el = abs(gpu["elbo"][0] - ref["elbo"][0]) / abs(ref["elbo"][0])
+    print(f"\ncfg{cfg}: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
+    assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+
+
+def test_default_start_matches_oracle(L, ctx):
+    """iters = 0 returns the default start (Eq. 6 with z ~ beta, d = 1/N)."""
+    p = dict(make_problem(0, 3), iters=0)
+    g = L.fit(ctx, p)
+    V, beta, A, pi = O.paper_arrays(p)
+    a0 = O.init_alpha(V, beta, O.mask_B(p["S"], p["N"], p["K"]), 1.0, p["N"])
+    assert np.max(np.abs(g["alpha"] - a0) / a0) < TOL_A
+    assert np.allclose(g["post"], 1.0 / p["N"])
+
+
+# ------------------------------------------------------------------ full runs
+def test_full_run_cfg0(L, ctx):
+    p = make_problem(0, 0)
+    g = L.fit(ctx, p)
+    ref = O.fit_problem(p)
+    ea, ed, es = _errs(g, ref, p["V"].astype(np.float64))
+    el = np.max(np.abs(g["elbo"] - ref["elbo"]) / np.abs(ref["elbo"]))
+    print(f"\ncfg0 x{p['iters']}: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
+    assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+
+
+@pytest.mark.parametrize("gamma", [0.0, 2.5])
+def test_full_run_gamma(L, ctx, gamma):
+    p = dict(make_tiny(S=2, N=5, K=4, F=50, T=80, seed=9, quanta=1000), iters=6, gamma=gamma)
+    g = L.fit(ctx, p)
+    ref = O.fit_problem(p)
+    ea, ed, es = _errs(g, ref, p["V"].astype(np.float64))
+    el = np.max(np.abs(g["elbo"] - ref["elbo"]) / np.abs(ref["elbo"]))
+    assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+
+
+def test_invariants_on_gpu_outputs(L, ctx):
+    p = make_problem(1, 1)
+    p = dict(p, iters=8)
+    g = L.fit(ctx, p)
+    S, N, K = p["S"], p["N"], p["K"]
+    v = p["V"].astype(np.float64).sum(1)
+    assert np.max(np.abs(g["post"].sum(-1) - 1.0)) < 1e-5
+    assert g["alpha"].min() >= 1.0
+    np.testing.assert_allclose(g["alpha"].astype(np.float64).sum(1), v + S * K + S * N * K, rtol=2e-6)
+    np.testing.assert_allclose(g["sep"].astype(np.float64).sum(0), p["V"], rtol=1e-5, atol=1e-3)
+    assert g["sep"].min() >= 0.0
+    tr = g["elbo"]
+    assert np.all(np.diff(tr) >= -2e-7 * np.abs(tr[1:])), np.diff(tr)
+
+
+# ------------------------------------------------------------------ BF16 contraction
+def test_bf16_stated_bounds(L, ctx):
+    p = make_problem(1, 0)
+    gpu, ref = _one_step(L, ctx, p, 2, precision="bf16")
+    ea, ed, es = _errs(gpu, ref, p["V"].astype(np.float64))
+    el = abs(gpu["elbo"][0] - ref["elbo"][0]) / abs(ref["elbo"][0])
+    print(f"\nbf16 cfg1 one step: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
+    assert ea < 2e-2 and ed < 5e-2 and es < 2e-2 and el < 1e-3
+
+
+# ------------------------------------------------------------------ batching / paths
+def test_batch_is_bitwise_invariant(L, ctx):
+    probs = [make_problem(0, 5), dict(make_tiny(S=3, N=4, K=3, F=70, T=150, seed=11, quanta=900), iters=4),
+             dict(make_problem(0, 6), iters=7)]
+    alone = [L.fit(ctx, p) for p in probs]
+    mixed = L.fit_batch(ctx, probs)
+    for a, b in zip(alone, mixed):
+        for k in ("alpha", "post", "sep", "elbo"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_device_path_equals_host_path(L, ctx):
+    import torch
+    probs = [make_problem(0, 7), make_problem(0, 8)]
+    host = L.fit_batch(ctx, probs)
+    jobs = [L.DeviceJob(p) for p in probs]
+    L.fit_batch_device(ctx, jobs)
+    torch.cuda.synchronize()
+    for h, j in zip(host, jobs):
+        assert np.array_equal(h["alpha"], j.alpha.cpu().numpy())
+        assert np.array_equal(h["post"], j.post.cpu().numpy())
+        assert np.array_equal(h["sep"], j.sep.cpu().numpy())
+        assert np.array_equal(h["elbo"], j.elbo.cpu().numpy()[: len(h["elbo"])])
+
+
+def test_resume_is_bitwise(L, ctx):
+    p = make_problem(0, 9)
+    full = L.fit(ctx, dict(p, iters=10))
+    a = L.fit(ctx, dict(p, iters=4))
+    b = L.fit(ctx, dict(p, iters=6, alpha_init=a["alpha"]))
+    assert np.array_equal(full["alpha"], b["alpha"])
+    assert np.array_equal(full["post"], b["post"])
+    assert np.array_equal(full["elbo"], np.concatenate([a["elbo"], b["elbo"]]))
+
+
+def test_invalid_inputs_rejected(L, ctx):
+    p = make_problem(0, 0)
+    bad = dict(p, V=p["V"].copy())
+    bad["V"][3, 4] = np.nan
+    with pytest.raises(L.NfhmmError) as e:
+        L.fit(ctx, bad)
+    assert e.value.status == L.E_INVALID
+    import torch
+    j = L.DeviceJob(bad)
+    with pytest.raises(L.NfhmmError) as e:
+        L.fit_device(ctx, j)
+    assert e.value.status == L.E_INVALID
+    # a good job still runs afterwards on the same context
+    g = L.fit(ctx, dict(p, iters=2))
+    assert np.all(np.isfinite(g["elbo"]))
