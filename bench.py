@@ -63,8 +63,13 @@ def make_jobs(cfg, n, iters=None):
     return probs
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def time_batch(L, ctx, jobs, precision, steps, warmup, profile=False):
     import torch
+    log(f"{len(jobs)} jobs, {precision}: {warmup} warm-up + {steps} timed steps")
     for _ in range(warmup):
         L.fit_batch_device(ctx, jobs, precision)
     torch.cuda.synchronize()
@@ -130,6 +135,7 @@ def main():
 
     from paper_1206_6468_amd import nfhmm as L
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"generating {args.jobs} config-1 problems")
     probs = make_jobs(1, args.jobs)
     S, N, K, F, T, iters = (probs[0][k] for k in ("S", "N", "K", "F", "T", "iters"))
     M = S * N * K
@@ -188,6 +194,7 @@ def main():
     }
     out.update(extra)
     if not args.no_cpu:
+        log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -10,11 +10,11 @@
 //   w      [T][Mp]     exp(E) (float32, or bfloat16 in wh)
 //   R      [T][Fp]     V / Lambda (float32, or bfloat16 in Rh)
 //   c      [T][Mp]     expected counts sum_l V z (the first term of Eq. 6)
-//   phi    [S][T][64]  gamma * phi-hat (Eq. 8), one 64-lane row per frame
+//   phi    [S][T][64]  gamma * sum_j psi(alpha_(s,n,j)): Eq. 8 up to a per-frame constant
 //   ev     [S][T][64]  exp(gamma*phi - sh): linear-domain chain evidence
 //   sh     [S][T]      per-frame log shift of ev
 //   fwd    [S][T][64]  scaled forward messages;  bwd: scaled backward messages
-//   nrm    [S][T]      forward scale factors (ln Z = sum sh - sum ln nrm)
+//   lnz    [S]         ln Z of each chain minus sum_t sh_t (hi, lo)
 //   post   [S][T][N]   state marginals d-hat
 //   vll    [nlt][T]    per (64-row tile, frame) partials of sum_l V ln Lambda (hi, lo)
 //   elbo   [iters][T]  per-frame bound contributions (hi, lo)
@@ -49,8 +49,8 @@ struct JobDesc {
   float *V, *Wfm, *Wmf;
   uint16_t *Wfm_h, *Wmf_h, *wh, *Rh;
   float *alpha, *E, *w, *R, *c;
-  float *phi, *ev, *sh, *fwd, *bwd, *nrm, *post;
-  float2 *vll, *elbo;
+  float *phi, *ev, *sh, *fwd, *bwd, *post;
+  float2 *vll, *elbo, *lnz;
   float *sep;
   int *status;
   int *chainflag;    // [S] set when a chain needs the exact log-space pass

@@ -50,25 +50,54 @@ __device__ __forceinline__ uint16_t f2bf(float f) {       // round to nearest ev
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float wave_max(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmaxf(x, __shfl_xor(x, o));
-  return x;
+// Wavefront reductions with DPP lane moves: within quads, half-rows and rows of
+// 16, then across rows with the row broadcasts; the total lands in lane 63 and
+// is read back to every lane.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_mov(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 __device__ __forceinline__ float wave_sum(float x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-  return x;
+  x += dpp_mov<0xb1, 0xf>(0.0f, x);      // quad_perm [1,0,3,2]
+  x += dpp_mov<0x4e, 0xf>(0.0f, x);      // quad_perm [2,3,0,1]
+  x += dpp_mov<0x141, 0xf>(0.0f, x);     // row_half_mirror
+  x += dpp_mov<0x140, 0xf>(0.0f, x);     // row_mirror
+  x += dpp_mov<0x142, 0xa>(0.0f, x);     // row_bcast:15 into rows 1, 3
+  x += dpp_mov<0x143, 0xc>(0.0f, x);     // row_bcast:31 into rows 2, 3
+  return lane63(x);
+}
+__device__ __forceinline__ float wave_max(float x) {
+  const float ninf = -INFINITY;
+  x = fmaxf(x, dpp_mov<0xb1, 0xf>(ninf, x));
+  x = fmaxf(x, dpp_mov<0x4e, 0xf>(ninf, x));
+  x = fmaxf(x, dpp_mov<0x141, 0xf>(ninf, x));
+  x = fmaxf(x, dpp_mov<0x140, 0xf>(ninf, x));
+  x = fmaxf(x, dpp_mov<0x142, 0xa>(ninf, x));
+  x = fmaxf(x, dpp_mov<0x143, 0xc>(ninf, x));
+  return lane63(x);
+}
+__device__ __forceinline__ Comp comp_dpp_step(Comp c, Comp d) { return comp_merge(c, d); }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ Comp comp_mov(Comp c) {
+  Comp d;
+  d.hi = dpp_mov<CTRL, ROWS>(0.0f, c.hi);
+  d.lo = dpp_mov<CTRL, ROWS>(0.0f, c.lo);
+  return d;
 }
 __device__ __forceinline__ Comp wave_comp(Comp c) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    Comp d;
-    d.hi = __shfl_xor(c.hi, o);
-    d.lo = __shfl_xor(c.lo, o);
-    c = comp_merge(c, d);
-  }
-  return c;
+  c = comp_merge(c, comp_mov<0xb1, 0xf>(c));
+  c = comp_merge(c, comp_mov<0x4e, 0xf>(c));
+  c = comp_merge(c, comp_mov<0x141, 0xf>(c));
+  c = comp_merge(c, comp_mov<0x140, 0xf>(c));
+  c = comp_merge(c, comp_mov<0x142, 0xa>(c));
+  c = comp_merge(c, comp_mov<0x143, 0xc>(c));
+  Comp r;
+  r.hi = lane63(c.hi);
+  r.lo = lane63(c.lo);
+  return r;
 }
 
 // ------------------------------------------------------------------ packing
@@ -432,19 +461,215 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
 // One 64-lane wavefront per (job, source, direction).  Lane n < N owns state n.
 // Messages are linear vectors with per-frame log offsets (the scaled recursion of
 // Rabiner's tutorial, which the paper cites): the evidence row of frame t is
-// ev = exp(gamma*phi - sh_t) <= 2^64, and ln Z = sum_t sh_t - sum_t ln nrm_t.
+// ev = exp(gamma*phi - sh_t) <= 2^64, each message is rescaled by the power of
+// two 2^-k_t that brings its normaliser into [1/2, 1), and
+//   ln Z = sum_t sh_t + lnz,   lnz = ln sum_n u_{T-1}(n) + ln 2 * sum_t k_t,
+// so the bookkeeping is exact integer arithmetic.
 // Lane N (the first unused lane) holds one extra row of the transition
 // operator so that the normaliser comes out of the same FMA pass: all ones in
 // the forward direction (sum of the incoming message), the column sums of A in
-// the backward direction (sum of the outgoing message).  For N = 64 a shuffle
-// reduction is used instead.
+// the backward direction (sum of the outgoing message).  For N = 64 a reduction
+// is used instead.
 // The largest entry of every forward message and of every backward message times
 // the evidence is kept above 2^-20: a frame where all of them would fall below is
 // redone in log space with its own shift (recorded in sh for the forward
 // direction).  States that end up more than ~100 nats below a frame's best are
 // flushed to zero; k_posterior detects the frames where that could matter and
 // k_chain_exact then recomputes the chain entirely in log space.
+//
+// The sweep runs in blocks of kFbBlock frames whose evidence rows are loaded one
+// block ahead, before that block's message stores, so the waits for the loads
+// never include the stores (stores and loads share one counter on gfx9).
 constexpr float kRescue = 9.5367431640625e-07f;   // 2^-20
+constexpr int kFbBlock = 8;
+
+// Global-memory pointers (address space 1), so that loads and stores are
+// global_* instructions, which count only against vmcnt.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ gfloat *gptr(float *p) { return (gfloat *)p; }
+__device__ __forceinline__ const gfloat *gptr(const float *p) { return (const gfloat *)p; }
+
+// One recursion step: every lane publishes x through LDS, then forms
+// y = sum_m x_m coef[m]; tot is the normaliser (lane N's row, or a reduction).
+template <int NR>
+__device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&coef)[NR], float x, int lane, int N,
+                                             bool sumlane, bool live, bool fwd, float &tot) {
+  if (lane < NR) buf[p * NR + lane] = x;
+  // The block is one wavefront and LDS executes a wavefront's operations in issue
+  // order, so the reads below see every lane's write; only the compiler must not
+  // move them across (no instruction, no wait on the outstanding global stores).
+  __asm__ volatile("" ::: "memory");
+  float4 v[NR / 4];
+#pragma unroll
+  for (int q = 0; q < NR / 4; ++q) v[q] = *(const float4 *)(buf + p * NR + 4 * q);
+  p ^= 1;
+  float y0 = 0.0f, y1 = 0.0f;
+#pragma unroll
+  for (int q = 0; q < NR / 4; ++q) {
+    y0 = fmaf(v[q].x, coef[4 * q + 0], y0);
+    y1 = fmaf(v[q].y, coef[4 * q + 1], y1);
+    y0 = fmaf(v[q].z, coef[4 * q + 2], y0);
+    y1 = fmaf(v[q].w, coef[4 * q + 3], y1);
+  }
+  const float y = y0 + y1;
+  if (sumlane) tot = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), N));
+  else tot = wave_sum(live ? (fwd ? x : y) : 0.0f);
+  return y;
+}
+
+template <int NR>
+__device__ void chain_forward(const JobDesc &J, int s, const float (&coef)[NR], float *buf) {
+  const int lane = threadIdx.x, N = J.N, T = J.T;
+  const bool sumlane = N < 64, live = lane < N;
+  const gfloat *ev = gptr(J.ev + (size_t)s * T * 64 + lane);
+  const gfloat *phi = gptr(J.phi + (size_t)s * T * 64 + lane);
+  gfloat *fwd = gptr(J.fwd + (size_t)s * T * 64 + lane);
+  gfloat *sh = gptr(J.sh + (size_t)s * T);
+  const gfloat *pi = gptr(J.pi_in + (size_t)s * N);
+  int p = 0, ksum = 0;
+  float u, yr = 0.0f;
+  {
+    const float p0 = live ? pi[lane] : 0.0f;
+    u = p0 * ev[0];
+    if (__ballot(live && u > kRescue) == 0) {   // frame 0 in log space
+      const float x = live ? logf(p0) + phi[0] : -INFINITY;
+      const float mx = wave_max(x);
+      u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+      if (lane == 0) sh[0] = mx - kEvHeadroomLog;
+    }
+    fwd[0] = u;
+  }
+  // one step at frame t with evidence e; false (yr kept) if the frame needs the rescue
+#define NFHMM_FSTEP(t, e, ok)                                                               \
+  {                                                                                         \
+    float tot_;                                                                             \
+    const float y_ = chain_apply<NR>(buf, p, coef, u, lane, N, sumlane, live, true, tot_); \
+    const int k_ = __builtin_amdgcn_frexp_expf(tot_);                                      \
+    ksum += k_;                                                                             \
+    yr = ldexpf(y_, -k_);                                                                   \
+    const float un_ = yr * (e);                                                             \
+    ok = __ballot(live && un_ > kRescue) != 0;                                              \
+    if (ok) {                                                                               \
+      u = un_;                                                                              \
+      fwd[(size_t)(t) * 64] = u;                                                            \
+    }                                                                                       \
+  }
+  int t = 1;
+  while (t < T) {
+    bool ok = true;
+    if (T - t >= 2 * kFbBlock) {
+      float ea[kFbBlock], eb[kFbBlock];
+#pragma unroll
+      for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)(t + i) * 64];
+      while (ok && T - t >= 2 * kFbBlock) {
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) eb[i] = ev[(size_t)(t + kFbBlock + i) * 64];
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) {
+          NFHMM_FSTEP(t, ea[i], ok);
+          if (!ok) break;
+          ++t;
+        }
+        if (!ok) break;
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)min(t + kFbBlock + i, T - 1) * 64];
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) {
+          NFHMM_FSTEP(t, eb[i], ok);
+          if (!ok) break;
+          ++t;
+        }
+      }
+    } else {
+      const float e1 = ev[(size_t)t * 64];
+      NFHMM_FSTEP(t, e1, ok);
+      if (ok) ++t;
+    }
+    if (!ok) {   // frame t in log space with its own shift
+      const float x = live ? logf(yr) + phi[(size_t)t * 64] : -INFINITY;
+      const float mx = wave_max(x);
+      u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+      if (lane == 0) sh[t] = mx - kEvHeadroomLog;
+      fwd[(size_t)t * 64] = u;
+      ++t;
+    }
+  }
+#undef NFHMM_FSTEP
+  const float last = wave_sum(live ? u : 0.0f);
+  if (lane == 0) {
+    const double z = log((double)last) + 0.69314718055994530942 * (double)ksum;
+    const float hi = (float)z;
+    J.lnz[s] = make_float2(hi, (float)(z - (double)hi));
+  }
+}
+
+template <int NR>
+__device__ void chain_backward(const JobDesc &J, int s, const float (&coef)[NR], float *buf) {
+  const int lane = threadIdx.x, N = J.N, T = J.T;
+  const bool sumlane = N < 64, live = lane < N;
+  const gfloat *ev = gptr(J.ev + (size_t)s * T * 64 + lane);
+  const gfloat *phi = gptr(J.phi + (size_t)s * T * 64 + lane);
+  gfloat *bwd = gptr(J.bwd + (size_t)s * T * 64 + lane);
+  int p = 0;
+  // b_{T-1} = 1; q = e_{T-1} * b_{T-1}
+  const float bcur = live ? 1.0f : 0.0f;
+  bwd[(size_t)(T - 1) * 64] = bcur;
+  float q = bcur * ev[(size_t)(T - 1) * 64], bb = 0.0f;
+  if (__ballot(live && q > kRescue) == 0) {
+    const float x = live ? phi[(size_t)(T - 1) * 64] : -INFINITY;
+    const float mx = wave_max(x);
+    q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+  }
+#define NFHMM_BSTEP(t, e, ok)                                                                \
+  {                                                                                          \
+    float tot_;                                                                              \
+    const float y_ = chain_apply<NR>(buf, p, coef, q, lane, N, sumlane, live, false, tot_); \
+    bb = ldexpf(y_, -__builtin_amdgcn_frexp_expf(tot_));                                    \
+    bwd[(size_t)(t) * 64] = bb;                                                              \
+    const float qn_ = bb * (e);                                                              \
+    ok = __ballot(live && qn_ > kRescue) != 0;                                               \
+    if (ok) q = qn_;                                                                         \
+  }
+  int t = T - 2;
+  while (t >= 0) {
+    bool ok = true;
+    if (t + 1 >= 2 * kFbBlock) {
+      float ea[kFbBlock], eb[kFbBlock];
+#pragma unroll
+      for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)(t - i) * 64];
+      while (ok && t + 1 >= 2 * kFbBlock) {
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) eb[i] = ev[(size_t)(t - kFbBlock - i) * 64];
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) {
+          NFHMM_BSTEP(t, ea[i], ok);
+          if (!ok) break;
+          --t;
+        }
+        if (!ok) break;
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)max(t - kFbBlock - i, 0) * 64];
+#pragma unroll
+        for (int i = 0; i < kFbBlock; ++i) {
+          NFHMM_BSTEP(t, eb[i], ok);
+          if (!ok) break;
+          --t;
+        }
+      }
+    } else {
+      const float e1 = ev[(size_t)t * 64];
+      NFHMM_BSTEP(t, e1, ok);
+      if (ok) --t;
+    }
+    if (!ok) {
+      const float x = live ? logf(bb) + phi[(size_t)t * 64] : -INFINITY;
+      const float mx = wave_max(x);
+      q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+      --t;
+    }
+  }
+#undef NFHMM_BSTEP
+}
 
 template <int NR>
 __global__ __launch_bounds__(64) void k_chain_fb(WorkList wl) {
@@ -454,137 +679,28 @@ __global__ __launch_bounds__(64) void k_chain_fb(WorkList wl) {
   const int local = b - wl.start[jb];
   const int s = local >> 1, dir = local & 1;
   const int lane = threadIdx.x;
-  const int N = J.N, T = J.T;
-  const bool sumlane = N < 64;
-  const float *A = J.A_in + (size_t)s * N * N;
-  const float *ev = J.ev + (size_t)s * T * 64;
-  const float *phi = J.phi + (size_t)s * T * 64;
-  __shared__ __attribute__((aligned(16))) float buf[2][NR];
-  float coef[NR];
-#pragma unroll
-  for (int m = 0; m < NR; ++m) {
-    float v = 0.0f;
-    if (m < N) {
-      if (lane < N) {
-        v = dir == 0 ? A[(size_t)m * N + lane] : A[(size_t)lane * N + m];
-      } else if (lane == N) {
-        if (dir == 0) {
-          v = 1.0f;
-        } else {
-          for (int i = 0; i < N; ++i) v += A[(size_t)i * N + m];
-        }
-      }
-    }
-    coef[m] = v;
-  }
+  const int N = J.N;
   const bool live = lane < N;
-  if (dir == 0 && lane == 0) J.chainflag[s] = 0;
-
-  auto matvec = [&](int p) -> float {
-    float y0 = 0.0f, y1 = 0.0f;
-#pragma unroll
-    for (int q = 0; q < NR / 4; ++q) {
-      const float4 v = *(const float4 *)(&buf[p][4 * q]);
-      y0 = fmaf(v.x, coef[4 * q + 0], y0);
-      y1 = fmaf(v.y, coef[4 * q + 1], y1);
-      y0 = fmaf(v.z, coef[4 * q + 2], y0);
-      y1 = fmaf(v.w, coef[4 * q + 3], y1);
-    }
-    return y0 + y1;
-  };
-  // value of lane N's row (sum-lane mode) or the same sum by reduction of x
-  auto total_of = [&](float y, float x) -> float {
-    if (sumlane) return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), N));
-    return wave_sum(live ? x : 0.0f);
-  };
-
+  const float *A = J.A_in + (size_t)s * N * N;
+  __shared__ __attribute__((aligned(16))) float buf[2 * NR];
+  float coef[NR];
   if (dir == 0) {
-    float *fwd = J.fwd + (size_t)s * T * 64;
-    float *nrm = J.nrm + (size_t)s * T;
-    float *sh = J.sh + (size_t)s * T;
-    const float *pi = J.pi_in + (size_t)s * N;
-    float u;
-    {
-      const float p0 = live ? pi[lane] : 0.0f;
-      u = p0 * ev[lane];
-      if (__ballot(live && u > kRescue) == 0) {   // frame 0 in log space
-        const float x = live ? logf(p0) + phi[lane] : -INFINITY;
-        const float mx = wave_max(x);
-        u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
-        if (lane == 0) sh[0] = mx - kEvHeadroomLog;
-      }
-      fwd[lane] = u;
-    }
-    float ering[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) ering[i] = (1 + i < T) ? ev[(size_t)(1 + i) * 64 + lane] : 0.0f;
-    int p = 0;
-    for (int t0 = 1; t0 < T; t0 += 8) {
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int t = t0 + i;
-        if (t < T) {
-          const float e = ering[i];
-          ering[i] = (t + 8 < T) ? ev[(size_t)(t + 8) * 64 + lane] : 0.0f;
-          if (lane < NR) buf[p][lane] = u;
-          __syncthreads();
-          const float y = matvec(p);
-          const float tot = total_of(y, u);
-          const float r = 1.0f / tot;
-          if (lane == 0) nrm[t - 1] = r;
-          const float yr = y * r;
-          u = yr * e;
-          if (__ballot(live && u > kRescue) == 0) {
-            const float x = live ? logf(yr) + phi[(size_t)t * 64 + lane] : -INFINITY;
-            const float mx = wave_max(x);
-            u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
-            if (lane == 0) sh[t] = mx - kEvHeadroomLog;
-          }
-          fwd[(size_t)t * 64 + lane] = u;
-          p ^= 1;
-        }
-      }
-    }
-    const float last = wave_sum(live ? u : 0.0f);
-    if (lane == 0) nrm[T - 1] = 1.0f / last;
+    for (int m = 0; m < NR; ++m) coef[m] = (m < N && live) ? A[(size_t)m * N + lane] : ((m < N && lane == N) ? 1.0f : 0.0f);
+    if (lane == 0) J.chainflag[s] = 0;
+    chain_forward<NR>(J, s, coef, buf);
   } else {
-    float *bwd = J.bwd + (size_t)s * T * 64;
-    // b_{T-1} = 1; q = e_{T-1} * b_{T-1}
-    const float bcur = live ? 1.0f : 0.0f;
-    bwd[(size_t)(T - 1) * 64 + lane] = bcur;
-    float q = bcur * ev[(size_t)(T - 1) * 64 + lane];
-    if (__ballot(live && q > kRescue) == 0) {
-      const float x = live ? phi[(size_t)(T - 1) * 64 + lane] : -INFINITY;
-      const float mx = wave_max(x);
-      q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
-    }
-    float ering[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) ering[i] = (T - 2 - i >= 0) ? ev[(size_t)(T - 2 - i) * 64 + lane] : 0.0f;
-    int p = 0;
-    for (int t0 = T - 2; t0 >= 0; t0 -= 8) {
+    for (int m = 0; m < NR; ++m) coef[m] = (m < N && live) ? A[(size_t)lane * N + m] : 0.0f;
+    if (lane == N) {   // column sums of A
+      for (int i = 0; i < N; ++i) {
+        const float *row = A + (size_t)i * N;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int t = t0 - i;
-        if (t >= 0) {
-          const float e = ering[i];
-          ering[i] = (t - 8 >= 0) ? ev[(size_t)(t - 8) * 64 + lane] : 0.0f;
-          if (lane < NR) buf[p][lane] = q;
-          __syncthreads();
-          const float y = matvec(p);
-          const float tot = total_of(y, y);   // sum of the outgoing message
-          const float bb = y * (1.0f / tot);
-          bwd[(size_t)t * 64 + lane] = bb;
-          q = bb * e;
-          if (__ballot(live && q > kRescue) == 0) {
-            const float x = live ? logf(bb) + phi[(size_t)t * 64 + lane] : -INFINITY;
-            const float mx = wave_max(x);
-            q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
-          }
-          p ^= 1;
-        }
+        for (int m = 0; m < NR; ++m)
+          if (m < N) coef[m] += row[m];
       }
     }
+    chain_backward<NR>(J, s, coef, buf);
   }
 }
 
@@ -638,7 +754,6 @@ __global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
   const float *phi = J.phi + (size_t)s * T * 64;
   float *la = J.fwd + (size_t)s * T * 64;     // log forward messages (overwrites the scaled ones)
   float *sh = J.sh + (size_t)s * T;
-  float *nrm = J.nrm + (size_t)s * T;
   __shared__ float buf[NR];
   float lac[NR];
   // forward: column n of ln A
@@ -654,7 +769,9 @@ __global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
   float c = lse_lanes(cur);
   cur = live ? cur - c : -INFINITY;
   la[lane] = cur;
-  if (lane == 0) { sh[0] = c; nrm[0] = 1.0f; }
+  Comp lz = comp_zero();              // ln Z = sum_t c_t; the shifts sh are cleared
+  comp_add(lz, c);
+  if (lane == 0) sh[0] = 0.0f;
   for (int t = 1; t < T; ++t) {
     if (lane < NR) buf[lane] = cur;
     __syncthreads();
@@ -671,8 +788,10 @@ __global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
     c = lse_lanes(l);
     cur = live ? l - c : -INFINITY;
     la[(size_t)t * 64 + lane] = cur;
-    if (lane == 0) { sh[t] = c; nrm[t] = 1.0f; }
+    comp_add(lz, c);
+    if (lane == 0) sh[t] = 0.0f;
   }
+  if (lane == 0) J.lnz[s] = make_float2(lz.hi, lz.lo);
   // backward with row m of ln A in lane m; d-hat on the way
 #pragma unroll
   for (int n = 0; n < NR; ++n) lac[n] = (live && n < N) ? logf(A[(size_t)lane * N + n]) : -INFINITY;
@@ -737,7 +856,11 @@ __global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round
       c = wave_comp(c);
       if (lane == 0) {
         comp_add(c, J.sh[(size_t)s * T + t]);
-        comp_add(c, -logf(J.nrm[(size_t)s * T + t]));
+        if (t == 0) {
+          const float2 z = J.lnz[s];
+          comp_add(c, z.x);
+          comp_add(c, z.y);
+        }
         chain = comp_merge(chain, c);
       }
     }
@@ -781,22 +904,29 @@ __global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round
   }
   __syncthreads();
   const float a0 = bcast[0];
-  const float psi0 = digammaf(a0);
+  float xs0;
+  const float rest0 = digamma_parts(a0, xs0);
 
-  // ---- E, w
+  // ---- E = psi(alpha) - psi(alpha_0) as ln(xs / xs0) + (rest - rest0); w = exp(E);
+  //      sE keeps psi(alpha_k) itself for Eq. 8
   for (int k = tid; k < Mp; k += 256) {
-    float e = 0.0f, w = 0.0f;
+    float e = 0.0f, w = 0.0f, ps = 0.0f;
     if (k < M) {
-      e = digammaf(sE[k]) - psi0;
+      float xs;
+      const float rest = digamma_parts(sE[k], xs);
+      ps = logf(xs) + rest;
+      e = logf(xs / xs0) + (rest - rest0);
       w = expf(e);
     }
-    sE[k] = e;
+    sE[k] = ps;
     J.E[row + k] = e;
     if (J.bf16) J.wh[row + k] = f2bf(w); else J.w[row + k] = w;
   }
   __syncthreads();
 
-  // ---- Eq. 8: gamma * phi-hat, its per-frame shift and linear evidence
+  // ---- Eq. 8 up to a per-frame constant: gamma * sum_j psi(alpha_(s,n,j)).  The
+  //      term -gamma K psi(alpha_0) is the same for every state of the frame and
+  //      changes neither the chain posterior nor the bound, so it is left out.
   for (int s = wave; s < S; s += 4) {
     const bool live = lane < N;
     float x = -INFINITY;

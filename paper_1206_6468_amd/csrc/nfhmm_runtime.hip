@@ -93,7 +93,7 @@ Dims dims_of(const nfhmm_problem *p, nfhmm_precision prec) {
 struct Layout {
   size_t V_in, W_in, A_in, pi_in, alpha_init;                // host-input copies
   size_t V, Wfm, Wmf, Wfm_h, Wmf_h, wh, Rh, w, R;
-  size_t alpha, E, c, phi, ev, sh, fwd, bwd, nrm, post, vll, elbo, sep, status, chainflag;
+  size_t alpha, E, c, phi, ev, sh, fwd, bwd, lnz, post, vll, elbo, sep, status, chainflag;
   size_t out_alpha, out_post, out_sep, out_elbo;              // host-output staging
   size_t total;
 };
@@ -127,7 +127,7 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   L.sh = take(S * T * 4);
   L.fwd = take(S * T * 64 * 4);
   L.bwd = take(S * T * 64 * 4);
-  L.nrm = take(S * T * 4);
+  L.lnz = take(S * 8);
   L.post = take(S * T * N * 4);
   L.vll = take(nlt * T * 8);
   L.elbo = take(it * T * 8);
@@ -263,7 +263,7 @@ void fill_desc(Job &j, float gamma) {
   D.w = F32(L.w); D.R = F32(L.R);
   D.alpha = F32(L.alpha); D.E = F32(L.E); D.c = F32(L.c);
   D.phi = F32(L.phi); D.ev = F32(L.ev); D.sh = F32(L.sh); D.fwd = F32(L.fwd); D.bwd = F32(L.bwd);
-  D.nrm = F32(L.nrm); D.post = F32(L.post);
+  D.lnz = reinterpret_cast<float2 *>(a + L.lnz); D.post = F32(L.post);
   D.vll = reinterpret_cast<float2 *>(a + L.vll);
   D.elbo = reinterpret_cast<float2 *>(a + L.elbo);
   D.sep = F32(L.sep);
@@ -1036,7 +1036,7 @@ nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float
   D.sh = reinterpret_cast<float *>(a + o_sh);
   D.fwd = reinterpret_cast<float *>(a + o_f);
   D.bwd = reinterpret_cast<float *>(a + o_b);
-  D.nrm = reinterpret_cast<float *>(a + o_n);
+  D.lnz = reinterpret_cast<float2 *>(a + o_n);
   D.post = reinterpret_cast<float *>(a + o_p);
   D.chainflag = reinterpret_cast<int *>(a + o_flag);
   const int npost = (int)((T_ + 3) / 4);
@@ -1053,14 +1053,16 @@ nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float
   }
   HIP_OK(launch_chain_fb(wl[0], N, st));
   HIP_OK(launch_posterior(wl[1], wl[2], N, st));
-  std::vector<float> sh(T_), nrm(T_);
+  std::vector<float> sh(T_);
+  float lnz2[2] = {0.0f, 0.0f};
   if (post) HIP_OK(hipMemcpyAsync(post, a + o_p, T_ * N * 4, hipMemcpyDeviceToHost, st));
   HIP_OK(hipMemcpyAsync(sh.data(), a + o_sh, T_ * 4, hipMemcpyDeviceToHost, st));
-  HIP_OK(hipMemcpyAsync(nrm.data(), a + o_n, T_ * 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(lnz2, a + o_n, 8, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (lnZ) {
     double z = 0.0;
-    for (size_t t = 0; t < T_; ++t) z += (double)sh[t] - std::log((double)nrm[t]);
+    for (size_t t = 0; t < T_; ++t) z += (double)sh[t];
+    z += (double)lnz2[0] + (double)lnz2[1];
     *lnZ = z;
   }
   return NFHMM_OK;

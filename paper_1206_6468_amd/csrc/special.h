@@ -24,6 +24,29 @@
 
 namespace nfhmm {
 
+// psi(x) = ln(xs) + rest with xs = x shifted to >= 6: returns rest, writes xs.
+// Differences psi(a) - psi(b) are then formed as ln(xs_a / xs_b) + (rest_a - rest_b),
+// which avoids cancelling two large logarithms.
+NFHMM_HD float digamma_parts(float x, float &xs) {
+  float shift = 0.0f;
+  if (x < 6.0f) {
+    float p = 1.0f, dp = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const float xi = x + (float)i;
+      dp = dp * xi + p;
+      p = p * xi;
+    }
+    shift = dp / p;
+    x += 6.0f;
+  }
+  const float r = 1.0f / x;
+  const float r2 = r * r;
+  const float series = r2 * (1.0f / 12.0f - r2 * (1.0f / 120.0f - r2 * (1.0f / 252.0f - r2 * (1.0f / 240.0f))));
+  xs = x;
+  return -0.5f * r - series - shift;
+}
+
 // psi(x) for x > 0
 NFHMM_HD float digammaf(float x) {
   float shift = 0.0f;

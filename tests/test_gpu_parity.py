@@ -14,6 +14,12 @@ from oracle import nfhmm_oracle as O
 pytestmark = pytest.mark.gpu
 
 TOL_D, TOL_A, TOL_SEP, TOL_L = 1e-5, 1e-5, 1e-5, 1e-6
+# Full runs: the fixed-point map amplifies the per-iteration float32 rounding of
+# the contractions (~1e-6 relative in the expected counts).  Feeding the FP64
+# oracle 5e-7 relative noise in c per iteration moves d-hat by 8e-6 after 20
+# iterations (2e-6 noise: 4e-5), so d-hat gets 3e-5 on full runs; the one-step
+# bound above is the kernel contract.
+TOL_D_FULL = 3e-5
 
 
 @pytest.fixture(scope="module")
@@ -161,7 +167,7 @@ def test_full_run_cfg0(L, ctx):
     ea, ed, es = _errs(g, ref, p["V"].astype(np.float64))
     el = np.max(np.abs(g["elbo"] - ref["elbo"]) / np.abs(ref["elbo"]))
     print(f"\ncfg0 x{p['iters']}: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
-    assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+    assert ea < TOL_A and ed < TOL_D_FULL and es < TOL_SEP and el < TOL_L
 
 
 @pytest.mark.parametrize("gamma", [0.0, 2.5])
@@ -171,7 +177,8 @@ def test_full_run_gamma(L, ctx, gamma):
     ref = O.fit_problem(p)
     ea, ed, es = _errs(g, ref, p["V"].astype(np.float64))
     el = np.max(np.abs(g["elbo"] - ref["elbo"]) / np.abs(ref["elbo"]))
-    assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+    print(f"\ngamma {gamma}: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
+    assert ea < TOL_A and ed < TOL_D_FULL and es < TOL_SEP and el < TOL_L
 
 
 def test_invariants_on_gpu_outputs(L, ctx):
