@@ -82,7 +82,7 @@ def time_batch(L, ctx, jobs, precision, steps, warmup, profile=False):
     dt = (time.perf_counter() - t0) / steps
     prof = None
     if profile:
-        prof = {k: L.profile_read(ctx, k) for k in ("spectrum", "counts", "chains", "update")}
+        prof = {k: L.profile_read(ctx, k) for k in ("spectrum", "counts", "chains", "posterior", "update")}
         L.profile_enable(ctx, False)
     return dt, prof
 
@@ -147,31 +147,33 @@ def main():
     J = len(jobs)
     value = J * T * iters / dt
 
-    # roofline of the dominant kernel (largest summed device time)
-    flops_per_job_launch = {"spectrum": 2.0 * F * M * T, "counts": 2.0 * F * M * T}
+    # roofline of the dominant contraction kernel.  Each launch covers a group of
+    # the jobs; achieved = algorithmic flops of all timed launches / their summed
+    # device time (= flops per launch / average launch duration).
+    flops_per_job_iter = {"spectrum": 2.0 * F * M * T, "counts": 2.0 * F * M * T}
     dom = max(prof, key=lambda k: prof[k][1])
     rows = {}
     for k, (n, ms) in prof.items():
-        avg = ms / max(n, 1) * 1e-3
-        rows[k] = {"launches": n, "avg_ms": avg * 1e3}
-        if k in flops_per_job_launch:
-            rows[k]["achieved_tflops"] = flops_per_job_launch[k] * J / avg / 1e12
+        rows[k] = {"launches": n, "avg_ms": ms / max(n, 1), "total_ms": ms}
+        if k in flops_per_job_iter:
+            rows[k]["achieved_tflops"] = flops_per_job_iter[k] * J * iters * args.steps / (ms * 1e-3) / 1e12
     gemm = max(("spectrum", "counts"), key=lambda k: prof[k][1])
-    avg_g = prof[gemm][1] / max(prof[gemm][0], 1) * 1e-3
-    ach = flops_per_job_launch[gemm] * J / avg_g
+    n_g, ms_g = prof[gemm]
+    flops_launch = flops_per_job_iter[gemm] * J * iters * args.steps / max(n_g, 1)
+    ach = flops_launch / (ms_g / max(n_g, 1) * 1e-3)
     workload = f"config1-x{J}"
     roofline = {"bound": "mfma", "kernel": f"k_{gemm}", "achieved": ach / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": _traffic_for(f"k_{gemm}", workload),
                 "dominant_by_time": f"k_{dom}", "kernels": rows,
-                "algorithmic_flops_per_launch": flops_per_job_launch[gemm] * J}
+                "algorithmic_flops_per_launch": flops_launch}
 
     extra = {}
     if not args.no_extra:
         dtb, profb = time_batch(L, ctx, jobs, "bf16", args.steps, 1, profile=True)
-        avgb = profb["counts"][1] / max(profb["counts"][0], 1) * 1e-3
+        tb = flops_per_job_iter["counts"] * J * iters * args.steps / (profb["counts"][1] * 1e-3)
         extra["bf16"] = {"value": J * T * iters / dtb, "ms_per_step": dtb * 1e3,
-                         "k_counts_tflops": flops_per_job_launch["counts"] * J / avgb / 1e12,
-                         "k_counts_frac_of_bf16_peak": flops_per_job_launch["counts"] * J / avgb / PEAK_BF16_MFMA}
+                         "k_counts_tflops": tb / 1e12, "k_counts_frac_of_bf16_peak": tb / PEAK_BF16_MFMA,
+                         "kernels_ms": {k: v[1] for k, v in profb.items()}}
         dt1, _ = time_batch(L, ctx, jobs[:1], "fp32", max(2, args.steps), 1)
         extra["single_job_fp32"] = {"value": T * iters / dt1, "ms_per_fit": dt1 * 1e3}
 

@@ -5,9 +5,9 @@
 //                      Mp = S*N*K rounded up to 32)
 //   Wfm    [Fp][Mp]    beta_l(k) with k contiguous: the operand of Lambda = beta w
 //   Wmf    [Mp][Fp]    beta_l(k) with l contiguous: the operand of beta^T R
-//   alpha  [T][Mp]     Dirichlet parameters alpha-hat (Eq. 6); the carried state
-//   E      [T][Mp]     expected log weights psi(alpha_k) - psi(alpha_0)
-//   w      [T][Mp]     exp(E) (float32, or bfloat16 in wh)
+//   alpha  [T][Mp]     Dirichlet parameters alpha-hat (Eq. 6), stored when an output
+//   w      [T][Mp]     exp(psi(alpha_k) - psi(alpha_0)): the carried state
+//                      (float32, or bfloat16 in wh)
 //   R      [T][Fp]     V / Lambda (float32, or bfloat16 in Rh)
 //   c      [T][Mp]     expected counts sum_l V z (the first term of Eq. 6)
 //   phi    [S][T][64]  gamma * sum_j psi(alpha_(s,n,j)): Eq. 8 up to a per-frame constant
@@ -16,7 +16,13 @@
 //   fwd    [S][T][64]  scaled forward messages;  bwd: scaled backward messages
 //   lnz    [S]         ln Z of each chain minus sum_t sh_t (hi, lo)
 //   post   [S][T][N]   state marginals d-hat
-//   vll    [nlt][T]    per (64-row tile, frame) partials of sum_l V ln Lambda (hi, lo)
+//   vll    [nvl][T]    per (128-row tile, frame) partials of sum_l V ln Lambda (hi, lo);
+//                      the last slot holds the tail bins when Ft > 0
+// Bins: F = 2^k + 1 (a 2^(k+1)-point STFT) would waste most of a 64-row tile, so
+// when F mod 64 is 1..4 the contractions run over Fm = F - (F mod 64) bins and
+// the Ft tail bins are handled by k_update (their Lambda row: a dot product with
+// the w it has just formed) and by the epilogue of k_counts (a rank-Ft update).
+//   clw    [nkt][T]    per (64-row tile, frame) partials of -sum_k c ln w (hi, lo)
 //   elbo   [iters][T]  per-frame bound contributions (hi, lo)
 //   sep    [S][T][Fp]  reconstructions, then masked separations
 //   chainflag [S]      1 if the chain's scaled messages lost posterior mass
@@ -25,8 +31,6 @@
 
 namespace nfhmm {
 
-constexpr int kTileM = 64;     // GEMM block tile rows
-constexpr int kTileN = 64;     // GEMM block tile columns (frames)
 constexpr int kLanes = 64;     // states per chain row (wavefront width)
 constexpr int kMaxSources = 8;
 constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
@@ -40,17 +44,20 @@ struct JobDesc {
   int start_round;   // round in which this job runs its iteration 0
   int bf16;          // contraction operands in bfloat16
   float gamma;
-  int nlt;           // ceil(Fp / 64)
-  int pad_;
+  int nlt;           // ceil(Fp / 64): row tiles of the reconstruction
+  int Fm;            // bins of the spectrum contraction (rows) and of the counts (k)
+  int Ft;            // tail bins [Fm, F) handled outside the MFMA tiles (0..4)
+  int nst;           // ceil(Fm / 128): row tiles of the spectrum contraction
+  int nvl;           // slots of vll: nst, plus one for the tail
   double elbo_const; // T * (lnG(M + gamma S K) - S K lnG(1 + gamma))
   // inputs in the ABI layouts (device)
   const float *V_in, *W_in, *A_in, *pi_in, *alpha_init;
   // working layouts
   float *V, *Wfm, *Wmf;
   uint16_t *Wfm_h, *Wmf_h, *wh, *Rh;
-  float *alpha, *E, *w, *R, *c;
+  float *alpha, *w, *R, *c;
   float *phi, *ev, *sh, *fwd, *bwd, *post;
-  float2 *vll, *elbo, *lnz;
+  float2 *vll, *clw, *elbo, *lnz;
   float *sep;
   int *status;
   int *chainflag;    // [S] set when a chain needs the exact log-space pass

@@ -16,7 +16,11 @@ hipError_t launch_chain_fb(const WorkList &wl, int nmax, hipStream_t st);
 // d-hat from the messages (post: one block per source and 4 frames), then the exact
 // log-space pass over flagged chains (chains: one block per source).
 hipError_t launch_posterior(const WorkList &post, const WorkList &chains, int nmax, hipStream_t st);
-hipError_t launch_update(const WorkList &wl, int mode, int round, int mp_max, hipStream_t st);
+// k_update: floats of LDS per frame (elements padded to mp_max, then the S*N
+// chain posteriors) and frames per block (one wavefront each)
+int update_stride(int mp_max, int sn_max);
+int update_waves(int stride);
+hipError_t launch_update(const WorkList &wl, int mode, int round, int stride, hipStream_t st);
 hipError_t launch_finish(const WorkList &frames, const WorkList &tiles, const WorkList &iters, hipStream_t st);
 hipError_t launch_special(int64_t n, const float *x, float *psi, float *lg, hipStream_t st);
 hipError_t launch_chain_prep(const JobDesc &J, const float *logev, hipStream_t st);

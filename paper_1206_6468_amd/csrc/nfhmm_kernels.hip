@@ -42,12 +42,8 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
   return x * q + min(x, r) + i;
 }
 
-__device__ __forceinline__ uint16_t f2bf(float f) {       // round to nearest even
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// float -> bfloat16, round to nearest even (the gfx950 conversion instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Wavefront reductions with DPP lane moves: within quads, half-rows and rows of
@@ -60,6 +56,26 @@ __device__ __forceinline__ float dpp_mov(float old, float v) {
 __device__ __forceinline__ float lane63(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
+// Global-memory pointers (address space 1), so that loads and stores are
+// global_* instructions, which count only against vmcnt.  A kernel copies the
+// descriptor fields it needs into such locals before its first store: loaded
+// then, they are scalar loads kept in SGPRs; read after a store, the compiler
+// must reload them per lane (the store might have changed the descriptor).
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef unsigned int vu2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) vf2 gfloat2;
+typedef __attribute__((address_space(1))) vf4 gfloat4;
+typedef __attribute__((address_space(1))) vu2 guint2;
+typedef __attribute__((address_space(1))) uint16_t gu16;
+__device__ __forceinline__ gfloat *gptr(float *p) { return (gfloat *)p; }
+__device__ __forceinline__ const gfloat *gptr(const float *p) { return (const gfloat *)p; }
+__device__ __forceinline__ gfloat2 *gptr(float2 *p) { return (gfloat2 *)p; }
+__device__ __forceinline__ const gfloat2 *gptr(const float2 *p) { return (const gfloat2 *)p; }
+__device__ __forceinline__ gu16 *gptr(uint16_t *p) { return (gu16 *)p; }
+__device__ __forceinline__ const gu16 *gptr(const uint16_t *p) { return (const gu16 *)p; }
+
 __device__ __forceinline__ float wave_sum(float x) {
   x += dpp_mov<0xb1, 0xf>(0.0f, x);      // quad_perm [1,0,3,2]
   x += dpp_mov<0x4e, 0xf>(0.0f, x);      // quad_perm [2,3,0,1]
@@ -165,12 +181,35 @@ __global__ void k_fill_w_ones(JobDesc J) {
   }
 }
 
+// Tail bins for the default start (w = 1): Lambda[l][t] = sum_k beta[l][k], R = V / Lambda.
+// One 64-lane block per frame.
+__global__ void k_tail_ones(JobDesc J) {
+  const int t = blockIdx.x, lane = threadIdx.x;
+  for (int jt = 0; jt < J.Ft; ++jt) {
+    const int l = J.Fm + jt;
+    float acc = 0.0f;
+    for (int k = lane; k < J.M; k += 64)
+      acc += J.bf16 ? bf2f(J.Wfm_h[(size_t)l * J.Mp + k]) : J.Wfm[(size_t)l * J.Mp + k];
+    const float lam = wave_sum(acc);
+    if (lane == 0) {
+      const float v = J.V[(size_t)t * J.Fp + l];
+      const float rr = v > 0.0f ? v / lam : 0.0f;
+      if (J.bf16) J.Rh[(size_t)t * J.Fp + l] = f2bf(rr);
+      else J.R[(size_t)t * J.Fp + l] = rr;
+    }
+  }
+}
+
 // ------------------------------------------------------------------ MFMA tiles
-// C[i][j] = sum_k A[i][k] B[j][k] for a 64x64 block tile; 256 threads = 4 waves
-// in a 2x2 grid of 32x32 wave tiles, each 2x2 MFMA 16x16 tiles.  Operand k-slices
-// are staged through LDS.  Within every 16 (f32) or 32 (bf16) wide k-chunk lane
-// (r, q) of a fragment supplies the q-th group of consecutive k; A and B use the
-// same grouping, so every k is summed exactly once.
+// C[i][j] = sum_k A[i][k] B[j][k] for a (32*WM) x (32*WN) block tile: 256 threads
+// = 4 waves in a 2x2 grid, each wave (16*WM) x (16*WN) = WM x WN MFMA 16x16 tiles
+// held in accumulator registers.  Operand k-slices are staged through LDS; a
+// larger wave tile reuses every fragment read from LDS across more MFMAs, which
+// keeps the contraction under the LDS bandwidth of a CU.  Within every 16 (f32)
+// or 32 (bf16) wide k-chunk lane (r, q) of a fragment supplies the q-th group of
+// consecutive k; A and B use the same grouping, so every k is summed once.
+// Output tile element (row, col) lives in lane (lr, lq) of wave (wr, wc) at
+// acc[i][j][r] with row = wr*16*WM + i*16 + 4*lq + r, col = wc*16*WN + j*16 + lr.
 struct Frag {
   int wr, wc, lr, lq;
 };
@@ -184,206 +223,217 @@ __device__ __forceinline__ Frag frag_of(int tid) {
 constexpr int kBKf = 32, kLdsF = kBKf + 4;          // f32: 32 k per stage, rows padded
 constexpr int kBKh = 64, kLdsH = kBKh + 8;          // bf16: 64 k per stage
 
+// ROWS x 32 floats: thread tid loads rows (tid/8) + 32h, float4 column (tid%8)
+template <int ROWS, bool kMasked>
 __device__ __forceinline__ void gload_f32(const float *__restrict__ src, int ld, int nrows, int row0, int k,
-                                          int kend, int tid, float4 (&r)[2]) {
+                                          int kb, int ke, int tid, float4 (&r)[ROWS / 32]) {
   const int rr = tid >> 3, c = (tid & 7) * 4;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int row = row0 + rr + 32 * h, kk = k + c;
-    r[h] = (row < nrows && kk < kend) ? *(const float4 *)(src + (size_t)row * ld + kk)
-                                      : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-}
-
-// k-range [kb, ke) with kb, ke arbitrary: elementwise masked (separation only).
-__device__ __forceinline__ void gload_f32_masked(const float *__restrict__ src, int ld, int nrows, int row0,
-                                                 int k, int kb, int ke, int tid, float4 (&r)[2]) {
-  const int rr = tid >> 3, c = (tid & 7) * 4;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < ROWS / 32; ++h) {
     const int row = row0 + rr + 32 * h, kk = k + c;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (row < nrows && kk + 3 >= kb && kk < ke) {
+    if (kMasked) {   // k-range [kb, ke) with kb, ke arbitrary: elementwise mask
+      if (row < nrows && kk + 3 >= kb && kk < ke) {
+        v = *(const float4 *)(src + (size_t)row * ld + kk);
+        if (kk + 0 < kb || kk + 0 >= ke) v.x = 0.f;
+        if (kk + 1 < kb || kk + 1 >= ke) v.y = 0.f;
+        if (kk + 2 < kb || kk + 2 >= ke) v.z = 0.f;
+        if (kk + 3 < kb || kk + 3 >= ke) v.w = 0.f;
+      }
+    } else if (row < nrows && kk < ke) {
       v = *(const float4 *)(src + (size_t)row * ld + kk);
-      if (kk + 0 < kb || kk + 0 >= ke) v.x = 0.f;
-      if (kk + 1 < kb || kk + 1 >= ke) v.y = 0.f;
-      if (kk + 2 < kb || kk + 2 >= ke) v.z = 0.f;
-      if (kk + 3 < kb || kk + 3 >= ke) v.w = 0.f;
     }
     r[h] = v;
   }
 }
 
-__device__ __forceinline__ void sstore_f32(float *lds, int tid, const float4 (&r)[2]) {
+template <int ROWS>
+__device__ __forceinline__ void sstore_f32(float *lds, int tid, const float4 (&r)[ROWS / 32]) {
   const int rr = tid >> 3, c = (tid & 7) * 4;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) *(float4 *)(lds + (rr + 32 * h) * kLdsF + c) = r[h];
+  for (int h = 0; h < ROWS / 32; ++h) *(float4 *)(lds + (rr + 32 * h) * kLdsF + c) = r[h];
 }
 
+template <int WM, int WN>
 __device__ __forceinline__ void mma_stage_f32(const float *As, const float *Bs, const Frag &f,
-                                              floatx4 (&acc)[2][2]) {
+                                              floatx4 (&acc)[WM][WN]) {
 #pragma unroll
   for (int kk = 0; kk < kBKf; kk += 16) {
-    float4 a[2], b[2];
+    float4 a[WM], b[WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = *(const float4 *)(As + (f.wr * 32 + i * 16 + f.lr) * kLdsF + kk + f.lq * 4);
+    for (int i = 0; i < WM; ++i)
+      a[i] = *(const float4 *)(As + (f.wr * 16 * WM + i * 16 + f.lr) * kLdsF + kk + f.lq * 4);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = *(const float4 *)(Bs + (f.wc * 32 + j * 16 + f.lr) * kLdsF + kk + f.lq * 4);
+    for (int j = 0; j < WN; ++j)
+      b[j] = *(const float4 *)(Bs + (f.wc * 16 * WN + j * 16 + f.lr) * kLdsF + kk + f.lq * 4);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].x, b[j].x, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].y, b[j].y, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].z, b[j].z, acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i].w, b[j].w, acc[i][j], 0, 0, 0);
-      }
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const float av = p == 0 ? a[i].x : p == 1 ? a[i].y : p == 2 ? a[i].z : a[i].w;
+          const float bv = p == 0 ? b[j].x : p == 1 ? b[j].y : p == 2 ? b[j].z : b[j].w;
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
+        }
   }
 }
 
-// Full f32 main loop over k in [kb, ke); masked selects the elementwise loader.
-template <bool kMasked>
+// f32 main loop over k in [kb, ke); kMasked selects the elementwise k mask
+template <int WM, int WN, bool kMasked>
 __device__ void gemm_nt_f32(const float *__restrict__ A, int lda, int arows, int row0, const float *__restrict__ B,
-                            int ldb, int bcols, int col0, int kb, int ke, floatx4 (&acc)[2][2]) {
-  __shared__ float As[2][64 * kLdsF];
-  __shared__ float Bs[2][64 * kLdsF];
+                            int ldb, int bcols, int col0, int kb, int ke, floatx4 (&acc)[WM][WN]) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  __shared__ float As[2][BM * kLdsF];
+  __shared__ float Bs[2][BN * kLdsF];
   const int tid = threadIdx.x;
   const Frag f = frag_of(tid);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int k0 = kMasked ? (kb & ~3) : kb;
-  float4 ra[2], rb[2];
-  if (kMasked) {
-    gload_f32_masked(A, lda, arows, row0, k0, kb, ke, tid, ra);
-    gload_f32_masked(B, ldb, bcols, col0, k0, kb, ke, tid, rb);
-  } else {
-    gload_f32(A, lda, arows, row0, k0, ke, tid, ra);
-    gload_f32(B, ldb, bcols, col0, k0, ke, tid, rb);
-  }
-  sstore_f32(As[0], tid, ra);
-  sstore_f32(Bs[0], tid, rb);
+  float4 ra[BM / 32], rb[BN / 32];
+  gload_f32<BM, kMasked>(A, lda, arows, row0, k0, kb, ke, tid, ra);
+  gload_f32<BN, kMasked>(B, ldb, bcols, col0, k0, kb, ke, tid, rb);
+  sstore_f32<BM>(As[0], tid, ra);
+  sstore_f32<BN>(Bs[0], tid, rb);
   __syncthreads();
   int buf = 0;
   for (int k = k0; k < ke; k += kBKf) {
     const int kn = k + kBKf;
     const bool more = kn < ke;
     if (more) {
-      if (kMasked) {
-        gload_f32_masked(A, lda, arows, row0, kn, kb, ke, tid, ra);
-        gload_f32_masked(B, ldb, bcols, col0, kn, kb, ke, tid, rb);
-      } else {
-        gload_f32(A, lda, arows, row0, kn, ke, tid, ra);
-        gload_f32(B, ldb, bcols, col0, kn, ke, tid, rb);
-      }
+      gload_f32<BM, kMasked>(A, lda, arows, row0, kn, kb, ke, tid, ra);
+      gload_f32<BN, kMasked>(B, ldb, bcols, col0, kn, kb, ke, tid, rb);
     }
-    mma_stage_f32(As[buf], Bs[buf], f, acc);
+    mma_stage_f32<WM, WN>(As[buf], Bs[buf], f, acc);
     if (more) {
-      sstore_f32(As[buf ^ 1], tid, ra);
-      sstore_f32(Bs[buf ^ 1], tid, rb);
+      sstore_f32<BM>(As[buf ^ 1], tid, ra);
+      sstore_f32<BN>(Bs[buf ^ 1], tid, rb);
     }
     __syncthreads();
     buf ^= 1;
   }
 }
 
+template <int ROWS>
 __device__ __forceinline__ void gload_bf16(const uint16_t *__restrict__ src, int ld, int nrows, int row0, int k,
-                                           int kend, int tid, uint4 (&r)[2]) {
+                                           int kend, int tid, uint4 (&r)[ROWS / 32]) {
   const int rr = tid >> 3, c = (tid & 7) * 8;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
+  for (int h = 0; h < ROWS / 32; ++h) {
     const int row = row0 + rr + 32 * h, kk = k + c;
     r[h] = (row < nrows && kk < kend) ? *(const uint4 *)(src + (size_t)row * ld + kk) : make_uint4(0, 0, 0, 0);
   }
 }
-__device__ __forceinline__ void sstore_bf16(uint16_t *lds, int tid, const uint4 (&r)[2]) {
+template <int ROWS>
+__device__ __forceinline__ void sstore_bf16(uint16_t *lds, int tid, const uint4 (&r)[ROWS / 32]) {
   const int rr = tid >> 3, c = (tid & 7) * 8;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) *(uint4 *)(lds + (rr + 32 * h) * kLdsH + c) = r[h];
+  for (int h = 0; h < ROWS / 32; ++h) *(uint4 *)(lds + (rr + 32 * h) * kLdsH + c) = r[h];
 }
+template <int WM, int WN>
 __device__ __forceinline__ void mma_stage_bf16(const uint16_t *As, const uint16_t *Bs, const Frag &f,
-                                               floatx4 (&acc)[2][2]) {
+                                               floatx4 (&acc)[WM][WN]) {
 #pragma unroll
   for (int kk = 0; kk < kBKh; kk += 32) {
-    bf16x8 a[2], b[2];
+    bf16x8 a[WM], b[WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-      a[i] = *(const bf16x8 *)(As + (f.wr * 32 + i * 16 + f.lr) * kLdsH + kk + f.lq * 8);
+    for (int i = 0; i < WM; ++i)
+      a[i] = *(const bf16x8 *)(As + (f.wr * 16 * WM + i * 16 + f.lr) * kLdsH + kk + f.lq * 8);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      b[j] = *(const bf16x8 *)(Bs + (f.wc * 32 + j * 16 + f.lr) * kLdsH + kk + f.lq * 8);
+    for (int j = 0; j < WN; ++j)
+      b[j] = *(const bf16x8 *)(Bs + (f.wc * 16 * WN + j * 16 + f.lr) * kLdsH + kk + f.lq * 8);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < WN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
 }
 
+template <int WM, int WN>
 __device__ void gemm_nt_bf16(const uint16_t *__restrict__ A, int lda, int arows, int row0,
                              const uint16_t *__restrict__ B, int ldb, int bcols, int col0, int kend,
-                             floatx4 (&acc)[2][2]) {
-  __shared__ uint16_t As[2][64 * kLdsH];
-  __shared__ uint16_t Bs[2][64 * kLdsH];
+                             floatx4 (&acc)[WM][WN]) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  __shared__ uint16_t As[2][BM * kLdsH];
+  __shared__ uint16_t Bs[2][BN * kLdsH];
   const int tid = threadIdx.x;
   const Frag f = frag_of(tid);
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  uint4 ra[2], rb[2];
-  gload_bf16(A, lda, arows, row0, 0, kend, tid, ra);
-  gload_bf16(B, ldb, bcols, col0, 0, kend, tid, rb);
-  sstore_bf16(As[0], tid, ra);
-  sstore_bf16(Bs[0], tid, rb);
+    for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  uint4 ra[BM / 32], rb[BN / 32];
+  gload_bf16<BM>(A, lda, arows, row0, 0, kend, tid, ra);
+  gload_bf16<BN>(B, ldb, bcols, col0, 0, kend, tid, rb);
+  sstore_bf16<BM>(As[0], tid, ra);
+  sstore_bf16<BN>(Bs[0], tid, rb);
   __syncthreads();
   int buf = 0;
   for (int k = 0; k < kend; k += kBKh) {
     const int kn = k + kBKh;
     const bool more = kn < kend;
     if (more) {
-      gload_bf16(A, lda, arows, row0, kn, kend, tid, ra);
-      gload_bf16(B, ldb, bcols, col0, kn, kend, tid, rb);
+      gload_bf16<BM>(A, lda, arows, row0, kn, kend, tid, ra);
+      gload_bf16<BN>(B, ldb, bcols, col0, kn, kend, tid, rb);
     }
-    mma_stage_bf16(As[buf], Bs[buf], f, acc);
+    mma_stage_bf16<WM, WN>(As[buf], Bs[buf], f, acc);
     if (more) {
-      sstore_bf16(As[buf ^ 1], tid, ra);
-      sstore_bf16(Bs[buf ^ 1], tid, rb);
+      sstore_bf16<BM>(As[buf ^ 1], tid, ra);
+      sstore_bf16<BN>(Bs[buf ^ 1], tid, rb);
     }
     __syncthreads();
     buf ^= 1;
   }
 }
 
+// Block tiles of the two contractions (wave tile = 16*W rows x 16*W columns).
+#ifndef NFHMM_SPEC_WM
+#define NFHMM_SPEC_WM 4
+#define NFHMM_SPEC_WN 4
+#endif
+#ifndef NFHMM_CNT_WM
+#define NFHMM_CNT_WM 2
+#define NFHMM_CNT_WN 4
+#endif
+constexpr int kSpecWM = NFHMM_SPEC_WM, kSpecWN = NFHMM_SPEC_WN;   // Lambda: bins x frames
+constexpr int kCntWM = NFHMM_CNT_WM, kCntWN = NFHMM_CNT_WN;       // counts: elements x frames
+
 // ------------------------------------------------------------------ Eq. 7: Lambda, R
-// Rows l (frequency), columns t (frames), k over all M elements.
-// Output tile element (row, col) lives in lane (lr, lq) of wave (wr, wc) at
-// acc[i][j][r] with row = wr*32 + i*16 + 4*lq + r and col = wc*32 + j*16 + lr.
+// Rows l (frequency, [0, Fm)), columns t (frames), k over all M elements.
 template <bool kBF16>
 __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
+  constexpr int WM = kSpecWM, WN = kSpecWN, BM = 32 * WM, BN = 32 * WN;
   const int b = xcd_remap(blockIdx.x, wl.total);
   const int jb = find_job(wl.start, wl.njobs, b);
   const JobDesc &J = wl.jobs[jb];
+  const int T = J.T, Fp = J.Fp, Fm = J.Fm;
+  const gfloat *Vin = gptr(J.V);
+  gfloat *Rout = gptr(J.R);
+  gu16 *Rh = gptr(J.Rh);
+  gfloat2 *vll = gptr(J.vll);
   const int tile = b - wl.start[jb];
-  const int nrt = J.nlt;
+  const int nrt = J.nst;
   const int rt = tile % nrt, ct = tile / nrt;
-  const int row0 = rt * 64, col0 = ct * 64;
-  floatx4 acc[2][2];
-  if constexpr (kBF16) gemm_nt_bf16(J.Wfm_h, J.Mp, J.Fp, row0, J.wh, J.Mp, J.T, col0, J.Mp, acc);
-  else gemm_nt_f32<false>(J.Wfm, J.Mp, J.Fp, row0, J.w, J.Mp, J.T, col0, 0, J.Mp, acc);
+  const int row0 = rt * BM, col0 = ct * BN;
+  floatx4 acc[WM][WN];
+  if constexpr (kBF16) gemm_nt_bf16<WM, WN>(J.Wfm_h, J.Mp, J.Fm, row0, J.wh, J.Mp, J.T, col0, J.Mp, acc);
+  else gemm_nt_f32<WM, WN, false>(J.Wfm, J.Mp, J.Fm, row0, J.w, J.Mp, J.T, col0, 0, J.Mp, acc);
 
   const Frag f = frag_of(threadIdx.x);
-  __shared__ Comp part[2][64];
+  __shared__ Comp part[2][BN];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int t = col0 + f.wc * 32 + j * 16 + f.lr;
+  for (int j = 0; j < WN; ++j) {
+    const int t = col0 + f.wc * 16 * WN + j * 16 + f.lr;
     Comp cs = comp_zero();
-    if (t < J.T) {
+    if (t < T) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const int l = row0 + f.wr * 32 + i * 16 + 4 * f.lq;
-        if (l < J.Fp) {
-          const float4 v = *(const float4 *)(J.V + (size_t)t * J.Fp + l);
+      for (int i = 0; i < WM; ++i) {
+        const int l = row0 + f.wr * 16 * WM + i * 16 + 4 * f.lq;
+        if (l < Fm) {
+          const vf4 v = *(const gfloat4 *)(Vin + (size_t)t * Fp + l);
           const float lam[4] = {acc[i][j][0], acc[i][j][1], acc[i][j][2], acc[i][j][3]};
           const float vv[4] = {v.x, v.y, v.z, v.w};
           float rr[4];
@@ -393,17 +443,17 @@ __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
             if (vv[r] > 0.0f) comp_add(cs, vv[r] * logf(lam[r]));
           }
           if constexpr (kBF16) {
-            uint2 h;
+            vu2 h;
             h.x = (uint32_t)f2bf(rr[0]) | ((uint32_t)f2bf(rr[1]) << 16);
             h.y = (uint32_t)f2bf(rr[2]) | ((uint32_t)f2bf(rr[3]) << 16);
-            *(uint2 *)(J.Rh + (size_t)t * J.Fp + l) = h;
+            *(guint2 *)(Rh + (size_t)t * Fp + l) = h;
           } else {
-            *(float4 *)(J.R + (size_t)t * J.Fp + l) = make_float4(rr[0], rr[1], rr[2], rr[3]);
+            *(gfloat4 *)(Rout + (size_t)t * Fp + l) = vf4{rr[0], rr[1], rr[2], rr[3]};
           }
         }
       }
     }
-    // reduce over the 4 lane groups that share column t
+    // reduce over the 4 lane groups that share column t, then over the two wave rows
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
       Comp d;
@@ -413,47 +463,92 @@ __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
     }
     if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
     __syncthreads();
-    if (f.lq == 0 && f.wr == 0 && t < J.T) {
+    if (f.lq == 0 && f.wr == 0 && t < T) {
       const Comp tot = comp_merge(cs, part[f.wc][j * 16 + f.lr]);
-      J.vll[(size_t)rt * J.T + t] = make_float2(tot.hi, tot.lo);
+      vll[(size_t)rt * T + t] = vf2{tot.hi, tot.lo};
     }
     __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ Eq. 6 first term: c
+// Rows k (elements), columns t (frames), contraction over the Fm bins, plus the
+// rank-Ft update of the tail bins in the epilogue.
 template <bool kBF16>
 __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
+  constexpr int WM = kCntWM, WN = kCntWN, BM = 32 * WM, BN = 32 * WN;
   const int b = xcd_remap(blockIdx.x, wl.total);
   const int jb = find_job(wl.start, wl.njobs, b);
   const JobDesc &J = wl.jobs[jb];
+  const int T = J.T, Fp = J.Fp, Fm = J.Fm, Ft = J.Ft, Mp = J.Mp;
+  const gfloat *Rin = gptr(J.R), *Wmf = gptr(J.Wmf), *win = gptr(J.w);
+  const gu16 *Rh = gptr(J.Rh), *Wmf_h = gptr(J.Wmf_h), *wh = gptr(J.wh);
+  gfloat *cout = gptr(J.c);
+  gfloat2 *clw = gptr(J.clw);
   const int tile = b - wl.start[jb];
-  const int nrt = (J.Mp + 63) / 64;
+  const int nrt = (Mp + BM - 1) / BM;
   const int rt = tile % nrt, ct = tile / nrt;
-  const int row0 = rt * 64, col0 = ct * 64;
-  floatx4 acc[2][2];
-  if constexpr (kBF16) gemm_nt_bf16(J.Wmf_h, J.Fp, J.Mp, row0, J.Rh, J.Fp, J.T, col0, J.Fp, acc);
-  else gemm_nt_f32<false>(J.Wmf, J.Fp, J.Mp, row0, J.R, J.Fp, J.T, col0, 0, J.Fp, acc);
+  const int row0 = rt * BM, col0 = ct * BN;
+  floatx4 acc[WM][WN];
+  if constexpr (kBF16) gemm_nt_bf16<WM, WN>(J.Wmf_h, J.Fp, J.Mp, row0, J.Rh, J.Fp, J.T, col0, J.Fm, acc);
+  else gemm_nt_f32<WM, WN, false>(J.Wmf, J.Fp, J.Mp, row0, J.R, J.Fp, J.T, col0, 0, J.Fm, acc);
   const Frag f = frag_of(threadIdx.x);
+  __shared__ Comp part[2][BN];
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int t = col0 + f.wc * 32 + j * 16 + f.lr;
-    if (t >= J.T) continue;
+  for (int j = 0; j < WN; ++j) {
+    const int t = col0 + f.wc * 16 * WN + j * 16 + f.lr;
+    Comp cs = comp_zero();     // -sum_k c ln w over this tile's rows: a bound term
+    if (t < T) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int k = row0 + f.wr * 32 + i * 16 + 4 * f.lq;
-      if (k >= J.Mp) continue;
-      float4 w;
-      if constexpr (kBF16) {
-        const uint2 h = *(const uint2 *)(J.wh + (size_t)t * J.Mp + k);
-        w = make_float4(bf2f((uint16_t)(h.x & 0xffff)), bf2f((uint16_t)(h.x >> 16)), bf2f((uint16_t)(h.y & 0xffff)),
-                        bf2f((uint16_t)(h.y >> 16)));
-      } else {
-        w = *(const float4 *)(J.w + (size_t)t * J.Mp + k);
+      for (int i = 0; i < WM; ++i) {
+        const int k = row0 + f.wr * 16 * WM + i * 16 + 4 * f.lq;
+        if (k >= Mp) continue;
+        // tail bins: acc += beta[l][k] R[t][l] for l in [Fm, F)
+        for (int l = Fm; l < Fm + Ft; ++l) {
+          float rl;
+          float wk[4];
+          if constexpr (kBF16) {
+            rl = bf2f(Rh[(size_t)t * Fp + l]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wk[r] = bf2f(Wmf_h[(size_t)(k + r) * Fp + l]);
+          } else {
+            rl = Rin[(size_t)t * Fp + l];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) wk[r] = Wmf[(size_t)(k + r) * Fp + l];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[i][j][r] = fmaf(wk[r], rl, acc[i][j][r]);
+        }
+        vf4 w;
+        if constexpr (kBF16) {
+          const vu2 h = *(const guint2 *)(wh + (size_t)t * Mp + k);
+          w = vf4{bf2f((uint16_t)(h.x & 0xffff)), bf2f((uint16_t)(h.x >> 16)),
+                  bf2f((uint16_t)(h.y & 0xffff)), bf2f((uint16_t)(h.y >> 16))};
+        } else {
+          w = *(const gfloat4 *)(win + (size_t)t * Mp + k);
+        }
+        const vf4 c = vf4{w.x * acc[i][j][0], w.y * acc[i][j][1], w.z * acc[i][j][2], w.w * acc[i][j][3]};
+        *(gfloat4 *)(cout + (size_t)t * Mp + k) = c;
+        if (w.x > 0.0f) comp_add(cs, -c.x * logf(w.x));
+        if (w.y > 0.0f) comp_add(cs, -c.y * logf(w.y));
+        if (w.z > 0.0f) comp_add(cs, -c.z * logf(w.z));
+        if (w.w > 0.0f) comp_add(cs, -c.w * logf(w.w));
       }
-      *(float4 *)(J.c + (size_t)t * J.Mp + k) =
-          make_float4(w.x * acc[i][j][0], w.y * acc[i][j][1], w.z * acc[i][j][2], w.w * acc[i][j][3]);
     }
+#pragma unroll
+    for (int o = 16; o < 64; o <<= 1) {
+      Comp d;
+      d.hi = __shfl_xor(cs.hi, o);
+      d.lo = __shfl_xor(cs.lo, o);
+      cs = comp_merge(cs, d);
+    }
+    if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
+    __syncthreads();
+    if (f.lq == 0 && f.wr == 0 && t < T) {
+      const Comp tot = comp_merge(cs, part[f.wc][j * 16 + f.lr]);
+      clw[(size_t)rt * T + t] = vf2{tot.hi, tot.lo};
+    }
+    __syncthreads();
   }
 }
 
@@ -481,19 +576,22 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
 // block ahead, before that block's message stores, so the waits for the loads
 // never include the stores (stores and loads share one counter on gfx9).
 constexpr float kRescue = 9.5367431640625e-07f;   // 2^-20
-constexpr int kFbBlock = 8;
+#ifndef NFHMM_FB_BLOCK
+#define NFHMM_FB_BLOCK 8
+#endif
+constexpr int kFbBlock = NFHMM_FB_BLOCK;
 
-// Global-memory pointers (address space 1), so that loads and stores are
-// global_* instructions, which count only against vmcnt.
-typedef __attribute__((address_space(1))) float gfloat;
-__device__ __forceinline__ gfloat *gptr(float *p) { return (gfloat *)p; }
-__device__ __forceinline__ const gfloat *gptr(const float *p) { return (const gfloat *)p; }
 
 // One recursion step: every lane publishes x through LDS, then forms
 // y = sum_m x_m coef[m]; tot is the normaliser (lane N's row, or a reduction).
+#ifndef NFHMM_FB_LDS
+#define NFHMM_FB_LDS 1
+#endif
 template <int NR>
 __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&coef)[NR], float x, int lane, int N,
                                              bool sumlane, bool live, bool fwd, float &tot) {
+  float y0 = 0.0f, y1 = 0.0f;
+#if NFHMM_FB_LDS
   if (lane < NR) buf[p * NR + lane] = x;
   // The block is one wavefront and LDS executes a wavefront's operations in issue
   // order, so the reads below see every lane's write; only the compiler must not
@@ -503,7 +601,6 @@ __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&c
 #pragma unroll
   for (int q = 0; q < NR / 4; ++q) v[q] = *(const float4 *)(buf + p * NR + 4 * q);
   p ^= 1;
-  float y0 = 0.0f, y1 = 0.0f;
 #pragma unroll
   for (int q = 0; q < NR / 4; ++q) {
     y0 = fmaf(v[q].x, coef[4 * q + 0], y0);
@@ -511,6 +608,17 @@ __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&c
     y0 = fmaf(v[q].z, coef[4 * q + 2], y0);
     y1 = fmaf(v[q].w, coef[4 * q + 3], y1);
   }
+#else
+  // Every lane needs the whole message: read it lane by lane into scalar
+  // registers (no LDS round trip, whose latency grows with the LDS traffic of
+  // other waves on the same CU).
+  const int xi = __float_as_int(x);
+#pragma unroll
+  for (int m = 0; m < NR; m += 2) {
+    y0 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m)), coef[m], y0);
+    y1 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m + 1)), coef[m + 1], y1);
+  }
+#endif
   const float y = y0 + y1;
   if (sumlane) tot = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), N));
   else tot = wave_sum(live ? (fwd ? x : y) : 0.0f);
@@ -821,114 +929,201 @@ __global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
 }
 
 // ------------------------------------------------------------------ Eq. 6 + Eq. 7/8 inputs
-// One block of 256 threads per (job, frame).  Modes:
-//   kUpdMessages: d-hat from this iteration's messages, alpha = c + gamma B'd + 1,
-//                 and the frame's bound contribution for iteration (round - start);
+// One wavefront per (job, frame), kUpdWaves(Mp) frames of one job per block; no
+// block-level synchronisation (LDS holds each wave's own rows).  Modes:
+//   kUpdMessages: alpha = c + gamma B'd + 1 with this iteration's d-hat, and the
+//                 frame's bound contribution for iteration (round - start);
 //   kUpdUniform:  the default start: alpha = c + gamma/N + 1 (c computed with w = 1);
 //   kUpdFromAlpha: alpha read from alpha_init ([T][M], warm start / resume).
-// Then, in every mode: alpha_0, E = psi(alpha) - psi(alpha_0), w = exp(E), and
-// gamma*phi (Eq. 8) with its shifted exponential for the next chain pass.
-__global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round) {
-  extern __shared__ float sE[];                  // [Mp]
-  __shared__ float sD[kMaxSources * 64];         // d-hat, then gamma*phi
-  __shared__ Comp red[4][4];
-  __shared__ float bcast[4];
-  const int b = blockIdx.x;
-  const int jb = find_job(wl.start, wl.njobs, b);
-  const JobDesc &J = wl.jobs[jb];
-  const int t = b - wl.start[jb];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int S = J.S, N = J.N, K = J.K, M = J.M, Mp = J.Mp, T = J.T;
-  const float gamma = J.gamma;
-  const size_t row = (size_t)t * Mp;
+// Then, in every mode: alpha_0, w = exp(psi(alpha) - psi(alpha_0)), gamma*phi
+// (Eq. 8, up to a per-frame constant) with its shifted exponential for the next
+// chain pass, and the Lambda rows of the tail bins.  alpha itself is stored only
+// when it is an output (the job's last iteration, or a start with no iterations):
+// it is c + gamma B'd + 1 and nothing else reads it.
+__device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
 
+#ifndef NFHMM_UPD_U
+#define NFHMM_UPD_U 4
+#endif
+#ifndef NFHMM_UPD_ATTR
+#define NFHMM_UPD_ATTR
+#endif
+constexpr int kUpdU = NFHMM_UPD_U;   // elements per lane whose loads are issued together
+constexpr int kMaxTail = 4;   // tail bins handled here (F mod 64 <= 4)
+
+template <bool kBF16>
+__device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, float *sE, int mode, int round) {
+  const int S = J.S, N = J.N, K = J.K, M = J.M, Mp = J.Mp, T = J.T, Fp = J.Fp;
+  const int Fm = J.Fm, Ft = J.Ft, nst = J.nst;
+  const int it = round - J.start_round, iters = J.iters;
+  const float gamma = J.gamma;
+  const gfloat *c = gptr(J.c), *alpha_init = gptr(J.alpha_init), *post_in = gptr(J.post);
+  const gfloat *phi_in = gptr(J.phi), *sh_in = gptr(J.sh), *Vin = gptr(J.V);
+  const gfloat *Wfm = gptr(J.Wfm);
+  const gu16 *Wfm_h = gptr(J.Wfm_h);
+  const gfloat2 *lnz = gptr(J.lnz), *clw = gptr(J.clw);
+  gfloat2 *vll = gptr(J.vll), *elbo = gptr(J.elbo);
+  gfloat *alpha = gptr(J.alpha), *wout = gptr(J.w), *Rout = gptr(J.R), *post = gptr(J.post);
+  gfloat *phi = gptr(J.phi), *ev = gptr(J.ev), *sh = gptr(J.sh);
+  gu16 *wh = gptr(J.wh), *Rh = gptr(J.Rh);
+
+  float *sD = sE + Mp;
+  const size_t row = (size_t)t * Mp;
+  const bool msg = mode == kUpdMessages;
+  const bool store_alpha = msg ? (it == iters - 1) : (iters == 0);
+  const bool live = lane < N;
+
+  // ---- loads that do not depend on anything computed here, issued first
+  vf2 vtail = vf2{0.0f, 0.0f};   // tail part of sum V ln Lambda (previous call)
+  Comp pv = comp_zero();                    // contraction-side parts of the bound
   Comp chain = comp_zero();
-  // ---- d-hat of every source at frame t (from k_posterior / k_chain_exact)
-  if (mode == kUpdMessages) {
-    for (int s = wave; s < S; s += 4) {
-      const size_t o = ((size_t)s * T + t) * 64 + lane;
-      const bool live = lane < N;
-      const float d = live ? J.post[((size_t)s * T + t) * N + lane] : 0.0f;
-      sD[s * 64 + lane] = d;
-      // -gamma sum_n d phi (phi holds gamma*phi-hat) and this frame's part of ln Z
-      Comp c = comp_zero();
-      if (live) comp_add(c, -d * J.phi[o]);
-      c = wave_comp(c);
-      if (lane == 0) {
-        comp_add(c, J.sh[(size_t)s * T + t]);
-        if (t == 0) {
-          const float2 z = J.lnz[s];
-          comp_add(c, z.x);
-          comp_add(c, z.y);
+  if (msg) {
+    if (Ft > 0) vtail = vll[(size_t)nst * T + t];
+    const int nkt = (Mp + 63) / 64;
+    for (int r = lane; r < nst; r += 64) {
+      const vf2 v = vll[(size_t)r * T + t];
+      Comp d; d.hi = v.x; d.lo = v.y;
+      pv = comp_merge(pv, d);
+    }
+    for (int r = lane; r < nkt; r += 64) {
+      const vf2 v = clw[(size_t)r * T + t];
+      Comp d; d.hi = v.x; d.lo = v.y;
+      pv = comp_merge(pv, d);
+    }
+    const int nl = live ? lane : 0;
+    float dv[kMaxSources], pf[kMaxSources], shv[kMaxSources];
+#pragma unroll
+    for (int s = 0; s < kMaxSources; ++s) {
+      const int ss = s < S ? s : 0;
+      dv[s] = post_in[((size_t)ss * T + t) * N + nl];
+      pf[s] = phi_in[((size_t)ss * T + t) * 64 + nl];
+      shv[s] = sh_in[(size_t)ss * T + t];
+    }
+    // d-hat of every source at frame t, -sum_n d (gamma phi) and ln Z's part
+    Comp cc = comp_zero();
+#pragma unroll
+    for (int s = 0; s < kMaxSources; ++s) {
+      if (s < S) {
+        if (live) {
+          sD[s * N + lane] = dv[s];
+          comp_add(cc, -dv[s] * pf[s]);
         }
-        chain = comp_merge(chain, c);
+        comp_add(chain, shv[s]);
+      }
+    }
+    chain = comp_merge(chain, wave_comp(cc));
+    if (t == 0) {
+      for (int s = 0; s < S; ++s) {
+        const vf2 z = lnz[s];
+        comp_add(chain, z.x);
+        comp_add(chain, z.y);
       }
     }
   } else {
-    for (int i = tid; i < S * 64; i += 256) sD[i] = ((i & 63) < N) ? 1.0f / (float)N : 0.0f;
-    for (int i = tid; i < S * N; i += 256) J.post[((size_t)(i / N) * T + t) * N + (i % N)] = 1.0f / (float)N;
+    for (int i = lane; i < S * N; i += 64) {
+      sD[i] = 1.0f / (float)N;
+      post[((size_t)(i / N) * T + t) * N + (i % N)] = 1.0f / (float)N;
+    }
   }
-  __syncthreads();
+  lds_order();
 
-  // ---- Eq. 6 and the sums over k
-  Comp asum = comp_zero(), lg = comp_zero(), ce = comp_zero();
-  for (int k = tid; k < Mp; k += 256) {
-    float a = 0.0f;
-    if (k < M) {
-      if (mode == kUpdFromAlpha) {
-        a = J.alpha_init[(size_t)t * M + k];
-      } else {
-        const int s = k / J.NK, n = (k / K) % N;
-        const float cc = J.c[row + k];
-        a = cc + gamma * sD[s * 64 + n] + 1.0f;
-        if (mode == kUpdMessages) {
-          comp_add(ce, -cc * J.E[row + k]);
-          comp_add(lg, lgammaf_pos(a));
+  // ---- Eq. 6; element k belongs to state g = k / K (kept incrementally).  Loads
+  //      past the end read the last element (in bounds) and are not used.
+  Comp asum = comp_zero();
+  {
+    const int step_g = 64 / K, step_r = 64 % K;
+    int g = lane / K, r = lane - (lane / K) * K;
+    const bool from_alpha = mode == kUpdFromAlpha;
+    for (int base = 0; base < Mp; base += 64 * kUpdU) {
+      float cv[kUpdU];
+#pragma unroll
+      for (int u = 0; u < kUpdU; ++u) {
+        const int k = min(base + 64 * u + lane, M - 1);
+        cv[u] = from_alpha ? alpha_init[(size_t)t * M + k] : c[row + k];
+      }
+#pragma unroll
+      for (int u = 0; u < kUpdU; ++u) {
+        const int k = base + 64 * u + lane;
+        float a = from_alpha ? cv[u] : cv[u] + gamma * sD[min(g, S * N - 1)] + 1.0f;
+        a = k < M ? a : 0.0f;
+        comp_add(asum, a);
+        if (store_alpha && k < M) alpha[row + k] = a;
+        if (k < Mp) sE[k] = a;
+        g += step_g;
+        r += step_r;
+        if (r >= K) { r -= K; ++g; }
+      }
+    }
+  }
+  asum = wave_comp(asum);
+  const float a0 = asum.hi + asum.lo;
+  const Shift8 z0 = shift8(a0);
+  const float rest0 = psi_rest(z0);
+  const float inv_xs0 = 1.0f / z0.xs;
+  lds_order();
+
+  // ---- w = exp(psi(alpha) - psi(alpha_0)) = (xs / xs0) exp(rest - rest0);
+  //      sE keeps psi(alpha_k) for Eq. 8; sum_k lnG(alpha_k) for the bound;
+  //      tail bins: Lambda[l][t] = sum_k beta[l][k] w_k for the next contraction
+  Comp lg = comp_zero();
+  float tacc[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int base = 0; base < Mp; base += 64 * kUpdU) {
+    float tw[kMaxTail][kUpdU];
+#pragma unroll
+    for (int jt = 0; jt < kMaxTail; ++jt) {
+      if (jt < Ft) {
+#pragma unroll
+        for (int u = 0; u < kUpdU; ++u) {
+          const size_t o = (size_t)(Fm + jt) * Mp + min(base + 64 * u + lane, M - 1);
+          tw[jt][u] = kBF16 ? bf2f(Wfm_h[o]) : Wfm[o];
         }
       }
-      comp_add(asum, a);
     }
-    sE[k] = a;
-    J.alpha[row + k] = a;
+#pragma unroll
+    for (int u = 0; u < kUpdU; ++u) {
+      const int k = base + 64 * u + lane;
+      const bool in = k < M;
+      const Shift8 z = shift8(in ? sE[k] : 1.0f);
+      const float rest = psi_rest(z);
+      const float lxs = fast_ln(z.xs);
+      const float ps = lxs + rest;
+      float w = in ? (z.xs * inv_xs0) * fast_exp(rest - rest0) : 0.0f;
+      if (msg && in) comp_add(lg, lgamma_from(z, lxs));
+      if (k < Mp) {
+        sE[k] = in ? ps : 0.0f;
+        if constexpr (kBF16) {
+          const uint16_t h = f2bf(w);
+          wh[row + k] = h;
+          w = bf2f(h);
+        } else {
+          wout[row + k] = w;
+        }
+      }
+#pragma unroll
+      for (int jt = 0; jt < kMaxTail; ++jt)
+        if (jt < Ft) tacc[jt] = fmaf(tw[jt][u], w, tacc[jt]);
+    }
   }
-  // block reduction of (asum, lg, ce)
-  asum = wave_comp(asum);
-  lg = wave_comp(lg);
-  ce = wave_comp(ce);
-  if (lane == 0) { red[wave][0] = asum; red[wave][1] = lg; red[wave][2] = ce; red[wave][3] = chain; }
-  __syncthreads();
-  if (tid == 0) {
-    Comp a = red[0][0];
-    for (int w2 = 1; w2 < 4; ++w2) a = comp_merge(a, red[w2][0]);
-    bcast[0] = a.hi + a.lo;
-  }
-  __syncthreads();
-  const float a0 = bcast[0];
-  float xs0;
-  const float rest0 = digamma_parts(a0, xs0);
+  lds_order();
 
-  // ---- E = psi(alpha) - psi(alpha_0) as ln(xs / xs0) + (rest - rest0); w = exp(E);
-  //      sE keeps psi(alpha_k) itself for Eq. 8
-  for (int k = tid; k < Mp; k += 256) {
-    float e = 0.0f, w = 0.0f, ps = 0.0f;
-    if (k < M) {
-      float xs;
-      const float rest = digamma_parts(sE[k], xs);
-      ps = logf(xs) + rest;
-      e = logf(xs / xs0) + (rest - rest0);
-      w = expf(e);
+  // ---- tail bins of the next contraction: R = V / Lambda, and their V ln Lambda
+  Comp vl = comp_zero();
+  for (int jt = 0; jt < Ft; ++jt) {
+    const float lam = wave_sum(tacc[jt]);
+    const int l = Fm + jt;
+    const float v = Vin[(size_t)t * Fp + l];
+    const float rr = v > 0.0f ? v / lam : 0.0f;
+    if (v > 0.0f) comp_add(vl, v * logf(lam));
+    if (lane == 0) {
+      if constexpr (kBF16) Rh[(size_t)t * Fp + l] = f2bf(rr);
+      else Rout[(size_t)t * Fp + l] = rr;
     }
-    sE[k] = ps;
-    J.E[row + k] = e;
-    if (J.bf16) J.wh[row + k] = f2bf(w); else J.w[row + k] = w;
   }
-  __syncthreads();
 
   // ---- Eq. 8 up to a per-frame constant: gamma * sum_j psi(alpha_(s,n,j)).  The
   //      term -gamma K psi(alpha_0) is the same for every state of the frame and
   //      changes neither the chain posterior nor the bound, so it is left out.
-  for (int s = wave; s < S; s += 4) {
-    const bool live = lane < N;
+  for (int s = 0; s < S; ++s) {
     float x = -INFINITY;
     if (live) {
       float acc = 0.0f;
@@ -938,26 +1133,39 @@ __global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round
     }
     const float mx = wave_max(x);
     const size_t o = ((size_t)s * T + t) * 64 + lane;
-    J.phi[o] = live ? x : 0.0f;
-    J.ev[o] = live ? expf(x - mx + kEvHeadroomLog) : 0.0f;
-    if (lane == 0) J.sh[(size_t)s * T + t] = mx - kEvHeadroomLog;
+    phi[o] = live ? x : 0.0f;
+    ev[o] = live ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+    if (lane == 0) sh[(size_t)s * T + t] = mx - kEvHeadroomLog;
   }
 
-  // ---- bound contribution of frame t
-  if (mode == kUpdMessages && tid == 0) {
-    Comp tot = red[0][1];
-    for (int w2 = 1; w2 < 4; ++w2) tot = comp_merge(tot, red[w2][1]);
-    comp_add(tot, -lgammaf_pos(a0));
-    for (int w2 = 0; w2 < 4; ++w2) tot = comp_merge(tot, red[w2][2]);
-    for (int w2 = 0; w2 < 4; ++w2) tot = comp_merge(tot, red[w2][3]);
-    for (int r = 0; r < J.nlt; ++r) {
-      const float2 v = J.vll[(size_t)r * T + t];
-      Comp d; d.hi = v.x; d.lo = v.y;
-      tot = comp_merge(tot, d);
-    }
-    const int it = round - J.start_round;
-    J.elbo[(size_t)it * T + t] = make_float2(tot.hi, tot.lo);
+  // ---- bound contribution of frame t:
+  //   sum_k lnG(alpha_k) - lnG(alpha_0) + sum V ln Lambda - sum c ln w
+  //   + sum_s (ln Z_s part - sum_n d (gamma phi))
+  if (msg) {
+    Comp tot = wave_comp(lg);
+    tot = comp_merge(tot, wave_comp(pv));
+    comp_add(tot, -lgamma_from(z0, fast_ln(z0.xs)));
+    tot = comp_merge(tot, chain);
+    comp_add(tot, vtail.x);
+    comp_add(tot, vtail.y);
+    if (lane == 0) elbo[(size_t)it * T + t] = vf2{tot.hi, tot.lo};
   }
+  if (lane == 0 && Ft > 0) vll[(size_t)nst * T + t] = vf2{vl.hi, vl.lo};
+}
+
+__global__ __launch_bounds__(256) NFHMM_UPD_ATTR void k_update(WorkList wl, int mode, int round, int stride) {
+  extern __shared__ float smem[];   // per wave: [Mp] alpha, then psi(alpha); then [S N] d-hat
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int wpb = blockDim.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int t = (b - wl.start[jb]) * wpb + wave;
+  const bool bf16 = J.bf16;
+  if (t >= J.T) return;
+  float *sE = smem + (size_t)wave * stride;
+  if (bf16) update_frame<true>(J, t, lane, sE, mode, round);
+  else update_frame<false>(J, t, lane, sE, mode, round);
 }
 
 // ------------------------------------------------------------------ Section 4
@@ -995,7 +1203,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(WorkList wl) {
   const int row0 = rt * 64, col0 = ct * 64;
   const int kb = s * J.NK, ke = kb + J.NK;
   floatx4 acc[2][2];
-  gemm_nt_f32<true>(J.Wfm, J.Mp, J.Fp, row0, J.c, J.Mp, J.T, col0, kb, ke, acc);
+  gemm_nt_f32<2, 2, true>(J.Wfm, J.Mp, J.Fp, row0, J.c, J.Mp, J.T, col0, kb, ke, acc);
   const Frag f = frag_of(threadIdx.x);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -1095,6 +1303,7 @@ hipError_t launch_pack(const JobDesc &J, hipStream_t st) {
 
 hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st) {
   k_fill_w_ones<<<256, 256, 0, st>>>(J);
+  if (J.Ft > 0) k_tail_ones<<<J.T, 64, 0, st>>>(J);
   return last();
 }
 
@@ -1145,8 +1354,12 @@ hipError_t launch_posterior(const WorkList &post, const WorkList &chains, int nm
   return last();
 }
 
-hipError_t launch_update(const WorkList &wl, int mode, int round, int mp_max, hipStream_t st) {
-  if (wl.total > 0) k_update<<<wl.total, 256, (size_t)mp_max * sizeof(float), st>>>(wl, mode, round);
+int update_stride(int mp_max, int sn_max) { return mp_max + ((sn_max + 3) & ~3); }
+int update_waves(int stride) { return max(1, min(4, 14336 / max(stride, 1))); }
+
+hipError_t launch_update(const WorkList &wl, int mode, int round, int stride, hipStream_t st) {
+  const int wpb = update_waves(stride);
+  if (wl.total > 0) k_update<<<wl.total, 64 * wpb, (size_t)wpb * stride * sizeof(float), st>>>(wl, mode, round, stride);
   return last();
 }
 

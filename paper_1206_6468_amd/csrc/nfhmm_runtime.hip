@@ -15,6 +15,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -93,7 +94,7 @@ Dims dims_of(const nfhmm_problem *p, nfhmm_precision prec) {
 struct Layout {
   size_t V_in, W_in, A_in, pi_in, alpha_init;                // host-input copies
   size_t V, Wfm, Wmf, Wfm_h, Wmf_h, wh, Rh, w, R;
-  size_t alpha, E, c, phi, ev, sh, fwd, bwd, lnz, post, vll, elbo, sep, status, chainflag;
+  size_t alpha, c, phi, ev, sh, fwd, bwd, lnz, post, vll, clw, elbo, sep, status, chainflag;
   size_t out_alpha, out_post, out_sep, out_elbo;              // host-output staging
   size_t total;
 };
@@ -103,7 +104,7 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += (bytes + 255) / 256 * 256; return o; };
   const size_t T = d.T, S = d.S, N = d.N, M = d.M, Mp = d.Mp, F = d.F, Fp = d.Fp;
-  const size_t nlt = (Fp + 63) / 64, it = std::max(d.iters, 1);
+  const size_t nlt = (Fp + 63) / 64 + 1, it = std::max(d.iters, 1);
   const size_t none = ~size_t(0);
   L.V_in = host_in ? take(T * F * 4) : none;
   L.W_in = host_in ? take(M * F * 4) : none;
@@ -120,7 +121,6 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   L.w = d.bf16 ? none : take(T * Mp * 4);
   L.R = d.bf16 ? none : take(T * Fp * 4);
   L.alpha = take(T * Mp * 4);
-  L.E = take(T * Mp * 4);
   L.c = take(T * Mp * 4);
   L.phi = take(S * T * 64 * 4);
   L.ev = take(S * T * 64 * 4);
@@ -130,6 +130,7 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   L.lnz = take(S * 8);
   L.post = take(S * T * N * 4);
   L.vll = take(nlt * T * 8);
+  L.clw = take((Mp + 63) / 64 * T * 8);
   L.elbo = take(it * T * 8);
   L.sep = take(S * T * Fp * 4);
   L.status = take(4);
@@ -250,6 +251,11 @@ void fill_desc(Job &j, float gamma) {
   D.S = d.S; D.N = d.N; D.K = d.K; D.M = d.M; D.Mp = d.Mp; D.F = d.F; D.Fp = d.Fp; D.T = d.T;
   D.NK = d.N * d.K; D.iters = d.iters; D.start_round = j.start_round; D.bf16 = d.bf16 ? 1 : 0;
   D.gamma = gamma; D.nlt = (d.Fp + 63) / 64;
+  const int ftail = d.F % 64;
+  if (d.F >= 64 && ftail >= 1 && ftail <= 4) { D.Fm = d.F - ftail; D.Ft = ftail; }
+  else { D.Fm = d.Fp; D.Ft = 0; }
+  D.nst = (D.Fm + 127) / 128;     // spectrum block tiles are 128 bins high
+  D.nvl = D.nst + (D.Ft > 0 ? 1 : 0);
   const double C = std::lgamma((double)d.M + (double)gamma * d.S * d.K) - (double)d.S * d.K * std::lgamma(1.0 + gamma);
   D.elbo_const = (double)d.T * C;
   if (j.host_in) {
@@ -261,10 +267,11 @@ void fill_desc(Job &j, float gamma) {
   D.V = F32(L.V); D.Wfm = F32(L.Wfm); D.Wmf = F32(L.Wmf);
   D.Wfm_h = U16(L.Wfm_h); D.Wmf_h = U16(L.Wmf_h); D.wh = U16(L.wh); D.Rh = U16(L.Rh);
   D.w = F32(L.w); D.R = F32(L.R);
-  D.alpha = F32(L.alpha); D.E = F32(L.E); D.c = F32(L.c);
+  D.alpha = F32(L.alpha); D.c = F32(L.c);
   D.phi = F32(L.phi); D.ev = F32(L.ev); D.sh = F32(L.sh); D.fwd = F32(L.fwd); D.bwd = F32(L.bwd);
   D.lnz = reinterpret_cast<float2 *>(a + L.lnz); D.post = F32(L.post);
   D.vll = reinterpret_cast<float2 *>(a + L.vll);
+  D.clw = reinterpret_cast<float2 *>(a + L.clw);
   D.elbo = reinterpret_cast<float2 *>(a + L.elbo);
   D.sep = F32(L.sep);
   D.status = reinterpret_cast<int *>(a + L.status);
@@ -282,27 +289,29 @@ void fill_desc(Job &j, float gamma) {
 // ------------------------------------------------------------------ work-list tables
 // One table describes a set of jobs for every launch of a round: the job
 // descriptors and, per launch kind, the prefix sums of blocks per job.
-enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFB, kPost, kChain, kFrames, kRecon, kIters, kNumLists };
+enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFB, kPost, kChain, kUpd, kFrames, kRecon, kIters, kNumLists };
 
 struct Table {
   std::vector<uint64_t> key;
   WorkList lists[kNumLists];
-  int nmax = 1, mpmax = 32;
+  int nmax = 1, mpmax = 32, upd_stride = 32;
   char *dev = nullptr, *host = nullptr;
   size_t cap = 0;
   hipEvent_t ready = nullptr;
 };
 
-int blocks_of(ListKind k, const JobDesc &D, bool bf16) {
-  const int ct = (D.T + 63) / 64;
+int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb) {
+  const int ct = (D.T + 63) / 64;       // 64-frame tiles (reconstruction)
+  const int ct128 = (D.T + 127) / 128;  // 128-frame tiles (the two contractions)
   switch (k) {
-    case kSpecF: return bf16 ? 0 : D.nlt * ct;
-    case kSpecH: return bf16 ? D.nlt * ct : 0;
-    case kCntF: return bf16 ? 0 : ((D.Mp + 63) / 64) * ct;
-    case kCntH: return bf16 ? ((D.Mp + 63) / 64) * ct : 0;
+    case kSpecF: return bf16 ? 0 : D.nst * ct128;
+    case kSpecH: return bf16 ? D.nst * ct128 : 0;
+    case kCntF: return bf16 ? 0 : ((D.Mp + 63) / 64) * ct128;
+    case kCntH: return bf16 ? ((D.Mp + 63) / 64) * ct128 : 0;
     case kFB: return 2 * D.S;
     case kPost: return D.S * ((D.T + 3) / 4);
     case kChain: return D.S;
+    case kUpd: return (D.T + upd_wpb - 1) / upd_wpb;
     case kFrames: return D.T;
     case kRecon: return D.S * D.nlt * ct;
     case kIters: return D.iters;
@@ -317,8 +326,17 @@ struct nfhmm_ctx {
   int device = 0;
   size_t budget = 0;
   int max_slots = 64;
-  hipStream_t stream = nullptr, fb_stream = nullptr, io_stream = nullptr;
+  // Streams: lane 0's pair doubles as the context's own (stream / fb_stream).
+  // HIP maps streams onto a few hardware queues per process (4 by default); the
+  // context creates exactly 2 per lane so that the chain stream of a lane never
+  // shares a queue with that lane's contraction stream.
+  hipStream_t stream = nullptr, fb_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // execution lanes of the blocking engine: jobs are split into groups, each
+  // advancing on its own pair of streams so that groups overlap on the device
+  static constexpr int kMaxGroups = 2;
+  int groups = 2;
+  struct Lane { hipStream_t main, fb; hipEvent_t fork, join, done; } lanes[kMaxGroups] = {};
   std::vector<std::unique_ptr<Table>> tables;   // ring
   size_t table_next = 0;
   std::map<size_t, std::vector<char *>> arena_cache;   // device path: reusable arenas by size
@@ -379,17 +397,20 @@ nfhmm_status get_table(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream
   JobDesc *hd = reinterpret_cast<JobDesc *>(t.host);
   t.nmax = 1;
   t.mpmax = 32;
+  int snmax = 1;
   for (int i = 0; i < n; ++i) {
     hd[i] = jobs[i]->desc;
     t.nmax = std::max(t.nmax, jobs[i]->d.N);
     t.mpmax = std::max(t.mpmax, jobs[i]->d.Mp);
+    snmax = std::max(snmax, jobs[i]->d.S * jobs[i]->d.N);
   }
+  t.upd_stride = update_stride(t.mpmax, snmax);
   for (int k = 0; k < kNumLists; ++k) {
     int *hs = reinterpret_cast<int *>(t.host + desc_bytes + k * list_bytes);
     int acc = 0;
     for (int i = 0; i < n; ++i) {
       hs[i] = acc;
-      acc += blocks_of((ListKind)k, jobs[i]->desc, jobs[i]->d.bf16);
+      acc += blocks_of((ListKind)k, jobs[i]->desc, jobs[i]->d.bf16, update_waves(t.upd_stride));
     }
     hs[n] = acc;
     t.lists[k].jobs = reinterpret_cast<const JobDesc *>(t.dev);
@@ -474,13 +495,13 @@ nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStr
     HIP_OK(launch_spectrum(t->lists[kSpecH], true, st));
     HIP_OK(launch_counts(t->lists[kCntF], false, st));
     HIP_OK(launch_counts(t->lists[kCntH], true, st));
-    HIP_OK(launch_update(t->lists[kFrames], kUpdUniform, 0, t->mpmax, st));
+    HIP_OK(launch_update(t->lists[kUpd], kUpdUniform, 0, t->upd_stride, st));
   }
   if (!warm.empty()) {
     Table *t;
     nfhmm_status s = get_table(ctx, warm, st, &t);
     if (s != NFHMM_OK) return s;
-    HIP_OK(launch_update(t->lists[kFrames], kUpdFromAlpha, 0, t->mpmax, st));
+    HIP_OK(launch_update(t->lists[kUpd], kUpdFromAlpha, 0, t->upd_stride, st));
   }
   return NFHMM_OK;
 }
@@ -517,22 +538,23 @@ struct Timed {
 };
 
 // One iteration of every job in `jobs` (round index `round`).
-nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int round, hipStream_t st) {
+nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int round, hipStream_t st,
+                            hipStream_t fb, hipEvent_t ev_fork, hipEvent_t ev_join) {
   if (jobs.empty()) return NFHMM_OK;
   Table *t;
   nfhmm_status s = get_table(ctx, jobs, st, &t);
   if (s != NFHMM_OK) return s;
-  HIP_OK(hipEventRecord(ctx->ev_fork, st));
-  HIP_OK(hipStreamWaitEvent(ctx->fb_stream, ctx->ev_fork, 0));
+  HIP_OK(hipEventRecord(ev_fork, st));
+  HIP_OK(hipStreamWaitEvent(fb, ev_fork, 0));
   {
-    Timed tm(ctx, NFHMM_K_CHAINS, ctx->fb_stream);
-    HIP_OK(launch_chain_fb(t->lists[kFB], t->nmax, ctx->fb_stream));
+    Timed tm(ctx, NFHMM_K_CHAINS, fb);
+    HIP_OK(launch_chain_fb(t->lists[kFB], t->nmax, fb));
   }
   {
-    Timed tm(ctx, NFHMM_K_POSTERIOR, ctx->fb_stream);
-    HIP_OK(launch_posterior(t->lists[kPost], t->lists[kChain], t->nmax, ctx->fb_stream));
+    Timed tm(ctx, NFHMM_K_POSTERIOR, fb);
+    HIP_OK(launch_posterior(t->lists[kPost], t->lists[kChain], t->nmax, fb));
   }
-  HIP_OK(hipEventRecord(ctx->ev_join, ctx->fb_stream));
+  HIP_OK(hipEventRecord(ev_join, fb));
   {
     Timed tm(ctx, NFHMM_K_SPECTRUM, st);
     HIP_OK(launch_spectrum(t->lists[kSpecF], false, st));
@@ -543,10 +565,10 @@ nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int 
     HIP_OK(launch_counts(t->lists[kCntF], false, st));
     HIP_OK(launch_counts(t->lists[kCntH], true, st));
   }
-  HIP_OK(hipStreamWaitEvent(st, ctx->ev_join, 0));
+  HIP_OK(hipStreamWaitEvent(st, ev_join, 0));
   {
     Timed tm(ctx, NFHMM_K_UPDATE, st);
-    HIP_OK(launch_update(t->lists[kFrames], kUpdMessages, round, t->mpmax, st));
+    HIP_OK(launch_update(t->lists[kUpd], kUpdMessages, round, t->upd_stride, st));
   }
   return NFHMM_OK;
 }
@@ -560,7 +582,9 @@ nfhmm_status engine_finish(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipSt
   return NFHMM_OK;
 }
 
-// Run a fixed set of jobs to completion (all start at round 0).
+// Run a fixed set of jobs to completion (all start at round 0).  After packing
+// and the start (on st), the jobs are dealt into up to ctx->groups groups that
+// each run their rounds on their own lane; st waits for all lanes at the end.
 nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t st) {
   int max_it = 0;
   for (Job *j : jobs) {
@@ -576,14 +600,26 @@ nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t 
   for (Job *j : jobs)
     if (j->d.iters == 0) done0.push_back(j);
   if ((s = engine_finish(ctx, done0, st)) != NFHMM_OK) return s;
+  const int G = std::max(1, std::min<int>(ctx->groups, (int)jobs.size()));
+  std::vector<std::vector<Job *>> grp(G);
+  for (size_t i = 0; i < jobs.size(); ++i) grp[i * G / jobs.size()].push_back(jobs[i]);
+  HIP_OK(hipEventRecord(ctx->ev_fork, st));
+  for (int g = 0; g < G; ++g) HIP_OK(hipStreamWaitEvent(ctx->lanes[g].main, ctx->ev_fork, 0));
   for (int r = 0; r < max_it; ++r) {
-    std::vector<Job *> act, fin;
-    for (Job *j : jobs) {
-      if (r < j->d.iters) act.push_back(j);
-      if (r + 1 == j->d.iters) fin.push_back(j);
+    for (int g = 0; g < G; ++g) {
+      nfhmm_ctx::Lane &ln = ctx->lanes[g];
+      std::vector<Job *> act, fin;
+      for (Job *j : grp[g]) {
+        if (r < j->d.iters) act.push_back(j);
+        if (r + 1 == j->d.iters) fin.push_back(j);
+      }
+      if ((s = engine_iterate(ctx, act, r, ln.main, ln.fb, ln.fork, ln.join)) != NFHMM_OK) return s;
+      if ((s = engine_finish(ctx, fin, ln.main)) != NFHMM_OK) return s;
     }
-    if ((s = engine_iterate(ctx, act, r, st)) != NFHMM_OK) return s;
-    if ((s = engine_finish(ctx, fin, st)) != NFHMM_OK) return s;
+  }
+  for (int g = 0; g < G; ++g) {
+    HIP_OK(hipEventRecord(ctx->lanes[g].done, ctx->lanes[g].main));
+    HIP_OK(hipStreamWaitEvent(st, ctx->lanes[g].done, 0));
   }
   for (Job *j : jobs)
     if (j->host_out && (s = download_outputs(*j, st)) != NFHMM_OK) return s;
@@ -702,7 +738,7 @@ void scheduler(nfhmm_ctx *ctx) {
     }
     const int r = ctx->round;
     std::vector<Job *> fin = zero_iter;
-    if (s == NFHMM_OK) s = engine_iterate(ctx, act, r, st);
+    if (s == NFHMM_OK) s = engine_iterate(ctx, act, r, st, ctx->fb_stream, ctx->ev_fork, ctx->ev_join);
     for (Job *j : act)
       if (r - j->start_round + 1 == j->d.iters) fin.push_back(j);
     if (s == NFHMM_OK) s = engine_finish(ctx, fin, st);
@@ -764,11 +800,18 @@ nfhmm_status nfhmm_create(nfhmm_ctx **out, int device, size_t hbm_budget_bytes, 
   c->device = device;
   c->budget = hbm_budget_bytes;
   c->max_slots = max_slots > 0 ? max_slots : 64;
-  HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-  HIP_OK(hipStreamCreateWithFlags(&c->fb_stream, hipStreamNonBlocking));
-  HIP_OK(hipStreamCreateWithFlags(&c->io_stream, hipStreamNonBlocking));
   HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  if (const char *g = getenv("NFHMM_GROUPS")) c->groups = std::max(1, std::min(nfhmm_ctx::kMaxGroups, atoi(g)));
+  for (auto &ln : c->lanes) {
+    HIP_OK(hipStreamCreateWithFlags(&ln.main, hipStreamNonBlocking));
+    HIP_OK(hipStreamCreateWithFlags(&ln.fb, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&ln.join, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
+  }
+  c->stream = c->lanes[0].main;
+  c->fb_stream = c->lanes[0].fb;
   *out = c.release();
   return NFHMM_OK;
 }
@@ -801,9 +844,13 @@ void nfhmm_destroy(nfhmm_ctx *ctx) {
   }
   (void)hipEventDestroy(ctx->ev_fork);
   (void)hipEventDestroy(ctx->ev_join);
-  (void)hipStreamDestroy(ctx->stream);
-  (void)hipStreamDestroy(ctx->fb_stream);
-  (void)hipStreamDestroy(ctx->io_stream);
+  for (auto &ln : ctx->lanes) {
+    (void)hipEventDestroy(ln.fork);
+    (void)hipEventDestroy(ln.join);
+    (void)hipEventDestroy(ln.done);
+    (void)hipStreamDestroy(ln.main);
+    (void)hipStreamDestroy(ln.fb);
+  }
   delete ctx;
 }
 
