@@ -33,6 +33,21 @@ namespace nfhmm {
 
 constexpr int kLanes = 64;     // states per chain row (wavefront width)
 constexpr int kMaxSources = 8;
+
+// Block tiles of the two contractions: 2 x 2 wavefronts of 16*W rows x 16*W
+// columns each.  Lambda (spectrum): bins x frames; counts: elements x frames.
+#ifndef NFHMM_SPEC_WM
+#define NFHMM_SPEC_WM 4
+#define NFHMM_SPEC_WN 4
+#endif
+#ifndef NFHMM_CNT_WM
+#define NFHMM_CNT_WM 2
+#define NFHMM_CNT_WN 2
+#endif
+constexpr int kSpecWM = NFHMM_SPEC_WM, kSpecWN = NFHMM_SPEC_WN;
+constexpr int kCntWM = NFHMM_CNT_WM, kCntWN = NFHMM_CNT_WN;
+constexpr int kSpecBM = 32 * kSpecWM, kSpecBN = 32 * kSpecWN;
+constexpr int kCntBM = 32 * kCntWM, kCntBN = 32 * kCntWN;
 constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
 
 enum Status : int { kOk = 0, kBadV = 1, kBadW = 2, kNonFinite = 4 };

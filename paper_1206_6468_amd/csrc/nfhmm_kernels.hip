@@ -389,17 +389,6 @@ __device__ void gemm_nt_bf16(const uint16_t *__restrict__ A, int lda, int arows,
   }
 }
 
-// Block tiles of the two contractions (wave tile = 16*W rows x 16*W columns).
-#ifndef NFHMM_SPEC_WM
-#define NFHMM_SPEC_WM 4
-#define NFHMM_SPEC_WN 4
-#endif
-#ifndef NFHMM_CNT_WM
-#define NFHMM_CNT_WM 2
-#define NFHMM_CNT_WN 4
-#endif
-constexpr int kSpecWM = NFHMM_SPEC_WM, kSpecWN = NFHMM_SPEC_WN;   // Lambda: bins x frames
-constexpr int kCntWM = NFHMM_CNT_WM, kCntWN = NFHMM_CNT_WN;       // counts: elements x frames
 
 // ------------------------------------------------------------------ Eq. 7: Lambda, R
 // Rows l (frequency, [0, Fm)), columns t (frames), k over all M elements.
@@ -979,7 +968,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
   Comp chain = comp_zero();
   if (msg) {
     if (Ft > 0) vtail = vll[(size_t)nst * T + t];
-    const int nkt = (Mp + 63) / 64;
+    const int nkt = (Mp + kCntBM - 1) / kCntBM;
     for (int r = lane; r < nst; r += 64) {
       const vf2 v = vll[(size_t)r * T + t];
       Comp d; d.hi = v.x; d.lo = v.y;

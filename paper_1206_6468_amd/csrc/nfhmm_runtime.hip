@@ -130,7 +130,7 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   L.lnz = take(S * 8);
   L.post = take(S * T * N * 4);
   L.vll = take(nlt * T * 8);
-  L.clw = take((Mp + 63) / 64 * T * 8);
+  L.clw = take((Mp + kCntBM - 1) / kCntBM * T * 8);
   L.elbo = take(it * T * 8);
   L.sep = take(S * T * Fp * 4);
   L.status = take(4);
@@ -254,7 +254,7 @@ void fill_desc(Job &j, float gamma) {
   const int ftail = d.F % 64;
   if (d.F >= 64 && ftail >= 1 && ftail <= 4) { D.Fm = d.F - ftail; D.Ft = ftail; }
   else { D.Fm = d.Fp; D.Ft = 0; }
-  D.nst = (D.Fm + 127) / 128;     // spectrum block tiles are 128 bins high
+  D.nst = (D.Fm + kSpecBM - 1) / kSpecBM;   // spectrum row tiles
   D.nvl = D.nst + (D.Ft > 0 ? 1 : 0);
   const double C = std::lgamma((double)d.M + (double)gamma * d.S * d.K) - (double)d.S * d.K * std::lgamma(1.0 + gamma);
   D.elbo_const = (double)d.T * C;
@@ -302,12 +302,13 @@ struct Table {
 
 int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb) {
   const int ct = (D.T + 63) / 64;       // 64-frame tiles (reconstruction)
-  const int ct128 = (D.T + 127) / 128;  // 128-frame tiles (the two contractions)
+  const int spec = D.nst * ((D.T + kSpecBN - 1) / kSpecBN);
+  const int cnt = ((D.Mp + kCntBM - 1) / kCntBM) * ((D.T + kCntBN - 1) / kCntBN);
   switch (k) {
-    case kSpecF: return bf16 ? 0 : D.nst * ct128;
-    case kSpecH: return bf16 ? D.nst * ct128 : 0;
-    case kCntF: return bf16 ? 0 : ((D.Mp + 63) / 64) * ct128;
-    case kCntH: return bf16 ? ((D.Mp + 63) / 64) * ct128 : 0;
+    case kSpecF: return bf16 ? 0 : spec;
+    case kSpecH: return bf16 ? spec : 0;
+    case kCntF: return bf16 ? 0 : cnt;
+    case kCntH: return bf16 ? cnt : 0;
     case kFB: return 2 * D.S;
     case kPost: return D.S * ((D.T + 3) / 4);
     case kChain: return D.S;
