@@ -13,7 +13,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -27,24 +26,18 @@ PEAK_BF16_MFMA = 2.5e15       # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12             # B/s
 
 
-def _kernel_source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1206_6468_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
-    return h.hexdigest()[:16]
-
-
 def _traffic_for(kernel, workload):
-    """Measured HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel sources; else None."""
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
+    a plain copy) from the committed counter record, if it was taken on the
+    current kernel sources and this workload; else None."""
+    from paper_1206_6468_amd.rocprof_summary import kernel_source_hash
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     try:
-        d = json.load(open(path))
+        with open(path) as f:
+            d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != _kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash():
         return None
     e = d.get("kernels", {}).get(kernel, {})
     if e.get("workload") != workload:
@@ -87,6 +80,92 @@ def time_batch(L, ctx, jobs, precision, steps, warmup, profile=False):
     return dt, prof
 
 
+def _gen4(j):
+    from gen import make_problem
+    return make_problem(4, j)
+
+
+def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
+    """Serving form: n_jobs config-4 jobs (S in {2,3}, T in [200, 4000], 50
+    iterations, BF16 contraction) through nfhmm_submit / nfhmm_wait on a context
+    with a device-memory budget.  First all jobs at once (saturated throughput),
+    then Poisson arrivals at `load` x the saturated job rate (latency from the
+    scheduled arrival to the outputs in host memory), then the same jobs one at a
+    time with nfhmm_fit in FP32 as the sequential baseline."""
+    import threading
+    from multiprocessing import Pool
+
+    import numpy as np
+
+    log(f"serving: generating {n_jobs} config-4 problems")
+    with Pool(min(16, os.cpu_count() or 1)) as pool:
+        probs = pool.map(_gen4, range(n_jobs))
+    work = sum(p["T"] * p["iters"] for p in probs)
+    ctx = L.Context(0, hbm_budget_bytes=budget_bytes, max_slots=max_slots)
+    try:
+        L.wait(ctx, L.submit(ctx, dict(probs[0], iters=2), "bf16"))    # warm-up
+
+        log("serving: saturated (all jobs queued at once)")
+        t0 = time.perf_counter()
+        subs = [L.submit(ctx, p, "bf16") for p in probs]
+        lat_sat = [L.wait(ctx, s)[1] for s in subs]
+        t_sat = time.perf_counter() - t0
+        rate = load * n_jobs / t_sat
+
+        log(f"serving: Poisson arrivals at {rate:.1f} jobs/s")
+        rng = np.random.default_rng(seed)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
+        lags, subs = [None] * n_jobs, [None] * n_jobs
+        ready = [threading.Event() for _ in range(n_jobs)]
+
+        def submitter(t_start):
+            for j, a in enumerate(arrivals):
+                d = t_start + a - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                subs[j] = L.submit(ctx, probs[j], "bf16")
+                lags[j] = time.perf_counter() - (t_start + a)
+                ready[j].set()
+
+        t_start = time.perf_counter()
+        th = threading.Thread(target=submitter, args=(t_start,))
+        th.start()
+        lat = []
+        for j in range(n_jobs):
+            ready[j].wait()
+            lat.append(lags[j] + L.wait(ctx, subs[j])[1])
+        t_end = time.perf_counter()
+        th.join()
+        lat_ms = np.array(lat) * 1e3
+    finally:
+        ctx.close()
+
+    log("serving: sequential FP32 baseline (one job at a time)")
+    ctx = L.Context(0)
+    try:
+        L.fit(ctx, dict(probs[0], iters=2), "fp32")
+        t0 = time.perf_counter()
+        for p in probs:
+            L.fit(ctx, p, "fp32")
+        t_seq = time.perf_counter() - t0
+    finally:
+        ctx.close()
+    return {
+        "jobs": n_jobs, "precision": "bf16", "budget_bytes": budget_bytes, "max_slots": max_slots,
+        "frame_iterations": work,
+        "saturated": {"seconds": t_sat, "jobs_per_s": n_jobs / t_sat, "frame_iterations_per_s": work / t_sat,
+                      "p50_ms": float(np.percentile(np.array(lat_sat) * 1e3, 50)),
+                      "p99_ms": float(np.percentile(np.array(lat_sat) * 1e3, 99))},
+        "poisson": {"load": load, "rate_jobs_per_s": rate, "seconds": t_end - t_start,
+                    "frame_iterations_per_s": work / (t_end - t_start),
+                    "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                    "mean_ms": float(lat_ms.mean()), "max_submit_lag_ms": float(max(lags) * 1e3)},
+        "sequential_fp32": {"seconds": t_seq, "frame_iterations_per_s": work / t_seq,
+                            "mean_job_ms": t_seq / n_jobs * 1e3},
+        "note": "latency = scheduled arrival -> outputs in host memory (includes host<->device copies)",
+    }
+
+
 def cpu_baseline(seconds_target=15.0):
     """The FP64 oracle on the host cores: one config-1 job, one warm-up iteration,
     then iterations until about `seconds_target` seconds have passed."""
@@ -125,6 +204,9 @@ def main():
     ap.add_argument("--jobs", type=int, default=32, help="concurrent config-1 jobs per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the BF16 and single-job forms")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving (config 4) measurement")
+    ap.add_argument("--serving-jobs", type=int, default=256)
+    ap.add_argument("--serving-budget-gib", type=float, default=2.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
@@ -209,6 +291,8 @@ def main():
         "roofline": roofline,
     }
     out.update(extra)
+    if not args.no_serving:
+        out["serving"] = serving(L, args.serving_jobs, int(args.serving_budget_gib * (1 << 30)), 64)
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline()

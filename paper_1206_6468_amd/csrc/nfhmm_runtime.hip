@@ -229,6 +229,7 @@ struct Job {
   Layout L{};
   char *arena = nullptr;
   size_t arena_bytes = 0;
+  size_t charged = 0;         // bytes counted against the serving budget while admitted
   JobDesc desc{};
   nfhmm_status status = NFHMM_OK;
   std::string error;
@@ -665,7 +666,8 @@ void finish_job_locked(nfhmm_ctx *ctx, Job *j, nfhmm_status st, const std::strin
   j->error = err;
   j->state = kDone;
   j->t_done = now_s();
-  ctx->bytes_in_use -= j->arena ? j->arena_bytes : 0;
+  ctx->bytes_in_use -= j->charged;
+  j->charged = 0;
 }
 
 void scheduler(nfhmm_ctx *ctx) {
@@ -696,7 +698,8 @@ void scheduler(nfhmm_ctx *ctx) {
         if (adm[i] == 1) admitted.push_back(ctx->queue[i]);
       for (Job *j : admitted) {
         ctx->queue.erase(std::find(ctx->queue.begin(), ctx->queue.end(), j));
-        ctx->bytes_in_use += j->L.total;
+        j->charged = j->L.total;
+        ctx->bytes_in_use += j->charged;
       }
     }
     // allocate and start the admitted jobs

@@ -1,0 +1,163 @@
+"""Summaries of rocprofv3 output for the committed profile records.
+
+Reads the SQLite databases rocprofv3 writes (``*_results.db``) and produces
+short text records:
+
+  kernels   per-kernel dispatch statistics of a ``--kernel-trace --stats`` run
+            (calls, total and average duration, share of GPU time);
+  traffic   HBM bytes per dispatch from two ``--pmc`` runs (FETCH_SIZE, then
+            WRITE_SIZE) of the benchmark, each scaled by what the same counter
+            reads for a plain device copy of known size (two more runs of
+            ``bench.py --copy-calibration``).
+
+The traffic record carries a hash of the kernel sources so that a reader can
+tell whether it still describes the kernels in the tree.
+
+    python -m paper_1206_6468_amd.rocprof_summary kernels DB --command CMD --out FILE.md
+    python -m paper_1206_6468_amd.rocprof_summary traffic --fetch DB --write DB \
+        --copy-fetch DB --copy-write DB --workload NAME --commands CMD... --out FILE.json
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import re
+import sqlite3
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 prefix over the HIP sources and headers of the library."""
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(full: str) -> str:
+    """'void nfhmm::k_counts<false>(nfhmm::WorkList)' -> 'k_counts';
+    the BF16 instantiation (template argument true) gets a '_bf16' suffix;
+    the forward-backward keeps its state-count argument ('k_chain_fb<40>')."""
+    m = re.search(r"nfhmm::(\w+)(<([^>]*)>)?\(", full)
+    if not m:
+        return full
+    base, targ = m.group(1), m.group(3)
+    if targ is None:
+        return base
+    if targ in ("true", "false"):
+        return base + ("_bf16" if targ == "true" else "")
+    return f"{base}<{targ}>"
+
+
+def _db(path: str) -> str:
+    if os.path.isdir(path):
+        found = sorted(glob.glob(os.path.join(path, "**", "*_results.db"), recursive=True))
+        if not found:
+            raise FileNotFoundError(f"no *_results.db under {path}")
+        return found[0]
+    return path
+
+
+def kernel_stats(db: str):
+    con = sqlite3.connect(_db(db))
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    agent = con.execute("select * from rocpd_info_agent where type = 'GPU' limit 1").fetchone()
+    cols = [d[0] for d in con.execute("select * from rocpd_info_agent limit 1").description]
+    info = dict(zip(cols, agent)) if agent else {}
+    return rows, info
+
+
+def counter_per_kernel(db: str, counter: str):
+    con = sqlite3.connect(_db(db))
+    acc = defaultdict(list)
+    for name, val in con.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                                 (counter,)):
+        acc[name].append(float(val))
+    return acc
+
+
+def cmd_kernels(a):
+    rows, info = kernel_stats(a.db)
+    lines = [f"# Kernel dispatch statistics: {a.title}", "",
+             f"Command (run from /tmp with TMPDIR=/tmp; `$R` is the repository root):", "",
+             f"    {a.command}", "",
+             f"GPU: {info.get('product_name', info.get('name', '?'))}; "
+             f"kernel sources {kernel_source_hash()}.", "",
+             "| kernel | calls | total ms | average us | share of GPU time |",
+             "|---|---:|---:|---:|---:|"]
+    for name, calls, total, avg, pct in rows:
+        lines.append(f"| `{short_name(name)}` | {calls} | {total / 1e6:.3f} | {avg / 1e3:.2f} | {pct:.1f}% |")
+    if a.note:
+        lines += ["", a.note]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {a.out}")
+
+
+def cmd_traffic(a):
+    fetch = counter_per_kernel(a.fetch, "FETCH_SIZE")
+    write = counter_per_kernel(a.write, "WRITE_SIZE")
+    cf = counter_per_kernel(a.copy_fetch, "FETCH_SIZE")
+    cw = counter_per_kernel(a.copy_write, "WRITE_SIZE")
+    copy_bytes = a.copy_bytes
+
+    def copy_factor(d):
+        # the copy dispatches are the ones that move about copy_bytes
+        vals = [v for vs in d.values() for v in vs if v * 1024 > 0.25 * copy_bytes]
+        if not vals:
+            raise SystemExit("no copy-sized dispatch found in the calibration run")
+        return copy_bytes / (1024 * sum(vals) / len(vals)), len(vals)
+
+    f_fac, nf = copy_factor(cf)
+    w_fac, nw = copy_factor(cw)
+    kernels = {}
+    for full in sorted(set(fetch) | set(write)):
+        fv, wv = fetch.get(full, []), write.get(full, [])
+        if not fv or not wv:
+            continue
+        fk, wk = sum(fv) / len(fv), sum(wv) / len(wv)
+        kernels[short_name(full)] = {
+            "workload": a.workload, "dispatches": len(fv),
+            "fetch_kib_per_dispatch": fk, "write_kib_per_dispatch": wk,
+            "fetch_bytes_per_launch": fk * 1024 * f_fac, "write_bytes_per_launch": wk * 1024 * w_fac,
+            "bytes_per_launch": fk * 1024 * f_fac + wk * 1024 * w_fac,
+        }
+    out = {"kernel_source_hash": kernel_source_hash(), "workload": a.workload,
+           "calibration": {"copy_bytes": copy_bytes, "fetch_scale": f_fac, "write_scale": w_fac,
+                           "copy_dispatches": [nf, nw]},
+           "commands": a.commands, "kernels": kernels}
+    with open(a.out, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"wrote {a.out}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("db")
+    k.add_argument("--command", required=True)
+    k.add_argument("--title", default="")
+    k.add_argument("--note", default="")
+    k.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    for n in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + n.replace("_", "-"), dest=n, required=True)
+    t.add_argument("--copy-bytes", type=float, default=float(256 << 20))
+    t.add_argument("--workload", required=True)
+    t.add_argument("--commands", nargs="+", required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    cmd_kernels(a) if a.what == "kernels" else cmd_traffic(a)
+
+
+if __name__ == "__main__":
+    main()

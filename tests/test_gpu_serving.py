@@ -1,0 +1,100 @@
+"""The serving loop (nfhmm_submit / poll / wait / cancel) on the GPU.
+
+Jobs of different lengths and source counts are submitted while others are
+resident; the context's device-memory budget is set so that admission has to
+queue.  Each job's result must equal the same job run alone (nfhmm_fit, same
+precision) -- bitwise, since every kernel computes a job's values from that
+job's data only, in the same order, whatever else shares the launch.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from gen import make_problem, make_tiny
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1206_6468_amd import nfhmm
+    return nfhmm
+
+
+def _mix():
+    return [
+        dict(make_problem(0, 20), iters=6),
+        dict(make_tiny(S=3, N=4, K=3, F=70, T=150, seed=21, quanta=900), iters=5),
+        dict(make_problem(0, 21), iters=3),
+        dict(make_tiny(S=1, N=7, K=2, F=33, T=57, seed=22, quanta=500), iters=8),
+        dict(make_tiny(S=2, N=5, K=4, F=129, T=300, seed=23, quanta=2000), iters=4),
+        dict(make_problem(0, 22), iters=1),
+    ]
+
+
+def _same(a, b):
+    for k in ("alpha", "post", "sep", "elbo"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_serving_results_equal_alone(L, precision):
+    probs = _mix()
+    alone_ctx = L.Context(0)
+    alone = [L.fit(alone_ctx, p, precision) for p in probs]
+    alone_ctx.close()
+    fps = [L.footprint_bytes(p, precision) for p in probs]
+    budget = sorted(fps)[-1] + sorted(fps)[-2]          # at most about two resident jobs
+    ctx = L.Context(0, hbm_budget_bytes=budget, max_slots=3)
+    try:
+        subs = [L.submit(ctx, p, precision) for p in probs[:3]]
+        # the rest arrive while the first ones are resident
+        time.sleep(0.002)
+        subs += [L.submit(ctx, p, precision) for p in probs[3:]]
+        lat = []
+        for s, a in zip(subs, alone):
+            out, t = L.wait(ctx, s)
+            lat.append(t)
+            _same(out, a)
+        assert all(t > 0 for t in lat)
+    finally:
+        ctx.close()
+
+
+def test_serving_poll_and_cancel(L):
+    ctx = L.Context(0, max_slots=2)
+    try:
+        long_job = dict(make_problem(0, 30), iters=400)
+        short = dict(make_problem(0, 31), iters=2)
+        a = L.submit(ctx, long_job, "fp32")
+        b = L.submit(ctx, short, "fp32")
+        L.cancel(ctx, a)
+        st, _, _ = L.wait_status(ctx, a)
+        assert st == L.E_CANCELLED
+        out, _ = L.wait(ctx, b)
+        ref = L.fit(ctx, short, "fp32")
+        _same(out, ref)
+        c = L.submit(ctx, short, "fp32")
+        while not L.poll(ctx, c):
+            time.sleep(0.001)
+        out, _ = L.wait(ctx, c)
+        _same(out, ref)
+    finally:
+        ctx.close()
+
+
+def test_serving_rejects_job_over_budget(L):
+    p = make_problem(0, 32)
+    ctx = L.Context(0, hbm_budget_bytes=L.footprint_bytes(p, "fp32") // 2)
+    try:
+        with pytest.raises(L.NfhmmError) as e:
+            L.submit(ctx, p, "fp32")
+        assert e.value.status == L.E_NOMEM
+        bad = dict(p, V=p["V"].copy())
+        bad["V"][0, 0] = -1.0
+        with pytest.raises(L.NfhmmError) as e:
+            L.submit(ctx, bad, "fp32")
+        assert e.value.status == L.E_INVALID
+    finally:
+        ctx.close()
