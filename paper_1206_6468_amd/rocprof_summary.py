@@ -67,12 +67,14 @@ def _db(path: str) -> str:
 
 
 def kernel_stats(db: str):
+    """[(name, calls, total ns, average ns, share)] by total time, and the GPU's name."""
     con = sqlite3.connect(_db(db))
-    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
-    agent = con.execute("select * from rocpd_info_agent where type = 'GPU' limit 1").fetchone()
-    cols = [d[0] for d in con.execute("select * from rocpd_info_agent limit 1").description]
-    info = dict(zip(cols, agent)) if agent else {}
-    return rows, info
+    rows = con.execute("select name, count(*), sum(duration), avg(duration) from kernels "
+                       "group by name order by sum(duration) desc").fetchall()
+    tot = sum(r[2] for r in rows) or 1
+    rows = [(n, c, t, a, 100.0 * t / tot) for n, c, t, a in rows]
+    gpu = con.execute("select name from rocpd_info_agent where type = 'GPU' limit 1").fetchone()
+    return rows, (gpu[0] if gpu else "?")
 
 
 def counter_per_kernel(db: str, counter: str):
@@ -85,16 +87,15 @@ def counter_per_kernel(db: str, counter: str):
 
 
 def cmd_kernels(a):
-    rows, info = kernel_stats(a.db)
+    rows, gpu = kernel_stats(a.db)
     lines = [f"# Kernel dispatch statistics: {a.title}", "",
              f"Command (run from /tmp with TMPDIR=/tmp; `$R` is the repository root):", "",
              f"    {a.command}", "",
-             f"GPU: {info.get('product_name', info.get('name', '?'))}; "
-             f"kernel sources {kernel_source_hash()}.", "",
+             f"GPU: {gpu}; kernel sources {kernel_source_hash()}.", "",
              "| kernel | calls | total ms | average us | share of GPU time |",
              "|---|---:|---:|---:|---:|"]
     for name, calls, total, avg, pct in rows:
-        lines.append(f"| `{short_name(name)}` | {calls} | {total / 1e6:.3f} | {avg / 1e3:.2f} | {pct:.1f}% |")
+        lines.append(f"| `{short_name(name)}` | {calls} | {total / 1e6:.3f} | {avg / 1e3:.1f} | {pct:.1f}% |")
     if a.note:
         lines += ["", a.note]
     with open(a.out, "w") as f:
@@ -137,6 +138,23 @@ def cmd_traffic(a):
     with open(a.out, "w") as f:
         json.dump(out, f, indent=1)
     print(f"wrote {a.out}")
+    if a.md:
+        lines = [f"# HBM traffic per launch: {a.workload}", "",
+                 "Commands (run from /tmp with TMPDIR=/tmp; `$R` is the repository root):", ""]
+        lines += [f"    {c}" for c in a.commands]
+        lines += ["", f"Kernel sources {out['kernel_source_hash']}.  Calibration: a {copy_bytes / 2**20:.0f} MiB "
+                  f"device copy reads FETCH_SIZE x {f_fac:.4f} and WRITE_SIZE x {w_fac:.4f} of its true bytes; "
+                  "the figures below are scaled by those factors.", "",
+                  "| kernel | dispatches | fetched MB / launch | written MB / launch | total MB / launch |",
+                  "|---|---:|---:|---:|---:|"]
+        for name, e in sorted(kernels.items(), key=lambda kv: -kv[1]["bytes_per_launch"] * kv[1]["dispatches"]):
+            if e["bytes_per_launch"] * e["dispatches"] < 1e6:
+                continue
+            lines.append(f"| `{name}` | {e['dispatches']} | {e['fetch_bytes_per_launch'] / 1e6:.1f} | "
+                         f"{e['write_bytes_per_launch'] / 1e6:.1f} | {e['bytes_per_launch'] / 1e6:.1f} |")
+        with open(a.md, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print(f"wrote {a.md}")
 
 
 def main():
@@ -155,6 +173,7 @@ def main():
     t.add_argument("--workload", required=True)
     t.add_argument("--commands", nargs="+", required=True)
     t.add_argument("--out", required=True)
+    t.add_argument("--md", default="", help="also write a markdown table here")
     a = ap.parse_args()
     cmd_kernels(a) if a.what == "kernels" else cmd_traffic(a)
 
