@@ -334,10 +334,12 @@ struct nfhmm_ctx {
   // shares a queue with that lane's contraction stream.
   hipStream_t stream = nullptr, fb_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // execution lanes of the blocking engine: jobs are split into groups, each
-  // advancing on its own pair of streams so that groups overlap on the device
+  // execution lanes of the blocking engine: jobs can be split into groups, each
+  // advancing on its own pair of streams so that groups overlap on the device.
+  // One group is the default: a batch then shares every launch, and a kernel's
+  // launch time is its own (with two groups the lanes' launches share the chip).
   static constexpr int kMaxGroups = 2;
-  int groups = 2;
+  int groups = 1;
   struct Lane { hipStream_t main, fb; hipEvent_t fork, join, done; } lanes[kMaxGroups] = {};
   std::vector<std::unique_ptr<Table>> tables;   // ring
   size_t table_next = 0;
