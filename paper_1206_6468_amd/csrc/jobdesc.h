@@ -50,6 +50,19 @@ constexpr int kSpecBM = 32 * kSpecWM, kSpecBN = 32 * kSpecWN;
 constexpr int kCntBM = 32 * kCntWM, kCntBN = 32 * kCntWN;
 constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
 
+// Chunks of the time-parallel forward-backward: about kFbChunk frames each, at
+// most kFbMaxChunks per chain.  A job's chunking depends on its T only, so its
+// results do not depend on what else runs beside it.
+constexpr int kFbChunk = 64;
+constexpr int kFbMaxChunks = 256;
+inline void fb_geometry(int T, int *C, int *L) {
+  int c = (T + kFbChunk - 1) / kFbChunk;
+  c = c < 1 ? 1 : (c > kFbMaxChunks ? kFbMaxChunks : c);
+  const int l = (T + c - 1) / c;
+  *L = l;
+  *C = (T + l - 1) / l;
+}
+
 enum Status : int { kOk = 0, kBadV = 1, kBadW = 2, kNonFinite = 4 };
 
 struct JobDesc {
@@ -64,6 +77,7 @@ struct JobDesc {
   int Ft;            // tail bins [Fm, F) handled outside the MFMA tiles (0..4)
   int nst;           // ceil(Fm / 128): row tiles of the spectrum contraction
   int nvl;           // slots of vll: nst, plus one for the tail
+  int fbC, fbL;      // chunks of the forward-backward and frames per chunk
   double elbo_const; // T * (lnG(M + gamma S K) - S K lnG(1 + gamma))
   // inputs in the ABI layouts (device)
   const float *V_in, *W_in, *A_in, *pi_in, *alpha_init;
@@ -73,6 +87,8 @@ struct JobDesc {
   float *alpha, *w, *R, *c;
   float *phi, *ev, *sh, *fwd, *bwd, *post;
   float2 *vll, *clw, *elbo, *lnz;
+  float *bnd;        // boundary messages of the chunked sweep [S][2][4][fbC][64]
+  float2 *bgain;     // forward log gains of the chunks [S][2 rounds][fbC]
   float *sep;
   int *status;
   int *chainflag;    // [S] set when a chain needs the exact log-space pass

@@ -12,7 +12,9 @@ hipError_t launch_pack(const JobDesc &J, hipStream_t st);
 hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st);
 hipError_t launch_spectrum(const WorkList &wl, bool bf16, hipStream_t st);
 hipError_t launch_counts(const WorkList &wl, bool bf16, hipStream_t st);
-hipError_t launch_chain_fb(const WorkList &wl, int nmax, hipStream_t st);
+// Chunked forward-backward: rounds 1 and 2 (one block per source, direction and
+// chunk), then the fix-up (one block per source and direction).
+hipError_t launch_chain_fb(const WorkList &rounds, const WorkList &fixup, int nmax, hipStream_t st);
 // d-hat from the messages (post: one block per source and 4 frames), then the exact
 // log-space pass over flagged chains (chains: one block per source).
 hipError_t launch_posterior(const WorkList &post, const WorkList &chains, int nmax, hipStream_t st);

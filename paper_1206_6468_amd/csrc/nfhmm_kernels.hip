@@ -1,15 +1,17 @@
 // HIP kernels (gfx950) of variational inference in the Bayesian N-FHMM.
 //
-// One iteration of the loop (Section 3.2 of the paper) is four launches:
+// One iteration of the loop (Section 3.2 of the paper):
 //   k_spectrum   Lambda = beta w,  R = V / Lambda, partials of sum V ln Lambda
 //                (the normaliser kappa = ln Lambda of Eq. 7)            [MFMA]
 //   k_counts     c = w (.) beta^T R: sum_l V z, the first term of Eq. 6 [MFMA]
-//   k_chain_fb   forward and backward recursions of every source chain on the
-//                evidence of Eq. 8 (one wavefront per chain and direction)
-//   k_update     d-hat from the messages, Eq. 6, then psi / E / w / Eq. 8 for
-//                the next iteration, and the per-frame bound contributions
-// k_chain_fb runs on its own stream beside k_spectrum -> k_counts: given the
-// current alpha-hat the chains and the contractions do not depend on each other.
+//   k_fb_round (x2), k_fb_fixup
+//                forward and backward recursions of every source chain on the
+//                evidence of Eq. 8, swept in parallel over chunks of frames
+//   k_posterior  d-hat from the messages (k_chain_exact where flagged)
+//   k_update     Eq. 6, then psi / w / Eq. 8 for the next iteration, and the
+//                per-frame bound contributions
+// The chain kernels run on their own stream beside k_spectrum -> k_counts: given
+// the current alpha-hat the chains and the contractions do not depend on each other.
 //
 // Z-hat of Eq. 7 is never formed: z[t,l,k] = beta[l,k] w[t,k] / Lambda[l,t]
 // with w = exp(psi(alpha_tk) - psi(alpha_t0)), so sum_l V z is c[t,k] above.
@@ -542,13 +544,13 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
 }
 
 // ------------------------------------------------------------------ forward-backward
-// One 64-lane wavefront per (job, source, direction).  Lane n < N owns state n.
-// Messages are linear vectors with per-frame log offsets (the scaled recursion of
-// Rabiner's tutorial, which the paper cites): the evidence row of frame t is
-// ev = exp(gamma*phi - sh_t) <= 2^64, each message is rescaled by the power of
-// two 2^-k_t that brings its normaliser into [1/2, 1), and
-//   ln Z = sum_t sh_t + lnz,   lnz = ln sum_n u_{T-1}(n) + ln 2 * sum_t k_t,
-// so the bookkeeping is exact integer arithmetic.
+// One 64-lane wavefront per (job, source, direction, chunk).  Lane n < N owns
+// state n.  Messages are linear vectors with per-frame log offsets (the scaled
+// recursion of Rabiner's tutorial, which the paper cites): the evidence row of
+// frame t is ev = exp(gamma*phi - sh_t) <= 2^64, and each message is rescaled by
+// the power of two 2^-k_t that brings its normaliser into [1/2, 1), so
+//   ln Z = sum_t sh_t + lnz,   lnz = ln sum_n u_{T-1}(n) + ln 2 * sum_t k_t
+// is exact integer bookkeeping.
 // Lane N (the first unused lane) holds one extra row of the transition
 // operator so that the normaliser comes out of the same FMA pass: all ones in
 // the forward direction (sum of the incoming message), the column sums of A in
@@ -556,20 +558,38 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
 // is used instead.
 // The largest entry of every forward message and of every backward message times
 // the evidence is kept above 2^-20: a frame where all of them would fall below is
-// redone in log space with its own shift (recorded in sh for the forward
-// direction).  States that end up more than ~100 nats below a frame's best are
+// redone in log space with its own shift (the forward adds the shift's change to
+// its log gain).  States that end up more than ~100 nats below a frame's best are
 // flushed to zero; k_posterior detects the frames where that could matter and
 // k_chain_exact then recomputes the chain entirely in log space.
 //
-// The sweep runs in blocks of kFbBlock frames whose evidence rows are loaded one
+// Time-parallel sweep.  The T frames are cut into C chunks of L frames:
+//   round 1  every chunk is swept from a uniform start (the first forward chunk
+//            from pi, the last backward chunk from b = 1: both exact);
+//   round 2  every chunk whose round-1 start disagrees with its neighbour's
+//            round-1 end is swept again from that end;
+//   fix-up   one wavefront per chain and direction walks the chunks in order and
+//            sweeps again every chunk whose start disagrees with the final end of
+//            its neighbour, so the result is that of the sequential recursion
+//            whatever the chain's memory.
+// Two boundary messages agree when every state matches to 2^-20 relative, or both
+// lie below 2^-60 of the largest state (where k_posterior's 40-nat check takes
+// over).  A chunk forgets its start geometrically, so after round 2 the fix-up
+// normally sweeps nothing and the critical path is about 2L steps instead of T.
+// Boundary messages are stored with their largest entry scaled by a power of two
+// into [1/2, 1); a forward chunk's log gain G (exponents times ln 2, plus the
+// log-space shifts) is relative to its start, and lnz = sum_c G_c + ln sum_n u_{T-1}.
+//
+// Each sweep runs in blocks of kFbBlock frames whose evidence rows are loaded one
 // block ahead, before that block's message stores, so the waits for the loads
 // never include the stores (stores and loads share one counter on gfx9).
-constexpr float kRescue = 9.5367431640625e-07f;   // 2^-20
+constexpr float kRescue = 9.5367431640625e-07f;      // 2^-20
+constexpr float kChunkTol = 9.5367431640625e-07f;    // 2^-20
+constexpr float kChunkFloor = 8.673617379884035e-19f;  // 2^-60
 #ifndef NFHMM_FB_BLOCK
 #define NFHMM_FB_BLOCK 8
 #endif
 constexpr int kFbBlock = NFHMM_FB_BLOCK;
-
 
 // One recursion step: every lane publishes x through LDS, then forms
 // y = sum_m x_m coef[m]; tot is the normaliser (lane N's row, or a reduction).
@@ -614,27 +634,56 @@ __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&c
   return y;
 }
 
+// Scale a boundary message by the power of two that brings its largest entry into
+// [1/2, 1); returns the exponent removed (0 for a zero or non-finite message).
+__device__ __forceinline__ int canon_msg(float &x, bool live) {
+  const float mx = wave_max(live ? x : 0.0f);
+  if (!(mx > 0.0f && mx < INFINITY)) return 0;
+  const int k = __builtin_amdgcn_frexp_expf(mx);
+  x = ldexpf(x, -k);
+  return k;
+}
+
+// Do two messages agree up to a positive factor?  Each is divided by its largest
+// entry; on agreement lr = ln(max b / max a), the log of the factor that turns a
+// into b (a forward gain measured from a start a then holds from b once lr is
+// added).  Two zero messages agree; a zero and a non-zero one do not.
+__device__ __forceinline__ bool msgs_agree(float a, float b, bool live, float &lr) {
+  const float ma = wave_max(live ? a : 0.0f), mb = wave_max(live ? b : 0.0f);
+  lr = 0.0f;
+  if (!(ma > 0.0f) || !(mb > 0.0f)) return !(ma > 0.0f) && !(mb > 0.0f) && ma == 0.0f && mb == 0.0f;
+  const float an = a / ma, bn = b / mb;
+  const bool ok = !live || fabsf(an - bn) <= kChunkTol * fmaxf(an, bn) + kChunkFloor;
+  lr = logf(mb) - logf(ma);
+  return __ballot(!ok) == 0;
+}
+
+// Forward sweep over frames [t0, t1).  For t0 == 0 it starts from pi; otherwise u
+// is the message of frame t0 - 1.  On return u is the message of frame t1 - 1 and
+// g its log gain relative to the start.
 template <int NR>
-__device__ void chain_forward(const JobDesc &J, int s, const float (&coef)[NR], float *buf) {
-  const int lane = threadIdx.x, N = J.N, T = J.T;
+__device__ void fwd_sweep(const JobDesc &J, int s, const float (&coef)[NR], float *buf, int t0, int t1, float &u,
+                          double &g) {
+  const int lane = threadIdx.x & 63, N = J.N, T = J.T;
   const bool sumlane = N < 64, live = lane < N;
   const gfloat *ev = gptr(J.ev + (size_t)s * T * 64 + lane);
   const gfloat *phi = gptr(J.phi + (size_t)s * T * 64 + lane);
   gfloat *fwd = gptr(J.fwd + (size_t)s * T * 64 + lane);
-  gfloat *sh = gptr(J.sh + (size_t)s * T);
-  const gfloat *pi = gptr(J.pi_in + (size_t)s * N);
+  const gfloat *sh = gptr(J.sh + (size_t)s * T);
   int p = 0, ksum = 0;
-  float u, yr = 0.0f;
-  {
-    const float p0 = live ? pi[lane] : 0.0f;
+  float lam = 0.0f, yr = 0.0f;
+  int t = t0;
+  if (t0 == 0) {
+    const float p0 = live ? J.pi_in[(size_t)s * N + lane] : 0.0f;
     u = p0 * ev[0];
     if (__ballot(live && u > kRescue) == 0) {   // frame 0 in log space
       const float x = live ? logf(p0) + phi[0] : -INFINITY;
       const float mx = wave_max(x);
       u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
-      if (lane == 0) sh[0] = mx - kEvHeadroomLog;
+      lam += (mx - kEvHeadroomLog) - sh[0];
     }
     fwd[0] = u;
+    t = 1;
   }
   // one step at frame t with evidence e; false (yr kept) if the frame needs the rescue
 #define NFHMM_FSTEP(t, e, ok)                                                               \
@@ -651,14 +700,13 @@ __device__ void chain_forward(const JobDesc &J, int s, const float (&coef)[NR], 
       fwd[(size_t)(t) * 64] = u;                                                            \
     }                                                                                       \
   }
-  int t = 1;
-  while (t < T) {
+  while (t < t1) {
     bool ok = true;
-    if (T - t >= 2 * kFbBlock) {
+    if (t1 - t >= 2 * kFbBlock) {
       float ea[kFbBlock], eb[kFbBlock];
 #pragma unroll
       for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)(t + i) * 64];
-      while (ok && T - t >= 2 * kFbBlock) {
+      while (ok && t1 - t >= 2 * kFbBlock) {
 #pragma unroll
         for (int i = 0; i < kFbBlock; ++i) eb[i] = ev[(size_t)(t + kFbBlock + i) * 64];
 #pragma unroll
@@ -669,7 +717,7 @@ __device__ void chain_forward(const JobDesc &J, int s, const float (&coef)[NR], 
         }
         if (!ok) break;
 #pragma unroll
-        for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)min(t + kFbBlock + i, T - 1) * 64];
+        for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)min(t + kFbBlock + i, t1 - 1) * 64];
 #pragma unroll
         for (int i = 0; i < kFbBlock; ++i) {
           NFHMM_FSTEP(t, eb[i], ok);
@@ -686,36 +734,38 @@ __device__ void chain_forward(const JobDesc &J, int s, const float (&coef)[NR], 
       const float x = live ? logf(yr) + phi[(size_t)t * 64] : -INFINITY;
       const float mx = wave_max(x);
       u = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
-      if (lane == 0) sh[t] = mx - kEvHeadroomLog;
+      lam += (mx - kEvHeadroomLog) - sh[t];
       fwd[(size_t)t * 64] = u;
       ++t;
     }
   }
 #undef NFHMM_FSTEP
-  const float last = wave_sum(live ? u : 0.0f);
-  if (lane == 0) {
-    const double z = log((double)last) + 0.69314718055994530942 * (double)ksum;
-    const float hi = (float)z;
-    J.lnz[s] = make_float2(hi, (float)(z - (double)hi));
-  }
+  g = 0.69314718055994530942 * (double)ksum + (double)lam;
 }
 
+// Backward sweep over frames [t0, t1), from t1 - 1 down to t0.  For t1 == T it
+// starts from b_{T-1} = 1; otherwise q is e_{t1} * b_{t1}, the evidence-weighted
+// message of frame t1.  On return q = e_{t0} * b_{t0} (any positive scale).
 template <int NR>
-__device__ void chain_backward(const JobDesc &J, int s, const float (&coef)[NR], float *buf) {
-  const int lane = threadIdx.x, N = J.N, T = J.T;
+__device__ void bwd_sweep(const JobDesc &J, int s, const float (&coef)[NR], float *buf, int t0, int t1, float &q) {
+  const int lane = threadIdx.x & 63, N = J.N, T = J.T;
   const bool sumlane = N < 64, live = lane < N;
   const gfloat *ev = gptr(J.ev + (size_t)s * T * 64 + lane);
   const gfloat *phi = gptr(J.phi + (size_t)s * T * 64 + lane);
   gfloat *bwd = gptr(J.bwd + (size_t)s * T * 64 + lane);
   int p = 0;
-  // b_{T-1} = 1; q = e_{T-1} * b_{T-1}
-  const float bcur = live ? 1.0f : 0.0f;
-  bwd[(size_t)(T - 1) * 64] = bcur;
-  float q = bcur * ev[(size_t)(T - 1) * 64], bb = 0.0f;
-  if (__ballot(live && q > kRescue) == 0) {
-    const float x = live ? phi[(size_t)(T - 1) * 64] : -INFINITY;
-    const float mx = wave_max(x);
-    q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+  float bb = 0.0f;
+  int t = t1 - 1;
+  if (t1 == T) {   // b_{T-1} = 1; q = e_{T-1} * b_{T-1}
+    const float bcur = live ? 1.0f : 0.0f;
+    bwd[(size_t)(T - 1) * 64] = bcur;
+    q = bcur * ev[(size_t)(T - 1) * 64];
+    if (__ballot(live && q > kRescue) == 0) {
+      const float x = live ? phi[(size_t)(T - 1) * 64] : -INFINITY;
+      const float mx = wave_max(x);
+      q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
+    }
+    t = T - 2;
   }
 #define NFHMM_BSTEP(t, e, ok)                                                                \
   {                                                                                          \
@@ -727,14 +777,13 @@ __device__ void chain_backward(const JobDesc &J, int s, const float (&coef)[NR],
     ok = __ballot(live && qn_ > kRescue) != 0;                                               \
     if (ok) q = qn_;                                                                         \
   }
-  int t = T - 2;
-  while (t >= 0) {
+  while (t >= t0) {
     bool ok = true;
-    if (t + 1 >= 2 * kFbBlock) {
+    if (t - t0 + 1 >= 2 * kFbBlock) {
       float ea[kFbBlock], eb[kFbBlock];
 #pragma unroll
       for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)(t - i) * 64];
-      while (ok && t + 1 >= 2 * kFbBlock) {
+      while (ok && t - t0 + 1 >= 2 * kFbBlock) {
 #pragma unroll
         for (int i = 0; i < kFbBlock; ++i) eb[i] = ev[(size_t)(t - kFbBlock - i) * 64];
 #pragma unroll
@@ -745,7 +794,7 @@ __device__ void chain_backward(const JobDesc &J, int s, const float (&coef)[NR],
         }
         if (!ok) break;
 #pragma unroll
-        for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)max(t - kFbBlock - i, 0) * 64];
+        for (int i = 0; i < kFbBlock; ++i) ea[i] = ev[(size_t)max(t - kFbBlock - i, t0) * 64];
 #pragma unroll
         for (int i = 0; i < kFbBlock; ++i) {
           NFHMM_BSTEP(t, eb[i], ok);
@@ -758,7 +807,7 @@ __device__ void chain_backward(const JobDesc &J, int s, const float (&coef)[NR],
       NFHMM_BSTEP(t, e1, ok);
       if (ok) --t;
     }
-    if (!ok) {
+    if (!ok) {   // q = b e underflows at frame t: that frame in log space
       const float x = live ? logf(bb) + phi[(size_t)t * 64] : -INFINITY;
       const float mx = wave_max(x);
       q = (live && mx > -INFINITY) ? expf(x - mx + kEvHeadroomLog) : 0.0f;
@@ -768,36 +817,169 @@ __device__ void chain_backward(const JobDesc &J, int s, const float (&coef)[NR],
 #undef NFHMM_BSTEP
 }
 
+// Lane n's coefficients of the step operator (see chain_apply): column n of A
+// forward (lane N: ones), row n of A backward (lane N: the column sums of A,
+// formed by lane m for column m and then read across).
 template <int NR>
-__global__ __launch_bounds__(64) void k_chain_fb(WorkList wl) {
+__device__ __forceinline__ void chain_coef(const float *A, int N, int lane, bool fwd, float (&coef)[NR]) {
+  const bool live = lane < N;
+  if (fwd) {
+#pragma unroll
+    for (int m = 0; m < NR; ++m) coef[m] = (m < N && live) ? A[(size_t)m * N + lane] : ((m < N && lane == N) ? 1.0f : 0.0f);
+  } else {
+    float colsum = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      coef[i] = (i < N && live) ? A[(size_t)lane * N + i] : 0.0f;
+      if (i < N && live) colsum += A[(size_t)i * N + lane];
+    }
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      const float cs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(colsum), m));
+      if (lane == N && m < N) coef[m] = cs;
+    }
+  }
+}
+
+// Boundary slots of chain s: [dir][slot][chunk][64] with slots 0/1 = round-1
+// start/end and 2/3 = round-2 start/end; forward gains [round][chunk].
+__device__ __forceinline__ float *bnd_of(const JobDesc &J, int s, int dir) {
+  return J.bnd + ((size_t)s * 2 + dir) * 4 * (size_t)J.fbC * 64;
+}
+__device__ __forceinline__ void put_gain(float2 *gp, double g) {
+  const float hi = (float)g;
+  *gp = make_float2(hi, (float)(g - (double)hi));
+}
+
+// Rounds 1 and 2 of the chunked sweep: one wavefront per (job, source, direction,
+// chunk).
+template <int NR>
+__global__ __launch_bounds__(64) void k_fb_round(WorkList wl, int round) {
   const int b = blockIdx.x;
   const int jb = find_job(wl.start, wl.njobs, b);
   const JobDesc &J = wl.jobs[jb];
+  const int C = J.fbC, L = J.fbL, T = J.T, N = J.N;
+  const int local = b - wl.start[jb];
+  const int s = local / (2 * C), rem = local - s * 2 * C;
+  const int dir = rem / C, c = rem - dir * C;
+  const int lane = threadIdx.x;
+  const bool live = lane < N;
+  const int t0 = c * L, t1 = min(T, t0 + L);
+  float *bs = bnd_of(J, s, dir) + lane;
+  float2 *gs = J.bgain + (size_t)s * 2 * C;
+  const bool exact = dir == 0 ? c == 0 : c == C - 1;
+  float x;
+  if (round == 1) {
+    if (dir == 0 && c == 0 && lane == 0) J.chainflag[s] = 0;
+    x = live ? 0.5f : 0.0f;
+  } else {
+    const float in1 = bs[(size_t)c * 64];
+    const float out1 = bs[(size_t)(C + c) * 64];
+    bool keep = exact;
+    x = 0.0f;
+    if (!exact) {
+      x = bs[(size_t)(C + (dir == 0 ? c - 1 : c + 1)) * 64];   // the neighbour's round-1 end
+      float lr;
+      keep = msgs_agree(in1, x, live, lr);
+    }
+    if (keep) {
+      bs[(size_t)(2 * C + c) * 64] = in1;
+      bs[(size_t)(3 * C + c) * 64] = out1;
+      if (dir == 0 && lane == 0) gs[C + c] = gs[c];
+      return;
+    }
+  }
+  const int slot = round == 1 ? 0 : 2;
+  bs[(size_t)(slot * C + c) * 64] = x;
+  __shared__ __attribute__((aligned(16))) float buf[2 * NR];
+  float coef[NR];
+  chain_coef<NR>(J.A_in + (size_t)s * N * N, N, lane, dir == 0, coef);
+  double g = 0.0;
+  if (dir == 0) fwd_sweep<NR>(J, s, coef, buf, t0, t1, x, g);
+  else bwd_sweep<NR>(J, s, coef, buf, t0, t1, x);
+  const int k = canon_msg(x, live);
+  bs[(size_t)((slot + 1) * C + c) * 64] = x;
+  if (dir == 0 && lane == 0) put_gain(gs + (round - 1) * C + c, g + 0.69314718055994530942 * (double)k);
+}
+
+// Fix-up of the chunked sweep: one wavefront per (job, source, direction).  The
+// agreement of every chunk's round-2 start with its neighbour's round-2 end is
+// checked first with all loads in flight; from the first disagreement on, the
+// chunks are walked in order and swept again wherever the start differs from the
+// final end before them.  The forward wavefront also forms lnz.
+template <int NR>
+__global__ __launch_bounds__(64) void k_fb_fixup(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int C = J.fbC, L = J.fbL, T = J.T, N = J.N;
   const int local = b - wl.start[jb];
   const int s = local >> 1, dir = local & 1;
   const int lane = threadIdx.x;
-  const int N = J.N;
   const bool live = lane < N;
-  const float *A = J.A_in + (size_t)s * N * N;
-  __shared__ __attribute__((aligned(16))) float buf[2 * NR];
-  float coef[NR];
-  if (dir == 0) {
+  const float *bs = bnd_of(J, s, dir) + lane;
+  const float2 *gs = J.bgain + (size_t)s * 2 * C + C;   // round-2 gains
+  const float *in2 = bs + (size_t)2 * C * 64, *out2 = bs + (size_t)3 * C * 64;
+  // pass 1: first chunk (in sweep order) whose start disagrees
+  double tot = 0.0;
+  int first = C;
+  for (int i0 = 1; i0 < C && first == C; i0 += kFbBlock) {
+    float a[kFbBlock], e[kFbBlock];
+    float2 gg[kFbBlock];
 #pragma unroll
-    for (int m = 0; m < NR; ++m) coef[m] = (m < N && live) ? A[(size_t)m * N + lane] : ((m < N && lane == N) ? 1.0f : 0.0f);
-    if (lane == 0) J.chainflag[s] = 0;
-    chain_forward<NR>(J, s, coef, buf);
-  } else {
-#pragma unroll
-    for (int m = 0; m < NR; ++m) coef[m] = (m < N && live) ? A[(size_t)lane * N + m] : 0.0f;
-    if (lane == N) {   // column sums of A
-      for (int i = 0; i < N; ++i) {
-        const float *row = A + (size_t)i * N;
-#pragma unroll
-        for (int m = 0; m < NR; ++m)
-          if (m < N) coef[m] += row[m];
-      }
+    for (int i = 0; i < kFbBlock; ++i) {
+      const int i1 = min(i0 + i, C - 1);
+      const int c = dir == 0 ? i1 : C - 1 - i1, cp = dir == 0 ? c - 1 : c + 1;
+      a[i] = in2[(size_t)c * 64];
+      e[i] = out2[(size_t)cp * 64];
+      gg[i] = dir == 0 ? gs[c] : make_float2(0.0f, 0.0f);
     }
-    chain_backward<NR>(J, s, coef, buf);
+#pragma unroll
+    for (int i = 0; i < kFbBlock; ++i) {
+      if (i0 + i >= C || first != C) break;
+      float lr;
+      if (msgs_agree(a[i], e[i], live, lr)) tot += (double)gg[i].x + (double)gg[i].y + (double)lr;
+      else first = i0 + i;
+    }
+  }
+  const int c_first = dir == 0 ? 0 : C - 1;
+  float prev;
+  if (first == C) {
+    prev = out2[(size_t)(dir == 0 ? C - 1 : 0) * 64];
+  } else {
+    // pass 2: walk from the first disagreement
+    __shared__ __attribute__((aligned(16))) float buf[2 * NR];
+    float coef[NR];
+    chain_coef<NR>(J.A_in + (size_t)s * N * N, N, lane, dir == 0, coef);
+    const int cb = dir == 0 ? first - 1 : C - first;   // chunk before the first disagreement
+    prev = out2[(size_t)cb * 64];
+    for (int i = first; i < C; ++i) {
+      const int c = dir == 0 ? i : C - 1 - i;
+      const float a = in2[(size_t)c * 64];
+      float lr;
+      if (i > first && msgs_agree(a, prev, live, lr)) {
+        prev = out2[(size_t)c * 64];
+        if (dir == 0) tot += (double)gs[c].x + (double)gs[c].y + (double)lr;
+        continue;
+      }
+      const int t0 = c * L, t1 = min(T, t0 + L);
+      float x = prev;
+      double g = 0.0;
+      if (dir == 0) fwd_sweep<NR>(J, s, coef, buf, t0, t1, x, g);
+      else bwd_sweep<NR>(J, s, coef, buf, t0, t1, x);
+      g += 0.69314718055994530942 * (double)canon_msg(x, live);
+      tot += g;
+      prev = x;
+    }
+  }
+  if (dir == 0) {
+    const float g0x = gs[c_first].x, g0y = gs[c_first].y;
+    const float last = wave_sum(live ? prev : 0.0f);
+    if (lane == 0) {
+      const double z = tot + (double)g0x + (double)g0y + log((double)last);
+      const float hi = (float)z;
+      J.lnz[s] = make_float2(hi, (float)(z - (double)hi));
+    }
   }
 }
 
@@ -1310,11 +1492,15 @@ hipError_t launch_counts(const WorkList &wl, bool bf16, hipStream_t st) {
   return last();
 }
 
-hipError_t launch_chain_fb(const WorkList &wl, int nmax, hipStream_t st) {
-  if (wl.total <= 0) return last();
+hipError_t launch_chain_fb(const WorkList &rounds, const WorkList &fixup, int nmax, hipStream_t st) {
+  if (rounds.total <= 0) return last();
   const int nr = (nmax + 3) & ~3;
-#define NFHMM_FB_CASE(R) \
-  case R: k_chain_fb<R><<<wl.total, 64, 0, st>>>(wl); break;
+#define NFHMM_FB_CASE(R)                                    \
+  case R:                                                   \
+    k_fb_round<R><<<rounds.total, 64, 0, st>>>(rounds, 1); \
+    k_fb_round<R><<<rounds.total, 64, 0, st>>>(rounds, 2); \
+    k_fb_fixup<R><<<fixup.total, 64, 0, st>>>(fixup);      \
+    break;
   switch (nr) {
     NFHMM_FB_CASE(4) NFHMM_FB_CASE(8) NFHMM_FB_CASE(12) NFHMM_FB_CASE(16)
     NFHMM_FB_CASE(20) NFHMM_FB_CASE(24) NFHMM_FB_CASE(28) NFHMM_FB_CASE(32)

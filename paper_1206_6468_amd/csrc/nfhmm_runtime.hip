@@ -94,7 +94,7 @@ Dims dims_of(const nfhmm_problem *p, nfhmm_precision prec) {
 struct Layout {
   size_t V_in, W_in, A_in, pi_in, alpha_init;                // host-input copies
   size_t V, Wfm, Wmf, Wfm_h, Wmf_h, wh, Rh, w, R;
-  size_t alpha, c, phi, ev, sh, fwd, bwd, lnz, post, vll, clw, elbo, sep, status, chainflag;
+  size_t alpha, c, phi, ev, sh, fwd, bwd, lnz, post, vll, clw, elbo, sep, status, chainflag, bnd, bgain;
   size_t out_alpha, out_post, out_sep, out_elbo;              // host-output staging
   size_t total;
 };
@@ -135,6 +135,10 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   L.sep = take(S * T * Fp * 4);
   L.status = take(4);
   L.chainflag = take(S * 4);
+  int fbC = 1, fbL = 1;
+  fb_geometry((int)T, &fbC, &fbL);
+  L.bnd = take(S * 2 * 4 * (size_t)fbC * 64 * 4);
+  L.bgain = take(S * 2 * (size_t)fbC * 8);
   L.out_alpha = host_out ? take(T * M * 4) : none;
   L.out_post = host_out ? take(S * T * N * 4) : none;
   L.out_sep = host_out ? take(S * T * F * 4) : none;
@@ -277,6 +281,9 @@ void fill_desc(Job &j, float gamma) {
   D.sep = F32(L.sep);
   D.status = reinterpret_cast<int *>(a + L.status);
   D.chainflag = reinterpret_cast<int *>(a + L.chainflag);
+  fb_geometry(d.T, &D.fbC, &D.fbL);
+  D.bnd = F32(L.bnd);
+  D.bgain = reinterpret_cast<float2 *>(a + L.bgain);
   if (j.host_out) {
     D.out_alpha = j.res.alpha ? F32(L.out_alpha) : nullptr;
     D.out_post = j.res.post ? F32(L.out_post) : nullptr;
@@ -290,7 +297,7 @@ void fill_desc(Job &j, float gamma) {
 // ------------------------------------------------------------------ work-list tables
 // One table describes a set of jobs for every launch of a round: the job
 // descriptors and, per launch kind, the prefix sums of blocks per job.
-enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFB, kPost, kChain, kUpd, kFrames, kRecon, kIters, kNumLists };
+enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFBR, kFB, kPost, kChain, kUpd, kFrames, kRecon, kIters, kNumLists };
 
 struct Table {
   std::vector<uint64_t> key;
@@ -310,6 +317,7 @@ int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb) {
     case kSpecH: return bf16 ? spec : 0;
     case kCntF: return bf16 ? 0 : cnt;
     case kCntH: return bf16 ? cnt : 0;
+    case kFBR: return 2 * D.S * D.fbC;
     case kFB: return 2 * D.S;
     case kPost: return D.S * ((D.T + 3) / 4);
     case kChain: return D.S;
@@ -552,7 +560,7 @@ nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int 
   HIP_OK(hipStreamWaitEvent(fb, ev_fork, 0));
   {
     Timed tm(ctx, NFHMM_K_CHAINS, fb);
-    HIP_OK(launch_chain_fb(t->lists[kFB], t->nmax, fb));
+    HIP_OK(launch_chain_fb(t->lists[kFBR], t->lists[kFB], t->nmax, fb));
   }
   {
     Timed tm(ctx, NFHMM_K_POSTERIOR, fb);
@@ -1073,7 +1081,10 @@ nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float
   const size_t o_phi = take(T_ * 64 * 4), o_ev = take(T_ * 64 * 4), o_sh = take(T_ * 4);
   const size_t o_f = take(T_ * 64 * 4), o_b = take(T_ * 64 * 4), o_n = take(T_ * 4), o_p = take(T_ * N * 4);
   const size_t o_flag = take(4);
-  const size_t o_desc = take(sizeof(JobDesc)), o_start = take(6 * sizeof(int));
+  int fbC = 1, fbL = 1;
+  fb_geometry((int)T, &fbC, &fbL);
+  const size_t o_bnd = take((size_t)2 * 4 * fbC * 64 * 4), o_bg = take((size_t)2 * fbC * 8);
+  const size_t o_desc = take(sizeof(JobDesc)), o_start = take(8 * sizeof(int));
   char *a = nullptr;
   HIP_OK(hipMalloc(&a, off));
   std::unique_ptr<char, void (*)(char *)> guard(a, [](char *p) { (void)hipFree(p); });
@@ -1092,20 +1103,24 @@ nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float
   D.lnz = reinterpret_cast<float2 *>(a + o_n);
   D.post = reinterpret_cast<float *>(a + o_p);
   D.chainflag = reinterpret_cast<int *>(a + o_flag);
+  D.fbC = fbC;
+  D.fbL = fbL;
+  D.bnd = reinterpret_cast<float *>(a + o_bnd);
+  D.bgain = reinterpret_cast<float2 *>(a + o_bg);
   const int npost = (int)((T_ + 3) / 4);
-  const int start[6] = {0, 2, 0, npost, 0, 1};    // chain_fb, posterior, exact
+  const int start[8] = {0, 2 * fbC, 0, 2, 0, npost, 0, 1};    // rounds, fix-up, posterior, exact
   HIP_OK(hipMemcpyAsync(a + o_desc, &D, sizeof D, hipMemcpyHostToDevice, st));
   HIP_OK(hipMemcpyAsync(a + o_start, start, sizeof start, hipMemcpyHostToDevice, st));
   HIP_OK(launch_chain_prep(D, reinterpret_cast<const float *>(a + o_lev), st));
-  WorkList wl[3];
-  for (int i = 0; i < 3; ++i) {
+  WorkList wl[4];
+  for (int i = 0; i < 4; ++i) {
     wl[i].jobs = reinterpret_cast<const JobDesc *>(a + o_desc);
     wl[i].start = reinterpret_cast<const int *>(a + o_start) + 2 * i;
     wl[i].njobs = 1;
     wl[i].total = start[2 * i + 1];
   }
-  HIP_OK(launch_chain_fb(wl[0], N, st));
-  HIP_OK(launch_posterior(wl[1], wl[2], N, st));
+  HIP_OK(launch_chain_fb(wl[0], wl[1], N, st));
+  HIP_OK(launch_posterior(wl[2], wl[3], N, st));
   std::vector<float> sh(T_);
   float lnz2[2] = {0.0f, 0.0f};
   if (post) HIP_OK(hipMemcpyAsync(post, a + o_p, T_ * N * 4, hipMemcpyDeviceToHost, st));
