@@ -55,8 +55,10 @@ constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
 // results do not depend on what else runs beside it.
 constexpr int kFbChunk = 64;
 constexpr int kFbMaxChunks = 256;
+int fb_chunk_frames();   // kFbChunk, or the NFHMM_FB_CHUNK environment variable (tuning)
 inline void fb_geometry(int T, int *C, int *L) {
-  int c = (T + kFbChunk - 1) / kFbChunk;
+  const int len = fb_chunk_frames();
+  int c = (T + len - 1) / len;
   c = c < 1 ? 1 : (c > kFbMaxChunks ? kFbMaxChunks : c);
   const int l = (T + c - 1) / c;
   *L = l;

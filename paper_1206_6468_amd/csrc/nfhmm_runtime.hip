@@ -99,6 +99,19 @@ struct Layout {
   size_t total;
 };
 
+}  // namespace
+
+int nfhmm::fb_chunk_frames() {
+  static const int len = [] {
+    const char *e = getenv("NFHMM_FB_CHUNK");
+    const int v = e ? atoi(e) : 0;
+    return v > 0 ? v : kFbChunk;
+  }();
+  return len;
+}
+
+namespace {
+
 Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   Layout L{};
   size_t off = 0;

@@ -116,6 +116,46 @@ def test_chain_posterior_extreme_evidence(L, ctx, N, T, scale):
     assert abs(lnZ - z) <= 1e-5 * abs(z)
 
 
+def _long_memory_chain(kind, N):
+    """Chains that forget their start slowly or never, so that chunks of the
+    time-parallel sweep started from a uniform message end in the wrong place and
+    the fix-up walk has to sweep them again."""
+    if kind == "sticky":          # stays put for ~1e4 frames
+        A = np.full((N, N), 1e-4 / (N - 1))
+        A[np.arange(N), np.arange(N)] = 1.0 - 1e-4
+    elif kind == "cycle":         # deterministic rotation: the start is never forgotten
+        A = np.zeros((N, N))
+        A[np.arange(N), (np.arange(N) + 1) % N] = 1.0
+    else:                         # two weakly coupled blocks
+        A = np.zeros((N, N))
+        h = N // 2
+        A[:h, :h] = 1.0 / h
+        A[h:, h:] = 1.0 / (N - h)
+        A[0, h] = A[h, 0] = 1e-6
+        A /= A.sum(1, keepdims=True)
+    pi = np.linspace(1.0, 2.0, N)
+    pi /= pi.sum()
+    return A.astype(np.float32), pi.astype(np.float32)
+
+
+# The last case's posteriors hang on the evidence of thousands of frames: FP32
+# rounding of the evidence rows accumulates along the chain, and the plain
+# sequential recursion (one chunk) lands on the same 1.5e-5 as the chunked one.
+@pytest.mark.parametrize("kind,N,T,scale,tol", [("sticky", 40, 1000, 0.05, TOL_D), ("cycle", 12, 700, 0.3, TOL_D),
+                                                ("blocks", 40, 1500, 0.1, TOL_D), ("sticky", 8, 4000, 0.02, 2e-5)])
+def test_chain_posterior_long_memory(L, ctx, kind, N, T, scale, tol):
+    """Weak evidence on chains with long memory: the chunk starts of the parallel
+    rounds are wrong and only the sequential fix-up gets the marginals right."""
+    rng = np.random.default_rng(T + N)
+    A, pi = _long_memory_chain(kind, N)
+    logev = (rng.normal(scale=scale, size=(T, N))).astype(np.float32)
+    post, lnZ = L.chain_posterior(ctx, logev, A, pi)
+    d, z = O.forward_backward(logev.astype(np.float64), A.astype(np.float64), pi.astype(np.float64))
+    print(f"\n{kind} N={N} T={T}: max |d| err {np.max(np.abs(post - d)):.2e}, lnZ err {abs(lnZ - z):.2e}")
+    assert np.max(np.abs(post - d)) < tol
+    assert abs(lnZ - z) <= 1e-6 * max(1.0, abs(z)) + 1e-4
+
+
 # ------------------------------------------------------------------ one VI step
 ONE_STEP_CASES = [
     ("cfg0", lambda: make_problem(0, 0), 3),
