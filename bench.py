@@ -166,19 +166,29 @@ def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
     }
 
 
-def cpu_baseline(seconds_target=15.0):
+def cpu_baseline(seconds_target=15.0, one_thread=False):
     """The FP64 oracle on the host cores: one config-1 job, one warm-up iteration,
-    then iterations until about `seconds_target` seconds have passed."""
+    then iterations until about `seconds_target` seconds have passed (all BLAS
+    threads, or one)."""
+    import contextlib
+
     import numpy as np
 
     from gen import make_problem
     from oracle import nfhmm_oracle as O
+    limit = contextlib.nullcontext()
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         threads = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+        if one_thread:
+            limit, threads = threadpool_limits(limits=1, user_api="blas"), 1
     except Exception:
-        threads = os.cpu_count()
-    p = make_problem(1, 0)
+        threads = 1 if one_thread else os.cpu_count()
+    with limit:
+        return _cpu_run(make_problem(1, 0), seconds_target, threads, O, np)
+
+
+def _cpu_run(p, seconds_target, threads, O, np):
     S, N, K = p["S"], p["N"], p["K"]
     V, beta, A, pi = O.paper_arrays(p)
     B = O.mask_B(S, N, K)
@@ -193,7 +203,7 @@ def cpu_baseline(seconds_target=15.0):
     assert np.all(np.isfinite(alpha))
     return {"value": p["T"] * n / dt, "unit": "frame-iterations/s", "cores": int(threads), "kind": "oracle",
             "sample": f"config-1 job 0 (S=2,N=40,K=10,F=513,T=1000): 1 warm-up + {n} timed FP64 iterations, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s, {threads} BLAS thread(s)"}
 
 
 def main():
@@ -272,6 +282,30 @@ def main():
                          "kernels_ms": {k: v[1] for k, v in profb.items()}}
         dt1, _ = time_batch(L, ctx, jobs[:1], "fp32", max(2, args.steps), 1)
         extra["single_job_fp32"] = {"value": T * iters / dt1, "ms_per_fit": dt1 * 1e3}
+        # batch sizes around the headline one (same per-job workload)
+        sweep = {}
+        for nj in (8, 128):
+            if nj <= J:
+                sub = jobs[:nj]
+            else:
+                from gen import make_problem
+                sub = jobs + [L.DeviceJob(make_problem(1, j)) for j in range(J, nj)]
+            dts, _ = time_batch(L, ctx, sub, "fp32", 2, 1)
+            sweep[str(nj)] = nj * T * iters / dts
+            del sub
+        sweep["1"] = extra["single_job_fp32"]["value"]
+        sweep[str(J)] = value
+        extra["jobs_sweep_fp32"] = dict(sorted(sweep.items(), key=lambda kv: int(kv[0])))
+        # config 3 (S=2, N=60, K=20, F=1025, T=4000), one job, timed over 10 iterations
+        p3 = dict(make_jobs(3, 1)[0], iters=10)
+        j3 = [L.DeviceJob(p3)]
+        c3 = {"iterations_timed": 10}
+        for prec in ("fp32", "bf16"):
+            dt3, pr3 = time_batch(L, ctx, j3, prec, 2, 1, profile=True)
+            c3[prec] = {"value": p3["T"] * 10 / dt3, "ms_per_10_iterations": dt3 * 1e3,
+                        "kernels_ms": {k: v[1] / 2 for k, v in pr3.items()}}
+        extra["config3_single_job"] = c3
+        del j3
 
     out = {
         "metric": "VI frame-iterations/s at S=2,N=40,F=513 (FP32 contraction)",
@@ -296,6 +330,7 @@ def main():
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline_1thread"] = cpu_baseline(10.0, one_thread=True)
     print(json.dumps(out), flush=True)
     ctx.close()
 

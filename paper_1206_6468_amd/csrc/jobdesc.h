@@ -91,6 +91,7 @@ struct JobDesc {
   float2 *vll, *clw, *elbo, *lnz;
   float *bnd;        // boundary messages of the chunked sweep [S][2][4][fbC][64]
   float2 *bgain;     // forward log gains of the chunks [S][2 rounds][fbC]
+  float2 *bchk;      // round-2 verdicts (1 / 0) and log factors of the chunk starts [S][2][fbC]
   float *sep;
   int *status;
   int *chainflag;    // [S] set when a chain needs the exact log-space pass

@@ -852,7 +852,11 @@ __device__ __forceinline__ void put_gain(float2 *gp, double g) {
 }
 
 // Rounds 1 and 2 of the chunked sweep: one wavefront per (job, source, direction,
-// chunk).
+// chunk).  In round 2 each chunk also decides, for the chunk after it in sweep
+// order, whether that chunk's round-2 start agrees with this chunk's round-2 end
+// (the same test the next chunk made to pick its start, then the agreement
+// test), and records the verdict and the log factor between the two in bchk:
+// the fix-up then only reads verdicts.
 template <int NR>
 __global__ __launch_bounds__(64) void k_fb_round(WorkList wl, int round) {
   const int b = blockIdx.x;
@@ -868,45 +872,59 @@ __global__ __launch_bounds__(64) void k_fb_round(WorkList wl, int round) {
   float *bs = bnd_of(J, s, dir) + lane;
   float2 *gs = J.bgain + (size_t)s * 2 * C;
   const bool exact = dir == 0 ? c == 0 : c == C - 1;
+  const int prev_c = dir == 0 ? c - 1 : c + 1, next_c = dir == 0 ? c + 1 : c - 1;
   float x;
+  bool swept = true;
   if (round == 1) {
     if (dir == 0 && c == 0 && lane == 0) J.chainflag[s] = 0;
     x = live ? 0.5f : 0.0f;
   } else {
     const float in1 = bs[(size_t)c * 64];
-    const float out1 = bs[(size_t)(C + c) * 64];
     bool keep = exact;
     x = 0.0f;
     if (!exact) {
-      x = bs[(size_t)(C + (dir == 0 ? c - 1 : c + 1)) * 64];   // the neighbour's round-1 end
+      x = bs[(size_t)(C + prev_c) * 64];   // the neighbour's round-1 end
       float lr;
       keep = msgs_agree(in1, x, live, lr);
     }
     if (keep) {
+      x = bs[(size_t)(C + c) * 64];        // round-1 end stands
       bs[(size_t)(2 * C + c) * 64] = in1;
-      bs[(size_t)(3 * C + c) * 64] = out1;
+      bs[(size_t)(3 * C + c) * 64] = x;
       if (dir == 0 && lane == 0) gs[C + c] = gs[c];
-      return;
+      swept = false;
     }
   }
-  const int slot = round == 1 ? 0 : 2;
-  bs[(size_t)(slot * C + c) * 64] = x;
-  __shared__ __attribute__((aligned(16))) float buf[2 * NR];
-  float coef[NR];
-  chain_coef<NR>(J.A_in + (size_t)s * N * N, N, lane, dir == 0, coef);
-  double g = 0.0;
-  if (dir == 0) fwd_sweep<NR>(J, s, coef, buf, t0, t1, x, g);
-  else bwd_sweep<NR>(J, s, coef, buf, t0, t1, x);
-  const int k = canon_msg(x, live);
-  bs[(size_t)((slot + 1) * C + c) * 64] = x;
-  if (dir == 0 && lane == 0) put_gain(gs + (round - 1) * C + c, g + 0.69314718055994530942 * (double)k);
+  if (swept) {
+    const int slot = round == 1 ? 0 : 2;
+    bs[(size_t)(slot * C + c) * 64] = x;
+    __shared__ __attribute__((aligned(16))) float buf[2 * NR];
+    float coef[NR];
+    chain_coef<NR>(J.A_in + (size_t)s * N * N, N, lane, dir == 0, coef);
+    double g = 0.0;
+    if (dir == 0) fwd_sweep<NR>(J, s, coef, buf, t0, t1, x, g);
+    else bwd_sweep<NR>(J, s, coef, buf, t0, t1, x);
+    const int k = canon_msg(x, live);
+    bs[(size_t)((slot + 1) * C + c) * 64] = x;
+    if (dir == 0 && lane == 0) put_gain(gs + (round - 1) * C + c, g + 0.69314718055994530942 * (double)k);
+  }
+  if (round == 2 && next_c >= 0 && next_c < C) {
+    // the next chunk's round-2 start: its round-1 start if that agreed with our
+    // round-1 end, else our round-1 end
+    const float in1n = bs[(size_t)next_c * 64], out1 = bs[(size_t)(C + c) * 64];
+    float lr;
+    const float in2n = msgs_agree(in1n, out1, live, lr) ? in1n : out1;
+    const bool ok = msgs_agree(in2n, x, live, lr);
+    if (lane == 0) J.bchk[((size_t)s * 2 + dir) * C + next_c] = make_float2(ok ? 1.0f : 0.0f, lr);
+  }
 }
 
 // Fix-up of the chunked sweep: one wavefront per (job, source, direction).  The
-// agreement of every chunk's round-2 start with its neighbour's round-2 end is
-// checked first with all loads in flight; from the first disagreement on, the
-// chunks are walked in order and swept again wherever the start differs from the
-// final end before them.  The forward wavefront also forms lnz.
+// verdicts of round 2 are read 64 chunks at a time to find the first chunk (in
+// sweep order) whose start disagrees with the end before it, summing the forward
+// gains up to there; from that chunk on, the chunks are walked in order and swept
+// again wherever the start differs from the final end before them.  The forward
+// wavefront also forms lnz.
 template <int NR>
 __global__ __launch_bounds__(64) void k_fb_fixup(WorkList wl) {
   const int b = blockIdx.x;
@@ -919,30 +937,28 @@ __global__ __launch_bounds__(64) void k_fb_fixup(WorkList wl) {
   const bool live = lane < N;
   const float *bs = bnd_of(J, s, dir) + lane;
   const float2 *gs = J.bgain + (size_t)s * 2 * C + C;   // round-2 gains
+  const float2 *chk = J.bchk + ((size_t)s * 2 + dir) * C;
   const float *in2 = bs + (size_t)2 * C * 64, *out2 = bs + (size_t)3 * C * 64;
-  // pass 1: first chunk (in sweep order) whose start disagrees
-  double tot = 0.0;
+  // pass 1: first chunk (in sweep order, from 1) whose start disagrees
+  Comp tot = comp_zero();
   int first = C;
-  for (int i0 = 1; i0 < C && first == C; i0 += kFbBlock) {
-    float a[kFbBlock], e[kFbBlock];
-    float2 gg[kFbBlock];
-#pragma unroll
-    for (int i = 0; i < kFbBlock; ++i) {
-      const int i1 = min(i0 + i, C - 1);
-      const int c = dir == 0 ? i1 : C - 1 - i1, cp = dir == 0 ? c - 1 : c + 1;
-      a[i] = in2[(size_t)c * 64];
-      e[i] = out2[(size_t)cp * 64];
-      gg[i] = dir == 0 ? gs[c] : make_float2(0.0f, 0.0f);
+  for (int i0 = 1; i0 < C; i0 += 64) {
+    const int i = i0 + lane;
+    const bool in = i < C;
+    const int c = dir == 0 ? i : C - 1 - i;
+    const float2 v = in ? chk[c] : make_float2(1.0f, 0.0f);
+    const float2 g = (in && dir == 0) ? gs[c] : make_float2(0.0f, 0.0f);
+    const uint64_t bad = __ballot(in && v.x == 0.0f);
+    const int l0 = bad ? __builtin_ctzll(bad) : 64;
+    Comp part = comp_zero();
+    if (in && lane < l0) {
+      comp_add(part, g.x);
+      comp_add(part, g.y);
+      comp_add(part, v.y);
     }
-#pragma unroll
-    for (int i = 0; i < kFbBlock; ++i) {
-      if (i0 + i >= C || first != C) break;
-      float lr;
-      if (msgs_agree(a[i], e[i], live, lr)) tot += (double)gg[i].x + (double)gg[i].y + (double)lr;
-      else first = i0 + i;
-    }
+    tot = comp_merge(tot, wave_comp(part));
+    if (bad) { first = i0 + l0; break; }
   }
-  const int c_first = dir == 0 ? 0 : C - 1;
   float prev;
   if (first == C) {
     prev = out2[(size_t)(dir == 0 ? C - 1 : 0) * 64];
@@ -959,7 +975,11 @@ __global__ __launch_bounds__(64) void k_fb_fixup(WorkList wl) {
       float lr;
       if (i > first && msgs_agree(a, prev, live, lr)) {
         prev = out2[(size_t)c * 64];
-        if (dir == 0) tot += (double)gs[c].x + (double)gs[c].y + (double)lr;
+        if (dir == 0) {
+          comp_add(tot, gs[c].x);
+          comp_add(tot, gs[c].y);
+          comp_add(tot, lr);
+        }
         continue;
       }
       const int t0 = c * L, t1 = min(T, t0 + L);
@@ -968,15 +988,17 @@ __global__ __launch_bounds__(64) void k_fb_fixup(WorkList wl) {
       if (dir == 0) fwd_sweep<NR>(J, s, coef, buf, t0, t1, x, g);
       else bwd_sweep<NR>(J, s, coef, buf, t0, t1, x);
       g += 0.69314718055994530942 * (double)canon_msg(x, live);
-      tot += g;
+      const float gh = (float)g;
+      comp_add(tot, gh);
+      comp_add(tot, (float)(g - (double)gh));
       prev = x;
     }
   }
   if (dir == 0) {
-    const float g0x = gs[c_first].x, g0y = gs[c_first].y;
+    const float2 g0 = gs[0];
     const float last = wave_sum(live ? prev : 0.0f);
     if (lane == 0) {
-      const double z = tot + (double)g0x + (double)g0y + log((double)last);
+      const double z = (double)tot.hi + (double)tot.lo + (double)g0.x + (double)g0.y + log((double)last);
       const float hi = (float)z;
       J.lnz[s] = make_float2(hi, (float)(z - (double)hi));
     }

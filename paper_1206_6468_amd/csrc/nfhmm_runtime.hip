@@ -94,7 +94,7 @@ Dims dims_of(const nfhmm_problem *p, nfhmm_precision prec) {
 struct Layout {
   size_t V_in, W_in, A_in, pi_in, alpha_init;                // host-input copies
   size_t V, Wfm, Wmf, Wfm_h, Wmf_h, wh, Rh, w, R;
-  size_t alpha, c, phi, ev, sh, fwd, bwd, lnz, post, vll, clw, elbo, sep, status, chainflag, bnd, bgain;
+  size_t alpha, c, phi, ev, sh, fwd, bwd, lnz, post, vll, clw, elbo, sep, status, chainflag, bnd, bgain, bchk;
   size_t out_alpha, out_post, out_sep, out_elbo;              // host-output staging
   size_t total;
 };
@@ -152,6 +152,7 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   fb_geometry((int)T, &fbC, &fbL);
   L.bnd = take(S * 2 * 4 * (size_t)fbC * 64 * 4);
   L.bgain = take(S * 2 * (size_t)fbC * 8);
+  L.bchk = take(S * 2 * (size_t)fbC * 8);
   L.out_alpha = host_out ? take(T * M * 4) : none;
   L.out_post = host_out ? take(S * T * N * 4) : none;
   L.out_sep = host_out ? take(S * T * F * 4) : none;
@@ -247,6 +248,9 @@ struct Job {
   char *arena = nullptr;
   size_t arena_bytes = 0;
   size_t charged = 0;         // bytes counted against the serving budget while admitted
+  bool in_slab = false;       // arena carved from the serving slab
+  size_t out_pin = ~size_t(0);  // offset of the outputs in the pinned ring (serving)
+  int dev_flag = 0;             // the device status word, delivered with the outputs
   JobDesc desc{};
   nfhmm_status status = NFHMM_OK;
   std::string error;
@@ -297,6 +301,7 @@ void fill_desc(Job &j, float gamma) {
   fb_geometry(d.T, &D.fbC, &D.fbL);
   D.bnd = F32(L.bnd);
   D.bgain = reinterpret_cast<float2 *>(a + L.bgain);
+  D.bchk = reinterpret_cast<float2 *>(a + L.bchk);
   if (j.host_out) {
     D.out_alpha = j.res.alpha ? F32(L.out_alpha) : nullptr;
     D.out_post = j.res.post ? F32(L.out_post) : nullptr;
@@ -378,6 +383,19 @@ struct nfhmm_ctx {
   size_t bytes_in_use = 0;
   int round = 0;
   std::string sched_error;
+  // serving memory: one device slab of `budget` bytes, sub-allocated first fit
+  // (no hipMalloc / hipFree per job: both synchronise the device)
+  char *slab = nullptr;
+  bool slab_tried = false;
+  std::map<size_t, size_t> slab_free;   // offset -> bytes of each free range
+  // serving copies: one pinned host ring, so that host<->device copies are
+  // asynchronous (a copy from or to pageable memory holds the calling thread
+  // until the stream reaches it, which would drain the device between rounds)
+  struct PinRegion { size_t off, len; hipEvent_t ev; bool done; };
+  char *pin = nullptr;
+  size_t pin_size = 0, pin_head = 0;
+  bool pin_tried = false;
+  std::deque<PinRegion> pin_regs;
 
   // measurement: (kind, start, end) event triples of timed launches
   bool profiling = false;
@@ -476,6 +494,108 @@ void arena_release(nfhmm_ctx *ctx, Job &j, bool cached) {
   j.arena = nullptr;
 }
 
+// Serving arenas: carved from the context's slab when a budget is set (falls back
+// to hipMalloc if the slab cannot be allocated).  Returns false, with nothing
+// allocated, when the slab has no free range large enough right now.
+bool serving_alloc(nfhmm_ctx *ctx, Job &j, nfhmm_status *err) {
+  *err = NFHMM_OK;
+  const size_t need = (j.L.total + 255) / 256 * 256;
+  if (ctx->budget && !ctx->slab_tried) {
+    ctx->slab_tried = true;
+    if (hipMalloc(&ctx->slab, ctx->budget) == hipSuccess) ctx->slab_free[0] = ctx->budget;
+    else { ctx->slab = nullptr; (void)hipGetLastError(); }
+  }
+  if (!ctx->slab) {
+    *err = arena_alloc(ctx, j, false);
+    return *err == NFHMM_OK;
+  }
+  for (auto it = ctx->slab_free.begin(); it != ctx->slab_free.end(); ++it) {
+    if (it->second < need) continue;
+    const size_t off = it->first, len = it->second;
+    ctx->slab_free.erase(it);
+    if (len > need) ctx->slab_free[off + need] = len - need;
+    j.arena = ctx->slab + off;
+    j.arena_bytes = need;
+    j.in_slab = true;
+    return true;
+  }
+  return false;
+}
+
+void serving_free(nfhmm_ctx *ctx, Job &j) {
+  if (!j.arena) return;
+  if (!j.in_slab) { arena_release(ctx, j, false); return; }
+  size_t off = (size_t)(j.arena - ctx->slab), len = j.arena_bytes;
+  auto next = ctx->slab_free.lower_bound(off);
+  if (next != ctx->slab_free.end() && off + len == next->first) {   // merge with the following range
+    len += next->second;
+    next = ctx->slab_free.erase(next);
+  }
+  if (next != ctx->slab_free.begin()) {                              // and with the preceding one
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += len;
+      len = 0;
+    }
+  }
+  if (len) ctx->slab_free[off] = len;
+  j.arena = nullptr;
+  j.in_slab = false;
+}
+
+constexpr size_t kPinBytes = size_t(1) << 30;
+
+// Reserve len bytes of the pinned ring (FIFO: regions are released in the order
+// they were reserved; the live ones occupy [tail, head) circularly).  Returns the
+// offset, or ~0 if there is no room right now.
+size_t pin_reserve(nfhmm_ctx *ctx, size_t len, hipEvent_t ev) {
+  len = (len + 255) / 256 * 256;
+  if (!ctx->pin_tried) {
+    ctx->pin_tried = true;
+    if (hipHostMalloc((void **)&ctx->pin, kPinBytes, hipHostMallocDefault) == hipSuccess) ctx->pin_size = kPinBytes;
+    else { ctx->pin = nullptr; (void)hipGetLastError(); }
+  }
+  if (!ctx->pin || len == 0 || len >= ctx->pin_size) return ~size_t(0);
+  size_t off;
+  if (ctx->pin_regs.empty()) {
+    off = 0;
+  } else {
+    const size_t tail = ctx->pin_regs.front().off, head = ctx->pin_head;
+    if (head > tail) {
+      if (ctx->pin_size - head >= len) off = head;
+      else if (tail > len) off = 0;
+      else return ~size_t(0);
+    } else {
+      if (tail - head > len) off = head;
+      else return ~size_t(0);
+    }
+  }
+  ctx->pin_head = off + len;
+  ctx->pin_regs.push_back({off, len, ev, false});
+  return off;
+}
+
+void pin_pop(nfhmm_ctx *ctx) {
+  while (!ctx->pin_regs.empty() && ctx->pin_regs.front().done) {
+    if (ctx->pin_regs.front().ev) (void)hipEventDestroy(ctx->pin_regs.front().ev);
+    ctx->pin_regs.pop_front();
+  }
+  if (ctx->pin_regs.empty()) ctx->pin_head = 0;
+}
+
+// Mark upload regions whose copies have completed; drop finished regions.
+void pin_poll(nfhmm_ctx *ctx) {
+  for (auto &r : ctx->pin_regs)
+    if (!r.done && r.ev && hipEventQuery(r.ev) == hipSuccess) r.done = true;
+  pin_pop(ctx);
+}
+
+void pin_release(nfhmm_ctx *ctx, size_t off) {
+  for (auto &r : ctx->pin_regs)
+    if (r.off == off && !r.done) { r.done = true; break; }
+  pin_pop(ctx);
+}
+
 // Copy a host-input job's arrays into its arena.
 nfhmm_status upload_inputs(Job &j, hipStream_t st) {
   const Dims &d = j.d;
@@ -499,6 +619,75 @@ nfhmm_status download_outputs(Job &j, hipStream_t st) {
   if (j.res.elbo && d.iters > 0)
     HIP_OK(hipMemcpyAsync(j.res.elbo, a + j.L.out_elbo, (size_t)d.iters * 8, hipMemcpyDeviceToHost, st));
   return NFHMM_OK;
+}
+
+// Serving forms of the two copies, through the pinned ring (pageable copies if
+// the ring has no room).
+nfhmm_status upload_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
+  const Dims &d = j.d;
+  const size_t nb[5] = {(size_t)d.T * d.F * 4, (size_t)d.M * d.F * 4, (size_t)d.S * d.N * d.N * 4,
+                        (size_t)d.S * d.N * 4, j.prob.alpha_init ? (size_t)d.T * d.M * 4 : 0};
+  const void *src[5] = {j.prob.V, j.prob.W, j.prob.A, j.prob.pi, j.prob.alpha_init};
+  const size_t dst[5] = {j.L.V_in, j.L.W_in, j.L.A_in, j.L.pi_in, j.L.alpha_init};
+  size_t total = 0, sub[5];
+  for (int i = 0; i < 5; ++i) { sub[i] = total; total += (nb[i] + 255) / 256 * 256; }
+  hipEvent_t ev = nullptr;
+  HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  const size_t off = pin_reserve(ctx, total, ev);
+  if (off == ~size_t(0)) {
+    (void)hipEventDestroy(ev);
+    return upload_inputs(j, st);
+  }
+  for (int i = 0; i < 5; ++i) {
+    if (!nb[i]) continue;
+    memcpy(ctx->pin + off + sub[i], src[i], nb[i]);
+    HIP_OK(hipMemcpyAsync(j.arena + dst[i], ctx->pin + off + sub[i], nb[i], hipMemcpyHostToDevice, st));
+  }
+  HIP_OK(hipEventRecord(ev, st));
+  return NFHMM_OK;
+}
+
+struct OutPiece { void *dst; size_t src, bytes; };
+void out_pieces(Job &j, OutPiece (&p)[5]) {
+  const Dims &d = j.d;
+  p[0] = {j.res.alpha, j.L.out_alpha, (size_t)d.T * d.M * 4};
+  p[1] = {j.res.post, j.L.out_post, (size_t)d.S * d.T * d.N * 4};
+  p[2] = {j.res.sep, j.L.out_sep, (size_t)d.S * d.T * d.F * 4};
+  p[3] = {d.iters > 0 ? j.res.elbo : nullptr, j.L.out_elbo, (size_t)d.iters * 8};
+  p[4] = {&j.dev_flag, j.L.status, 4};
+}
+
+nfhmm_status download_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
+  OutPiece p[5];
+  out_pieces(j, p);
+  size_t total = 0;
+  for (auto &q : p)
+    if (q.dst) total += (q.bytes + 255) / 256 * 256;
+  const size_t off = pin_reserve(ctx, total, nullptr);
+  if (off == ~size_t(0)) return download_outputs(j, st);
+  j.out_pin = off;
+  size_t o = off;
+  for (auto &q : p) {
+    if (!q.dst) continue;
+    HIP_OK(hipMemcpyAsync(ctx->pin + o, j.arena + q.src, q.bytes, hipMemcpyDeviceToHost, st));
+    o += (q.bytes + 255) / 256 * 256;
+  }
+  return NFHMM_OK;
+}
+
+// After the download has completed: ring -> the caller's output arrays.
+void deliver_staged(nfhmm_ctx *ctx, Job &j) {
+  if (j.out_pin == ~size_t(0)) return;
+  OutPiece p[5];
+  out_pieces(j, p);
+  size_t o = j.out_pin;
+  for (auto &q : p) {
+    if (!q.dst) continue;
+    memcpy(q.dst, ctx->pin + o, q.bytes);
+    o += (q.bytes + 255) / 256 * 256;
+  }
+  pin_release(ctx, j.out_pin);
+  j.out_pin = ~size_t(0);
 }
 
 // ------------------------------------------------------------------ engine
@@ -697,13 +886,21 @@ void scheduler(nfhmm_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   hipStream_t st = ctx->stream;
   struct Pending { Job *job; hipEvent_t ev; };
-  std::vector<Pending> pending;   // finished on the device, outputs in flight
+  std::vector<Pending> pending;        // off the device or cancelled; outputs / last work in flight
+  std::deque<hipEvent_t> inflight;     // end markers of the rounds still on the device
+  std::vector<hipEvent_t> spare;
+  auto new_event = [&]() {
+    hipEvent_t e = nullptr;
+    if (!spare.empty()) { e = spare.back(); spare.pop_back(); }
+    else (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    return e;
+  };
   for (;;) {
     std::vector<Job *> admitted, act;
     {
       std::unique_lock<std::mutex> lk(ctx->mu);
       ctx->cv.wait(lk, [&] { return ctx->stop || !ctx->queue.empty() || !ctx->resident.empty() || !pending.empty(); });
-      if (ctx->stop && ctx->queue.empty() && ctx->resident.empty() && pending.empty()) return;
+      if (ctx->stop && ctx->queue.empty() && ctx->resident.empty() && pending.empty()) break;
       // drop cancelled queued jobs
       for (auto it = ctx->queue.begin(); it != ctx->queue.end();) {
         if ((*it)->cancel) {
@@ -711,34 +908,47 @@ void scheduler(nfhmm_ctx *ctx) {
           it = ctx->queue.erase(it);
         } else ++it;
       }
-      // admission: first in, first out, within budget and slots
+      // admission: first in, first out, within budget and slots; then the
+      // arenas, stopping (in order) at the first job the slab cannot place yet
       std::vector<size_t> fp;
       for (Job *j : ctx->queue) fp.push_back(j->L.total);
       std::vector<int> adm(fp.size(), 0);
       nfhmm_admission_plan((int)fp.size(), fp.data(), ctx->bytes_in_use, ctx->budget, (int)ctx->resident.size(),
                            ctx->max_slots, adm.data());
-      for (size_t i = 0; i < adm.size(); ++i)
-        if (adm[i] == 1) admitted.push_back(ctx->queue[i]);
+      for (size_t i = 0; i < adm.size(); ++i) {
+        if (adm[i] != 1) break;
+        Job *j = ctx->queue[i];
+        nfhmm_status err;
+        if (!serving_alloc(ctx, *j, &err)) {
+          if (err == NFHMM_OK) break;            // no free range yet: wait for a job to leave
+          finish_job_locked(ctx, j, err, g_err); // the device refused the memory
+          ctx->cv_done.notify_all();
+          continue;
+        }
+        admitted.push_back(j);
+      }
       for (Job *j : admitted) {
         ctx->queue.erase(std::find(ctx->queue.begin(), ctx->queue.end(), j));
         j->charged = j->L.total;
         ctx->bytes_in_use += j->charged;
       }
-    }
-    // allocate and start the admitted jobs
-    std::vector<Job *> started;
-    for (Job *j : admitted) {
-      nfhmm_status s = arena_alloc(ctx, *j, false);
-      if (s == NFHMM_OK) {
-        j->start_round = ctx->round;
-        fill_desc(*j, j->prob.gamma);
-        s = upload_inputs(*j, st);
+      for (auto it = ctx->queue.begin(); it != ctx->queue.end();) {   // jobs failed above
+        if ((*it)->state == kDone) it = ctx->queue.erase(it);
+        else ++it;
       }
+    }
+    // start the admitted jobs
+    std::vector<Job *> started;
+    pin_poll(ctx);
+    for (Job *j : admitted) {
+      j->start_round = ctx->round;
+      fill_desc(*j, j->prob.gamma);
+      nfhmm_status s = upload_staged(ctx, *j, st);
       std::lock_guard<std::mutex> lk(ctx->mu);
-      if (s != NFHMM_OK) {
-        finish_job_locked(ctx, j, s, g_err);
-        arena_release(ctx, *j, false);
-        ctx->cv_done.notify_all();
+      if (s != NFHMM_OK) {   // finished (with this status) once the stream has passed it
+        j->status = s;
+        j->error = g_err;
+        pending.push_back({j, nullptr});
       } else {
         j->state = kResident;
         started.push_back(j);
@@ -752,12 +962,13 @@ void scheduler(nfhmm_ctx *ctx) {
         if (j->d.iters == 0) zero_iter.push_back(j);
         else ctx->resident.push_back(j);
       }
-      // cancelled resident jobs leave now (their in-flight work is ordered before any reuse)
+      // cancelled resident jobs leave now; their arenas are released once the
+      // work already queued for them has finished
       std::vector<Job *> keep;
       for (Job *j : ctx->resident) {
         if (j->cancel) {
-          pending.push_back({j, nullptr});
           j->status = NFHMM_E_CANCELLED;
+          pending.push_back({j, nullptr});
         } else keep.push_back(j);
       }
       ctx->resident.swap(keep);
@@ -770,12 +981,19 @@ void scheduler(nfhmm_ctx *ctx) {
       if (r - j->start_round + 1 == j->d.iters) fin.push_back(j);
     if (s == NFHMM_OK) s = engine_finish(ctx, fin, st);
     for (Job *j : fin) {
-      if (s == NFHMM_OK) s = download_outputs(*j, st);
-      hipEvent_t ev = nullptr;
-      (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-      (void)hipEventRecord(ev, st);
-      pending.push_back({j, ev});
+      if (s == NFHMM_OK) s = download_staged(ctx, *j, st);
+      pending.push_back({j, nullptr});
     }
+    // one marker for everything queued so far: finished jobs' outputs and the
+    // last work of cancelled ones are complete once it has passed
+    hipEvent_t mark = new_event();
+    (void)hipEventRecord(mark, st);
+    for (auto &pd : pending)
+      if (!pd.ev) {
+        pd.ev = new_event();
+        (void)hipEventRecord(pd.ev, st);
+      }
+    inflight.push_back(mark);
     {
       std::lock_guard<std::mutex> lk(ctx->mu);
       std::vector<Job *> keep;
@@ -785,30 +1003,39 @@ void scheduler(nfhmm_ctx *ctx) {
       ctx->round++;
       if (s != NFHMM_OK) ctx->sched_error = g_err;
     }
-    // Keep at most about two rounds in flight: wait for the previous round's
-    // completion markers, then retire jobs whose outputs have landed.
-    if (ctx->resident.empty() || pending.size() > 0) (void)hipStreamSynchronize(st);
+    // at most two rounds on the device; with nothing left to run, wait for all
+    const bool idle = ctx->resident.empty();
+    while (inflight.size() > 2 || (idle && !inflight.empty())) {
+      (void)hipEventSynchronize(inflight.front());
+      spare.push_back(inflight.front());
+      inflight.pop_front();
+    }
+    // retire the jobs whose outputs have landed
     std::vector<Pending> still;
     for (auto &pd : pending) {
-      bool ready = pd.ev == nullptr || hipEventQuery(pd.ev) == hipSuccess;
-      if (!ready) { still.push_back(pd); continue; }
-      if (pd.ev) (void)hipEventDestroy(pd.ev);
+      if (hipEventQuery(pd.ev) != hipSuccess) { still.push_back(pd); continue; }
+      spare.push_back(pd.ev);
       Job *j = pd.job;
-      int flag = 0;
-      (void)hipMemcpy(&flag, j->desc.status, 4, hipMemcpyDeviceToHost);
-      nfhmm_status js = j->status == NFHMM_E_CANCELLED ? NFHMM_E_CANCELLED : NFHMM_OK;
-      std::string err;
+      const bool staged = j->out_pin != ~size_t(0);
+      deliver_staged(ctx, *j);
+      int flag = j->dev_flag;
+      if (!staged && j->status == NFHMM_OK) (void)hipMemcpy(&flag, j->desc.status, 4, hipMemcpyDeviceToHost);
+      serving_free(ctx, *j);
+      std::lock_guard<std::mutex> lk(ctx->mu);
+      nfhmm_status js = j->status;
+      std::string err = j->error;
       if (js == NFHMM_OK && s != NFHMM_OK) { js = s; err = ctx->sched_error; }
       else if (js == NFHMM_OK && (flag & (kBadV | kBadW))) { js = NFHMM_E_INVALID; err = "invalid input detected on the device"; }
       else if (js == NFHMM_OK && (flag & kNonFinite)) { js = NFHMM_E_NONFINITE; err = "the evidence lower bound became non-finite"; }
-      arena_release(ctx, *j, false);
-      std::lock_guard<std::mutex> lk(ctx->mu);
+      else if (js == NFHMM_E_CANCELLED) err = "cancelled";
       finish_job_locked(ctx, j, js, err);
-      j->arena = nullptr;
       ctx->cv_done.notify_all();
     }
     pending.swap(still);
   }
+  (void)hipStreamSynchronize(st);
+  for (hipEvent_t e : inflight) (void)hipEventDestroy(e);
+  for (hipEvent_t e : spare) (void)hipEventDestroy(e);
 }
 
 }  // namespace
@@ -855,7 +1082,11 @@ void nfhmm_destroy(nfhmm_ctx *ctx) {
   if (ctx->sched.joinable()) ctx->sched.join();
   (void)hipDeviceSynchronize();
   for (auto &kv : ctx->jobs)
-    if (kv.second->arena) (void)hipFree(kv.second->arena);
+    if (kv.second->arena && !kv.second->in_slab) (void)hipFree(kv.second->arena);
+  if (ctx->slab) (void)hipFree(ctx->slab);
+  for (auto &r : ctx->pin_regs)
+    if (r.ev) (void)hipEventDestroy(r.ev);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
   for (auto &kv : ctx->arena_cache)
     for (char *a : kv.second) (void)hipFree(a);
   for (auto &r : ctx->recs) {
@@ -1097,6 +1328,7 @@ nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float
   int fbC = 1, fbL = 1;
   fb_geometry((int)T, &fbC, &fbL);
   const size_t o_bnd = take((size_t)2 * 4 * fbC * 64 * 4), o_bg = take((size_t)2 * fbC * 8);
+  const size_t o_chk = take((size_t)2 * fbC * 8);
   const size_t o_desc = take(sizeof(JobDesc)), o_start = take(8 * sizeof(int));
   char *a = nullptr;
   HIP_OK(hipMalloc(&a, off));
@@ -1120,6 +1352,7 @@ nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float
   D.fbL = fbL;
   D.bnd = reinterpret_cast<float *>(a + o_bnd);
   D.bgain = reinterpret_cast<float2 *>(a + o_bg);
+  D.bchk = reinterpret_cast<float2 *>(a + o_chk);
   const int npost = (int)((T_ + 3) / 4);
   const int start[8] = {0, 2 * fbC, 0, 2, 0, npost, 0, 1};    // rounds, fix-up, posterior, exact
   HIP_OK(hipMemcpyAsync(a + o_desc, &D, sizeof D, hipMemcpyHostToDevice, st));

@@ -42,6 +42,17 @@ def _errs(gpu, ref, V_TF):
     return ea, ed, es
 
 
+def _start_alpha(p, start_iters):
+    """alpha-hat after `start_iters` oracle iterations (or the default start), in float32."""
+    S, N, K = p["S"], p["N"], p["K"]
+    V, beta, A, pi = O.paper_arrays(p)
+    if start_iters > 0:
+        a0 = O.fit(V, beta, A, pi, S, N, K, iters=start_iters)["alpha"]
+    else:
+        a0 = O.init_alpha(V, beta, O.mask_B(S, N, K), 1.0, N)
+    return a0.astype(np.float32)
+
+
 def _one_step(L, ctx, p, start_iters, precision="fp32"):
     """Oracle to `start_iters`, cast alpha-hat to float32, one GPU and one oracle step."""
     S, N, K = p["S"], p["N"], p["K"]
@@ -187,6 +198,31 @@ def test_one_step_parity_full_size(L, ctx, cfg):
     el = abs(gpu["elbo"][0] - ref["elbo"][0]) / abs(ref["elbo"][0])
     print(f"\ncfg{cfg}: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
     assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+
+
+def test_config3_fp32_and_bf16(L, ctx):
+    """Config 3 (S=2, N=60, K=20, F=1025, T=4000): one FP32 step at the FP32
+    bounds, one BF16 step at the stated BF16 bounds, both from the same alpha-hat,
+    and the BF16 step against the FP32 GPU step."""
+    p = make_problem(3, 0)
+    S, N, K = p["S"], p["N"], p["K"]
+    a32 = _start_alpha(p, 1)
+    q = dict(p, iters=1, alpha_init=a32)
+    gpu = L.fit(ctx, q, "fp32")
+    hb = L.fit(ctx, q, "bf16")
+    V, beta, A, pi = O.paper_arrays(p)
+    ref = O.fit(V, beta, A, pi, S, N, K, iters=1, alpha_init=a32.astype(np.float64))
+    ref["sep"] = np.transpose(ref["sep"], (0, 2, 1))
+    Vd = p["V"].astype(np.float64)
+    for name, g, tol in (("fp32", gpu, (TOL_A, TOL_D, TOL_SEP, TOL_L)), ("bf16", hb, (2e-2, 5e-2, 2e-2, 1e-3))):
+        ea, ed, es = _errs(g, ref, Vd)
+        el = abs(g["elbo"][0] - ref["elbo"][0]) / abs(ref["elbo"][0])
+        print(f"\ncfg3 {name} vs oracle: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
+        assert ea < tol[0] and ed < tol[1] and es < tol[2] and el < tol[3]
+    eb = (np.max(np.abs(hb["alpha"] - gpu["alpha"]) / gpu["alpha"]), np.max(np.abs(hb["post"] - gpu["post"])),
+          np.max(np.abs(hb["sep"] - gpu["sep"]) / np.maximum(Vd[None], 1.0)))
+    print(f"cfg3 bf16 vs fp32 GPU: alpha rel {eb[0]:.2e}  post abs {eb[1]:.2e}  sep {eb[2]:.2e}")
+    assert eb[0] < 2e-2 and eb[1] < 5e-2 and eb[2] < 2e-2
 
 
 def test_default_start_matches_oracle(L, ctx):
