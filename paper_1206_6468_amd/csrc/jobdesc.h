@@ -48,6 +48,7 @@ constexpr int kSpecWM = NFHMM_SPEC_WM, kSpecWN = NFHMM_SPEC_WN;
 constexpr int kCntWM = NFHMM_CNT_WM, kCntWN = NFHMM_CNT_WN;
 constexpr int kSpecBM = 32 * kSpecWM, kSpecBN = 32 * kSpecWN;
 constexpr int kCntBM = 32 * kCntWM, kCntBN = 32 * kCntWN;
+constexpr int kSpecSmallBM = 64, kSpecSmallBN = 64;   // spectrum tile for small batches
 constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
 
 // Chunks of the time-parallel forward-backward: about kFbChunk frames each, at
@@ -77,8 +78,8 @@ struct JobDesc {
   int nlt;           // ceil(Fp / 64): row tiles of the reconstruction
   int Fm;            // bins of the spectrum contraction (rows) and of the counts (k)
   int Ft;            // tail bins [Fm, F) handled outside the MFMA tiles (0..4)
-  int nst;           // ceil(Fm / 128): row tiles of the spectrum contraction
-  int nvl;           // slots of vll: nst, plus one for the tail
+  int nsl;           // ceil(Fm / 64): 64-bin slots of the spectrum's bound partials
+                     // in vll (the tail bins' partial is slot nsl)
   int fbC, fbL;      // chunks of the forward-backward and frames per chunk
   double elbo_const; // T * (lnG(M + gamma S K) - S K lnG(1 + gamma))
   // inputs in the ABI layouts (device)

@@ -10,7 +10,9 @@ enum UpdateMode : int { kUpdMessages = 0, kUpdUniform = 1, kUpdFromAlpha = 2 };
 
 hipError_t launch_pack(const JobDesc &J, hipStream_t st);
 hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st);
-hipError_t launch_spectrum(const WorkList &wl, bool bf16, hipStream_t st);
+// small: 64 x 64 block tiles (work lists built with kSpecSmallBM / BN) instead of
+// kSpecBM x kSpecBN
+hipError_t launch_spectrum(const WorkList &wl, bool bf16, bool small, hipStream_t st);
 hipError_t launch_counts(const WorkList &wl, bool bf16, hipStream_t st);
 // Chunked forward-backward: rounds 1 and 2 (one block per source, direction and
 // chunk), then the fix-up (one block per source and direction).

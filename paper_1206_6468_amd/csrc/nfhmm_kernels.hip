@@ -394,19 +394,23 @@ __device__ void gemm_nt_bf16(const uint16_t *__restrict__ A, int lda, int arows,
 
 // ------------------------------------------------------------------ Eq. 7: Lambda, R
 // Rows l (frequency, [0, Fm)), columns t (frames), k over all M elements.
-template <bool kBF16>
+// Two block tiles: 128 x 128 for large batches, 64 x 64 when the batch would not
+// fill the chip.  Either way the per-frame partials of sum V ln Lambda go to one
+// slot per 64 bins (nsl slots), so the bound does not depend on the tile chosen.
+template <bool kBF16, int WM, int WN>
 __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
-  constexpr int WM = kSpecWM, WN = kSpecWN, BM = 32 * WM, BN = 32 * WN;
+  static_assert(WM == 2 || WM == 4, "a wave row covers 32 or 64 bins");
+  constexpr int BM = 32 * WM, BN = 32 * WN;
   const int b = xcd_remap(blockIdx.x, wl.total);
   const int jb = find_job(wl.start, wl.njobs, b);
   const JobDesc &J = wl.jobs[jb];
-  const int T = J.T, Fp = J.Fp, Fm = J.Fm;
+  const int T = J.T, Fp = J.Fp, Fm = J.Fm, nsl = J.nsl;
   const gfloat *Vin = gptr(J.V);
   gfloat *Rout = gptr(J.R);
   gu16 *Rh = gptr(J.Rh);
   gfloat2 *vll = gptr(J.vll);
   const int tile = b - wl.start[jb];
-  const int nrt = J.nst;
+  const int nrt = (Fm + BM - 1) / BM;
   const int rt = tile % nrt, ct = tile / nrt;
   const int row0 = rt * BM, col0 = ct * BN;
   floatx4 acc[WM][WN];
@@ -444,7 +448,7 @@ __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
         }
       }
     }
-    // reduce over the 4 lane groups that share column t, then over the two wave rows
+    // reduce over the 4 lane groups that share column t
 #pragma unroll
     for (int o = 16; o < 64; o <<= 1) {
       Comp d;
@@ -452,13 +456,18 @@ __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
       d.lo = __shfl_xor(cs.lo, o);
       cs = comp_merge(cs, d);
     }
-    if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
-    __syncthreads();
-    if (f.lq == 0 && f.wr == 0 && t < T) {
-      const Comp tot = comp_merge(cs, part[f.wc][j * 16 + f.lr]);
-      vll[(size_t)rt * T + t] = vf2{tot.hi, tot.lo};
+    if constexpr (WM == 4) {   // a wave row is one 64-bin slot
+      const int slot = rt * 2 + f.wr;
+      if (f.lq == 0 && t < T && slot < nsl) vll[(size_t)slot * T + t] = vf2{cs.hi, cs.lo};
+    } else {                   // the two wave rows form one slot
+      if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
+      __syncthreads();
+      if (f.lq == 0 && f.wr == 0 && t < T) {
+        const Comp tot = comp_merge(cs, part[f.wc][j * 16 + f.lr]);
+        vll[(size_t)rt * T + t] = vf2{tot.hi, tot.lo};
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -599,7 +608,7 @@ constexpr int kFbBlock = NFHMM_FB_BLOCK;
 template <int NR>
 __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&coef)[NR], float x, int lane, int N,
                                              bool sumlane, bool live, bool fwd, float &tot) {
-  float y0 = 0.0f, y1 = 0.0f;
+  float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f, y3 = 0.0f;
 #if NFHMM_FB_LDS
   if (lane < NR) buf[p * NR + lane] = x;
   // The block is one wavefront and LDS executes a wavefront's operations in issue
@@ -610,12 +619,13 @@ __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&c
 #pragma unroll
   for (int q = 0; q < NR / 4; ++q) v[q] = *(const float4 *)(buf + p * NR + 4 * q);
   p ^= 1;
+  // four independent accumulators: the dependent chain is NR/4 FMAs long
 #pragma unroll
   for (int q = 0; q < NR / 4; ++q) {
     y0 = fmaf(v[q].x, coef[4 * q + 0], y0);
     y1 = fmaf(v[q].y, coef[4 * q + 1], y1);
-    y0 = fmaf(v[q].z, coef[4 * q + 2], y0);
-    y1 = fmaf(v[q].w, coef[4 * q + 3], y1);
+    y2 = fmaf(v[q].z, coef[4 * q + 2], y2);
+    y3 = fmaf(v[q].w, coef[4 * q + 3], y3);
   }
 #else
   // Every lane needs the whole message: read it lane by lane into scalar
@@ -623,12 +633,14 @@ __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&c
   // other waves on the same CU).
   const int xi = __float_as_int(x);
 #pragma unroll
-  for (int m = 0; m < NR; m += 2) {
+  for (int m = 0; m < NR; m += 4) {
     y0 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m)), coef[m], y0);
     y1 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m + 1)), coef[m + 1], y1);
+    y2 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m + 2)), coef[m + 2], y2);
+    y3 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m + 3)), coef[m + 3], y3);
   }
 #endif
-  const float y = y0 + y1;
+  const float y = (y0 + y1) + (y2 + y3);
   if (sumlane) tot = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), N));
   else tot = wave_sum(live ? (fwd ? x : y) : 0.0f);
   return y;
@@ -1147,7 +1159,7 @@ constexpr int kMaxTail = 4;   // tail bins handled here (F mod 64 <= 4)
 template <bool kBF16>
 __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, float *sE, int mode, int round) {
   const int S = J.S, N = J.N, K = J.K, M = J.M, Mp = J.Mp, T = J.T, Fp = J.Fp;
-  const int Fm = J.Fm, Ft = J.Ft, nst = J.nst;
+  const int Fm = J.Fm, Ft = J.Ft, nsl = J.nsl;
   const int it = round - J.start_round, iters = J.iters;
   const float gamma = J.gamma;
   const gfloat *c = gptr(J.c), *alpha_init = gptr(J.alpha_init), *post_in = gptr(J.post);
@@ -1171,9 +1183,9 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
   Comp pv = comp_zero();                    // contraction-side parts of the bound
   Comp chain = comp_zero();
   if (msg) {
-    if (Ft > 0) vtail = vll[(size_t)nst * T + t];
+    if (Ft > 0) vtail = vll[(size_t)nsl * T + t];
     const int nkt = (Mp + kCntBM - 1) / kCntBM;
-    for (int r = lane; r < nst; r += 64) {
+    for (int r = lane; r < nsl; r += 64) {
       const vf2 v = vll[(size_t)r * T + t];
       Comp d; d.hi = v.x; d.lo = v.y;
       pv = comp_merge(pv, d);
@@ -1343,7 +1355,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
     comp_add(tot, vtail.y);
     if (lane == 0) elbo[(size_t)it * T + t] = vf2{tot.hi, tot.lo};
   }
-  if (lane == 0 && Ft > 0) vll[(size_t)nst * T + t] = vf2{vl.hi, vl.lo};
+  if (lane == 0 && Ft > 0) vll[(size_t)nsl * T + t] = vf2{vl.hi, vl.lo};
 }
 
 __global__ __launch_bounds__(256) NFHMM_UPD_ATTR void k_update(WorkList wl, int mode, int round, int stride) {
@@ -1500,10 +1512,15 @@ hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st) {
   return last();
 }
 
-hipError_t launch_spectrum(const WorkList &wl, bool bf16, hipStream_t st) {
+hipError_t launch_spectrum(const WorkList &wl, bool bf16, bool small, hipStream_t st) {
   if (wl.total <= 0) return last();
-  if (bf16) k_spectrum<true><<<wl.total, 256, 0, st>>>(wl);
-  else k_spectrum<false><<<wl.total, 256, 0, st>>>(wl);
+  if (small) {
+    if (bf16) k_spectrum<true, 2, 2><<<wl.total, 256, 0, st>>>(wl);
+    else k_spectrum<false, 2, 2><<<wl.total, 256, 0, st>>>(wl);
+  } else {
+    if (bf16) k_spectrum<true, kSpecWM, kSpecWN><<<wl.total, 256, 0, st>>>(wl);
+    else k_spectrum<false, kSpecWM, kSpecWN><<<wl.total, 256, 0, st>>>(wl);
+  }
   return last();
 }
 

@@ -276,8 +276,7 @@ void fill_desc(Job &j, float gamma) {
   const int ftail = d.F % 64;
   if (d.F >= 64 && ftail >= 1 && ftail <= 4) { D.Fm = d.F - ftail; D.Ft = ftail; }
   else { D.Fm = d.Fp; D.Ft = 0; }
-  D.nst = (D.Fm + kSpecBM - 1) / kSpecBM;   // spectrum row tiles
-  D.nvl = D.nst + (D.Ft > 0 ? 1 : 0);
+  D.nsl = (D.Fm + 63) / 64;
   const double C = std::lgamma((double)d.M + (double)gamma * d.S * d.K) - (double)d.S * d.K * std::lgamma(1.0 + gamma);
   D.elbo_const = (double)d.T * C;
   if (j.host_in) {
@@ -321,14 +320,24 @@ struct Table {
   std::vector<uint64_t> key;
   WorkList lists[kNumLists];
   int nmax = 1, mpmax = 32, upd_stride = 32;
+  bool spec_small = false;   // 64 x 64 spectrum tiles (the batch would not fill the chip)
   char *dev = nullptr, *host = nullptr;
   size_t cap = 0;
   hipEvent_t ready = nullptr;
 };
 
-int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb) {
+// below this many 128 x 128 blocks the spectrum runs on 64 x 64 tiles (four
+// times the blocks), so that a small batch still spreads over the 256 CUs
+constexpr int kSmallBatchBlocks = 256;
+
+int spec_blocks(const JobDesc &D, bool small) {
+  const int bm = small ? kSpecSmallBM : kSpecBM, bn = small ? kSpecSmallBN : kSpecBN;
+  return ((D.Fm + bm - 1) / bm) * ((D.T + bn - 1) / bn);
+}
+
+int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb, bool spec_small) {
   const int ct = (D.T + 63) / 64;       // 64-frame tiles (reconstruction)
-  const int spec = D.nst * ((D.T + kSpecBN - 1) / kSpecBN);
+  const int spec = spec_blocks(D, spec_small);
   const int cnt = ((D.Mp + kCntBM - 1) / kCntBM) * ((D.T + kCntBN - 1) / kCntBN);
   switch (k) {
     case kSpecF: return bf16 ? 0 : spec;
@@ -448,12 +457,15 @@ nfhmm_status get_table(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream
     snmax = std::max(snmax, jobs[i]->d.S * jobs[i]->d.N);
   }
   t.upd_stride = update_stride(t.mpmax, snmax);
+  int big = 0;
+  for (int i = 0; i < n; ++i) big += spec_blocks(jobs[i]->desc, false);
+  t.spec_small = big < kSmallBatchBlocks;
   for (int k = 0; k < kNumLists; ++k) {
     int *hs = reinterpret_cast<int *>(t.host + desc_bytes + k * list_bytes);
     int acc = 0;
     for (int i = 0; i < n; ++i) {
       hs[i] = acc;
-      acc += blocks_of((ListKind)k, jobs[i]->desc, jobs[i]->d.bf16, update_waves(t.upd_stride));
+      acc += blocks_of((ListKind)k, jobs[i]->desc, jobs[i]->d.bf16, update_waves(t.upd_stride), t.spec_small);
     }
     hs[n] = acc;
     t.lists[k].jobs = reinterpret_cast<const JobDesc *>(t.dev);
@@ -705,8 +717,8 @@ nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStr
     Table *t;
     nfhmm_status s = get_table(ctx, uni, st, &t);
     if (s != NFHMM_OK) return s;
-    HIP_OK(launch_spectrum(t->lists[kSpecF], false, st));
-    HIP_OK(launch_spectrum(t->lists[kSpecH], true, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecF], false, t->spec_small, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecH], true, t->spec_small, st));
     HIP_OK(launch_counts(t->lists[kCntF], false, st));
     HIP_OK(launch_counts(t->lists[kCntH], true, st));
     HIP_OK(launch_update(t->lists[kUpd], kUpdUniform, 0, t->upd_stride, st));
@@ -771,8 +783,8 @@ nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int 
   HIP_OK(hipEventRecord(ev_join, fb));
   {
     Timed tm(ctx, NFHMM_K_SPECTRUM, st);
-    HIP_OK(launch_spectrum(t->lists[kSpecF], false, st));
-    HIP_OK(launch_spectrum(t->lists[kSpecH], true, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecF], false, t->spec_small, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecH], true, t->spec_small, st));
   }
   {
     Timed tm(ctx, NFHMM_K_COUNTS, st);
