@@ -204,6 +204,11 @@ typedef enum {
  * Enabling clears earlier records. */
 NFHMM_API nfhmm_status nfhmm_profile_enable(nfhmm_ctx *ctx, int enable);
 
+/* Restrict the timing of nfhmm_profile_enable to the kinds whose bit (1 << kind)
+ * is set in `mask` (default: every kind).  Fewer timed launches perturb the
+ * timed run less. */
+NFHMM_API nfhmm_status nfhmm_profile_select(nfhmm_ctx *ctx, unsigned mask);
+
 /* Wait for the recorded launches of `kind`, then return their number and summed
  * device duration in milliseconds. */
 NFHMM_API nfhmm_status nfhmm_profile_read(nfhmm_ctx *ctx, int kind, int64_t *launches, double *total_ms);

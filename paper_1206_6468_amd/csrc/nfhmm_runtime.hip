@@ -408,6 +408,7 @@ struct nfhmm_ctx {
 
   // measurement: (kind, start, end) event triples of timed launches
   bool profiling = false;
+  unsigned profile_mask = ~0u;   // kinds timed while profiling
   struct Rec { int kind; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
@@ -750,7 +751,7 @@ struct Timed {
   hipStream_t st;
   hipEvent_t a = nullptr;
   Timed(nfhmm_ctx *c, int k, hipStream_t s) : ctx(c), kind(k), st(s) {
-    if (ctx->profiling) {
+    if (ctx->profiling && ((ctx->profile_mask >> k) & 1u)) {
       a = pooled_event(ctx);
       (void)hipEventRecord(a, st);
     }
@@ -1302,6 +1303,12 @@ nfhmm_status nfhmm_profile_enable(nfhmm_ctx *ctx, int enable) {
   }
   ctx->recs.clear();
   ctx->profiling = enable != 0;
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_profile_select(nfhmm_ctx *ctx, unsigned mask) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  ctx->profile_mask = mask;
   return NFHMM_OK;
 }
 

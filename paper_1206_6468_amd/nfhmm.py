@@ -39,7 +39,7 @@ SYMBOLS = [
     "nfhmm_validate", "nfhmm_admission_plan", "nfhmm_fit", "nfhmm_fit_batch",
     "nfhmm_fit_batch_device", "nfhmm_fit_device", "nfhmm_submit", "nfhmm_poll",
     "nfhmm_wait", "nfhmm_cancel", "nfhmm_chain_posterior", "nfhmm_special_functions",
-    "nfhmm_profile_enable", "nfhmm_profile_read",
+    "nfhmm_profile_enable", "nfhmm_profile_read", "nfhmm_profile_select",
 ]
 K_SPECTRUM, K_COUNTS, K_CHAINS, K_UPDATE, K_POSTERIOR = 0, 1, 2, 3, 4
 KERNEL_KINDS = {"spectrum": K_SPECTRUM, "counts": K_COUNTS, "chains": K_CHAINS, "update": K_UPDATE,
@@ -96,6 +96,8 @@ _lib.nfhmm_chain_posterior.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_
 _lib.nfhmm_chain_posterior.restype = C.c_int
 _lib.nfhmm_special_functions.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.nfhmm_special_functions.restype = C.c_int
+_lib.nfhmm_profile_select.argtypes = [C.c_void_p, C.c_uint]
+_lib.nfhmm_profile_select.restype = C.c_int
 _lib.nfhmm_profile_enable.argtypes = [C.c_void_p, C.c_int]
 _lib.nfhmm_profile_enable.restype = C.c_int
 _lib.nfhmm_profile_read.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C.c_double)]
@@ -316,6 +318,12 @@ def special_functions(ctx: Context, x):
 def profile_enable(ctx: Context, enable: bool = True):
     """nfhmm_profile_enable: time every later iteration launch with HIP events."""
     _check(_lib.nfhmm_profile_enable(ctx.handle, 1 if enable else 0), ctx.handle)
+
+
+def profile_select(ctx: Context, kinds=None):
+    """nfhmm_profile_select: time only these kernel kinds (None: every kind)."""
+    mask = 0xFFFFFFFF if kinds is None else sum(1 << KERNEL_KINDS.get(k, k) for k in kinds)
+    _check(_lib.nfhmm_profile_select(ctx.handle, C.c_uint(mask)), ctx.handle)
 
 
 def profile_read(ctx: Context, kind):
