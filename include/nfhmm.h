@@ -204,6 +204,11 @@ typedef enum {
  * Enabling clears earlier records. */
 NFHMM_API nfhmm_status nfhmm_profile_enable(nfhmm_ctx *ctx, int enable);
 
+/* Split later blocking batches (nfhmm_fit_batch*) across `lanes` stream lanes (1 or
+ * 2; default 2): each lane advances its share of the jobs on its own pair of
+ * streams, so one lane's update overlaps the other's contractions. */
+NFHMM_API nfhmm_status nfhmm_set_lanes(nfhmm_ctx *ctx, int lanes);
+
 /* Restrict the timing of nfhmm_profile_enable to the kinds whose bit (1 << kind)
  * is set in `mask` (default: every kind).  Fewer timed launches perturb the
  * timed run less. */

@@ -369,12 +369,11 @@ struct nfhmm_ctx {
   // shares a queue with that lane's contraction stream.
   hipStream_t stream = nullptr, fb_stream = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  // execution lanes of the blocking engine: jobs can be split into groups, each
-  // advancing on its own pair of streams so that groups overlap on the device.
-  // One group is the default: a batch then shares every launch, and a kernel's
-  // launch time is its own (with two groups the lanes' launches share the chip).
+  // execution lanes of the blocking engine: jobs are split into groups, each
+  // advancing on its own pair of streams, so that one group's update and launch
+  // gaps overlap the other group's contractions
   static constexpr int kMaxGroups = 2;
-  int groups = 1;
+  int groups = 2;
   struct Lane { hipStream_t main, fb; hipEvent_t fork, join, done; } lanes[kMaxGroups] = {};
   std::vector<std::unique_ptr<Table>> tables;   // ring
   size_t table_next = 0;
@@ -1303,6 +1302,12 @@ nfhmm_status nfhmm_profile_enable(nfhmm_ctx *ctx, int enable) {
   }
   ctx->recs.clear();
   ctx->profiling = enable != 0;
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_set_lanes(nfhmm_ctx *ctx, int lanes) {
+  if (!ctx || lanes < 1 || lanes > nfhmm_ctx::kMaxGroups) return fail(NFHMM_E_INVALID, "lanes must be 1 or 2");
+  ctx->groups = lanes;
   return NFHMM_OK;
 }
 

@@ -39,7 +39,7 @@ SYMBOLS = [
     "nfhmm_validate", "nfhmm_admission_plan", "nfhmm_fit", "nfhmm_fit_batch",
     "nfhmm_fit_batch_device", "nfhmm_fit_device", "nfhmm_submit", "nfhmm_poll",
     "nfhmm_wait", "nfhmm_cancel", "nfhmm_chain_posterior", "nfhmm_special_functions",
-    "nfhmm_profile_enable", "nfhmm_profile_read", "nfhmm_profile_select",
+    "nfhmm_profile_enable", "nfhmm_profile_read", "nfhmm_profile_select", "nfhmm_set_lanes",
 ]
 K_SPECTRUM, K_COUNTS, K_CHAINS, K_UPDATE, K_POSTERIOR = 0, 1, 2, 3, 4
 KERNEL_KINDS = {"spectrum": K_SPECTRUM, "counts": K_COUNTS, "chains": K_CHAINS, "update": K_UPDATE,
@@ -97,6 +97,8 @@ _lib.nfhmm_chain_posterior.restype = C.c_int
 _lib.nfhmm_special_functions.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.nfhmm_special_functions.restype = C.c_int
 _lib.nfhmm_profile_select.argtypes = [C.c_void_p, C.c_uint]
+_lib.nfhmm_set_lanes.argtypes = [C.c_void_p, C.c_int]
+_lib.nfhmm_set_lanes.restype = C.c_int
 _lib.nfhmm_profile_select.restype = C.c_int
 _lib.nfhmm_profile_enable.argtypes = [C.c_void_p, C.c_int]
 _lib.nfhmm_profile_enable.restype = C.c_int
@@ -318,6 +320,11 @@ def special_functions(ctx: Context, x):
 def profile_enable(ctx: Context, enable: bool = True):
     """nfhmm_profile_enable: time every later iteration launch with HIP events."""
     _check(_lib.nfhmm_profile_enable(ctx.handle, 1 if enable else 0), ctx.handle)
+
+
+def set_lanes(ctx: Context, lanes: int):
+    """nfhmm_set_lanes: stream lanes a blocking batch is split across (1 or 2)."""
+    _check(_lib.nfhmm_set_lanes(ctx.handle, int(lanes)), ctx.handle)
 
 
 def profile_select(ctx: Context, kinds=None):
