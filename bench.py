@@ -220,6 +220,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the BF16 and single-job forms")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (config 4) measurement")
+    ap.add_argument("--no-one-lane", action="store_true", help="skip the one-lane roofline pass")
     ap.add_argument("--serving-jobs", type=int, default=256)
     ap.add_argument("--serving-budget-gib", type=float, default=2.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -289,15 +290,17 @@ def main():
     # the same steps on one stream lane: every launch then has the chip to itself,
     # so this is the contraction's own rate (the two-lane schedule above overlaps
     # one lane's launches with the other's)
-    L.set_lanes(ctx, 1)
-    dt1l, prof1 = time_batch(L, ctx, jobs, "fp32", args.steps, 1, profile=True, kinds=("counts",))
-    L.set_lanes(ctx, 2)
-    n1, ms1 = prof1["counts"]
-    fl1 = flops_per_job_iter["counts"] * J * iters * args.steps / max(n1, 1)
-    a1 = fl1 / (ms1 / max(n1, 1) * 1e-3)
-    extra["roofline_one_lane"] = {"value": J * T * iters / dt1l, "ms_per_step": dt1l * 1e3, "kernel": "k_counts",
-                                  "achieved": a1 / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                                  "frac": a1 / PEAK_FP32_MFMA, "algorithmic_flops_per_launch": fl1}
+    if not args.no_one_lane:
+        L.set_lanes(ctx, 1)
+        dt1l, prof1 = time_batch(L, ctx, jobs, "fp32", args.steps, 1, profile=True, kinds=("counts",))
+        L.set_lanes(ctx, 2)
+        n1, ms1 = prof1["counts"]
+        fl1 = flops_per_job_iter["counts"] * J * iters * args.steps / max(n1, 1)
+        a1 = fl1 / (ms1 / max(n1, 1) * 1e-3)
+        extra["roofline_one_lane"] = {"value": J * T * iters / dt1l, "ms_per_step": dt1l * 1e3,
+                                      "kernel": "k_counts", "achieved": a1 / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                                      "unit": "TFLOP/s", "frac": a1 / PEAK_FP32_MFMA,
+                                      "algorithmic_flops_per_launch": fl1}
     if not args.no_extra:
         dtb, profb = time_batch(L, ctx, jobs, "bf16", args.steps, 1, profile=True, kinds=("counts",))
         tb = flops_per_job_iter["counts"] * J * iters * args.steps / (profb["counts"][1] * 1e-3)

@@ -157,6 +157,40 @@ def cmd_traffic(a):
         print(f"wrote {a.md}")
 
 
+def cmd_counters(a):
+    """Per-kernel averages of every counter of one --pmc run, with MFMA busy
+    fraction (SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE of one XCD times the
+    SIMDs) and LDS bank-conflict ratio where their counters are present."""
+    con = sqlite3.connect(_db(a.db))
+    acc = defaultdict(lambda: defaultdict(list))
+    for name, cn, v in con.execute("select kernel_name, counter_name, value from counters_collection"):
+        acc[name][cn].append(float(v))
+    lines = [f"# Hardware counters per dispatch: {a.title}", "",
+             "Command (run from /tmp with TMPDIR=/tmp; `$R` is the repository root):", "", f"    {a.command}", "",
+             f"Kernel sources {kernel_source_hash()}.  GRBM_GUI_ACTIVE is summed over the {a.xcds} XCDs; MFMA busy = "
+             f"SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {a.xcds} x {a.simds} SIMDs).", ""]
+    names = sorted({c for d in acc.values() for c in d})
+    lines += ["| kernel | dispatches | " + " | ".join(names) + " | MFMA busy | LDS conflict / access |",
+              "|---|---:|" + "---:|" * len(names) + "---:|---:|"]
+    rows = []
+    for k, d in acc.items():
+        avg = {c: sum(v) / len(v) for c, v in d.items()}
+        util = ""
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in avg and avg.get("GRBM_GUI_ACTIVE"):
+            util = f"{avg['SQ_VALU_MFMA_BUSY_CYCLES'] / (avg['GRBM_GUI_ACTIVE'] / a.xcds * a.simds):.3f}"
+        lds = ""
+        if "SQ_LDS_BANK_CONFLICT" in avg and avg.get("SQ_LDS_IDX_ACTIVE"):
+            lds = f"{avg['SQ_LDS_BANK_CONFLICT'] / max(1.0, avg['SQ_LDS_IDX_ACTIVE'] - avg['SQ_LDS_BANK_CONFLICT']):.3f}"
+        ndisp = len(next(iter(d.values())))
+        rows.append((avg.get("GRBM_GUI_ACTIVE", 0.0) * ndisp,
+                     f"| `{short_name(k)}` | {ndisp} | "
+                     + " | ".join(f"{avg.get(c, float('nan')):.4g}" for c in names) + f" | {util} | {lds} |"))
+    lines += [r for _, r in sorted(rows, key=lambda x: -x[0])]
+    with open(a.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(f"wrote {a.out}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
@@ -174,8 +208,15 @@ def main():
     t.add_argument("--commands", nargs="+", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--md", default="", help="also write a markdown table here")
+    q = sub.add_parser("counters")
+    q.add_argument("db")
+    q.add_argument("--command", required=True)
+    q.add_argument("--title", default="")
+    q.add_argument("--xcds", type=int, default=8)
+    q.add_argument("--simds", type=int, default=1024)
+    q.add_argument("--out", required=True)
     a = ap.parse_args()
-    cmd_kernels(a) if a.what == "kernels" else cmd_traffic(a)
+    {"kernels": cmd_kernels, "traffic": cmd_traffic, "counters": cmd_counters}[a.what](a)
 
 
 if __name__ == "__main__":
