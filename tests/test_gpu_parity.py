@@ -293,6 +293,32 @@ def test_batch_is_bitwise_invariant(L, ctx):
             assert np.array_equal(a[k], b[k]), k
 
 
+def test_bench_launch_configuration(L, ctx):
+    """The bench's configuration: 32 config-1 jobs in one batch (two stream lanes
+    of 16, 128 x 128 spectrum tiles).  One step from oracle alpha-hats: sampled
+    jobs against the FP64 oracle at the FP32 bounds, and every job bitwise equal
+    to the same job fitted alone (small spectrum tiles, one lane) -- except the
+    bound, whose per-64-bin partials are summed in a tile-dependent order."""
+    probs = [make_problem(1, j) for j in range(32)]
+    starts = {0: _start_alpha(probs[0], 1), 31: _start_alpha(probs[31], 1)}
+    qs = [dict(p, iters=1, alpha_init=starts.get(j, _start_alpha(p, 0))) for j, p in enumerate(probs)]
+    batch = L.fit_batch(ctx, qs)
+    for j in (0, 31):
+        p = probs[j]
+        V, beta, A, pi = O.paper_arrays(p)
+        ref = O.fit(V, beta, A, pi, p["S"], p["N"], p["K"], iters=1, alpha_init=starts[j].astype(np.float64))
+        ref["sep"] = np.transpose(ref["sep"], (0, 2, 1))
+        ea, ed, es = _errs(batch[j], ref, p["V"].astype(np.float64))
+        el = abs(batch[j]["elbo"][0] - ref["elbo"][0]) / abs(ref["elbo"][0])
+        print(f"\nbatch job {j}: alpha rel {ea:.2e}  post abs {ed:.2e}  sep {es:.2e}  elbo rel {el:.2e}")
+        assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
+    for j in (0, 5, 31):
+        alone = L.fit(ctx, qs[j])
+        for k in ("alpha", "post", "sep"):
+            assert np.array_equal(alone[k], batch[j][k]), (j, k)
+        assert np.allclose(alone["elbo"], batch[j]["elbo"], rtol=1e-12, atol=0.0)
+
+
 def test_device_path_equals_host_path(L, ctx):
     import torch
     probs = [make_problem(0, 7), make_problem(0, 8)]
