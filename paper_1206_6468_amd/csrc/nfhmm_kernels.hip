@@ -434,8 +434,8 @@ __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
           float rr[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            rr[r] = vv[r] > 0.0f ? vv[r] / lam[r] : 0.0f;
-            if (vv[r] > 0.0f) comp_add(cs, vv[r] * logf(lam[r]));
+            rr[r] = vv[r] > 0.0f ? vv[r] * fast_rcp(lam[r]) : 0.0f;
+            if (vv[r] > 0.0f) comp_add(cs, vv[r] * ln_pos(lam[r]));
           }
           if constexpr (kBF16) {
             vu2 h;
@@ -529,10 +529,10 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
         }
         const vf4 c = vf4{w.x * acc[i][j][0], w.y * acc[i][j][1], w.z * acc[i][j][2], w.w * acc[i][j][3]};
         *(gfloat4 *)(cout + (size_t)t * Mp + k) = c;
-        if (w.x > 0.0f) comp_add(cs, -c.x * logf(w.x));
-        if (w.y > 0.0f) comp_add(cs, -c.y * logf(w.y));
-        if (w.z > 0.0f) comp_add(cs, -c.z * logf(w.z));
-        if (w.w > 0.0f) comp_add(cs, -c.w * logf(w.w));
+        if (w.x > 0.0f) comp_add(cs, -c.x * ln_pos(w.x));
+        if (w.y > 0.0f) comp_add(cs, -c.y * ln_pos(w.y));
+        if (w.z > 0.0f) comp_add(cs, -c.z * ln_pos(w.z));
+        if (w.w > 0.0f) comp_add(cs, -c.w * ln_pos(w.w));
       }
     }
 #pragma unroll
@@ -1318,7 +1318,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
     const int l = Fm + jt;
     const float v = Vin[(size_t)t * Fp + l];
     const float rr = v > 0.0f ? v / lam : 0.0f;
-    if (v > 0.0f) comp_add(vl, v * logf(lam));
+    if (v > 0.0f) comp_add(vl, v * ln_pos(lam));
     if (lane == 0) {
       if constexpr (kBF16) Rh[(size_t)t * Fp + l] = f2bf(rr);
       else Rout[(size_t)t * Fp + l] = rr;

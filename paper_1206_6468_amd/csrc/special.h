@@ -63,6 +63,18 @@ NFHMM_HD float fast_exp(float x) {
 #endif
 }
 
+// ln x for any x > 0, subnormal included (scaled by 2^32 into the normal range
+// first): the hardware log2 on the device, as fast_ln.
+NFHMM_HD float ln_pos(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const bool tiny = x < 1.17549435e-38f;
+  const float l2 = __builtin_amdgcn_logf(tiny ? x * 4294967296.0f : x) - (tiny ? 32.0f : 0.0f);
+  return l2 * 0.69314718055994531f;
+#else
+  return logf(x);
+#endif
+}
+
 // Without branches: the product is formed for every x and selected, so lanes of
 // one wavefront with x on both sides of 4 do not diverge.
 NFHMM_HD Shift8 shift8(float x) {
