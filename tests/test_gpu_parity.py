@@ -176,7 +176,16 @@ ONE_STEP_CASES = [
     ("T1", lambda: make_tiny(S=2, N=4, K=2, F=16, T=1, seed=4, quanta=100), 1),
     ("K1-M-odd", lambda: make_tiny(S=3, N=3, K=1, F=9, T=64, seed=5, quanta=80), 2),
     ("N64", lambda: make_tiny(S=2, N=64, K=1, F=100, T=90, seed=6, quanta=2000, trans="sparse", diag=0.9), 2),
+    ("S8-max-sources", lambda: make_tiny(S=8, N=3, K=2, F=50, T=40, seed=7, quanta=400), 2),
+    ("silent-frames", lambda: _silence(make_problem(0, 1), [0, 1, 37, 38, 39, 99]), 2),
 ]
+
+
+def _silence(p, frames):
+    """Zero the mixture in the given frames (no counts at all: R = 0 there)."""
+    V = p["V"].copy()
+    V[frames] = 0.0
+    return dict(p, V=V)
 
 
 @pytest.mark.parametrize("name,mk,start", ONE_STEP_CASES, ids=[c[0] for c in ONE_STEP_CASES])
