@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/nfhmm.h"
+#include "host_copy.h"
 #include "jobdesc.h"
 #include "launch.h"
 
@@ -259,7 +260,7 @@ struct Job {
   int start_round = 0;
   int finish_round = -1;      // round after which the job's outputs were queued
   double t_submit = 0.0, t_done = 0.0;
-  std::vector<float> hV, hW, hA, hpi, hinit;   // serving: owned host copies of the inputs
+  std::unique_ptr<float[]> hV, hW, hA, hpi, hinit;   // serving: owned host copies of the inputs
 };
 
 void fill_desc(Job &j, float gamma) {
@@ -404,6 +405,10 @@ struct nfhmm_ctx {
   size_t pin_size = 0, pin_head = 0;
   bool pin_tried = false;
   std::deque<PinRegion> pin_regs;
+  // host copies of the serving path (inputs at submit, the ring on both sides),
+  // made on first submit
+  static constexpr int kCopyWorkers = 7;
+  std::unique_ptr<CopyPool> copies;
 
   // measurement: (kind, start, end) event triples of timed launches
   bool profiling = false;
@@ -650,11 +655,11 @@ nfhmm_status upload_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
     (void)hipEventDestroy(ev);
     return upload_inputs(j, st);
   }
-  for (int i = 0; i < 5; ++i) {
-    if (!nb[i]) continue;
-    memcpy(ctx->pin + off + sub[i], src[i], nb[i]);
-    HIP_OK(hipMemcpyAsync(j.arena + dst[i], ctx->pin + off + sub[i], nb[i], hipMemcpyHostToDevice, st));
-  }
+  CopyPool::Piece pc[5];
+  for (int i = 0; i < 5; ++i) pc[i] = {ctx->pin + off + sub[i], src[i], nb[i]};
+  ctx->copies->run(pc, 5);
+  for (int i = 0; i < 5; ++i)
+    if (nb[i]) HIP_OK(hipMemcpyAsync(j.arena + dst[i], ctx->pin + off + sub[i], nb[i], hipMemcpyHostToDevice, st));
   HIP_OK(hipEventRecord(ev, st));
   return NFHMM_OK;
 }
@@ -693,11 +698,14 @@ void deliver_staged(nfhmm_ctx *ctx, Job &j) {
   OutPiece p[5];
   out_pieces(j, p);
   size_t o = j.out_pin;
+  CopyPool::Piece pc[5];
+  int n = 0;
   for (auto &q : p) {
     if (!q.dst) continue;
-    memcpy(q.dst, ctx->pin + o, q.bytes);
+    pc[n++] = {q.dst, ctx->pin + o, q.bytes};
     o += (q.bytes + 255) / 256 * 256;
   }
+  ctx->copies->run(pc, n);
   pin_release(ctx, j.out_pin);
   j.out_pin = ~size_t(0);
 }
@@ -1235,18 +1243,27 @@ nfhmm_status nfhmm_submit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precisio
   if (ctx->budget && j->L.total > ctx->budget)
     return fail(NFHMM_E_NOMEM, "job needs %zu device bytes, budget is %zu", j->L.total, ctx->budget);
   const Dims &d = j->d;
-  j->hV.assign(p->V, p->V + (size_t)d.T * d.F);
-  j->hW.assign(p->W, p->W + (size_t)d.M * d.F);
-  j->hA.assign(p->A, p->A + (size_t)d.S * d.N * d.N);
-  j->hpi.assign(p->pi, p->pi + (size_t)d.S * d.N);
-  j->prob.V = j->hV.data();
-  j->prob.W = j->hW.data();
-  j->prob.A = j->hA.data();
-  j->prob.pi = j->hpi.data();
-  if (p->alpha_init) {
-    j->hinit.assign(p->alpha_init, p->alpha_init + (size_t)d.T * d.M);
-    j->prob.alpha_init = j->hinit.data();
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->copies) ctx->copies.reset(new CopyPool(nfhmm_ctx::kCopyWorkers));
   }
+  // the caller may reuse its arrays once submit returns: take copies
+  const size_t nV = (size_t)d.T * d.F, nW = (size_t)d.M * d.F, nA = (size_t)d.S * d.N * d.N,
+               npi = (size_t)d.S * d.N, ni = p->alpha_init ? (size_t)d.T * d.M : 0;
+  j->hV.reset(new float[nV]);
+  j->hW.reset(new float[nW]);
+  j->hA.reset(new float[nA]);
+  j->hpi.reset(new float[npi]);
+  if (ni) j->hinit.reset(new float[ni]);
+  const CopyPool::Piece pc[5] = {{j->hV.get(), p->V, nV * 4}, {j->hW.get(), p->W, nW * 4},
+                                 {j->hA.get(), p->A, nA * 4}, {j->hpi.get(), p->pi, npi * 4},
+                                 {j->hinit.get(), p->alpha_init, ni * 4}};
+  ctx->copies->run(pc, 5);
+  j->prob.V = j->hV.get();
+  j->prob.W = j->hW.get();
+  j->prob.A = j->hA.get();
+  j->prob.pi = j->hpi.get();
+  j->prob.alpha_init = ni ? j->hinit.get() : nullptr;
   j->t_submit = now_s();
   j->id = new_id(ctx);
   std::lock_guard<std::mutex> lk(ctx->mu);
