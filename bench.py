@@ -222,7 +222,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving (config 4) measurement")
     ap.add_argument("--no-one-lane", action="store_true", help="skip the one-lane roofline pass")
     ap.add_argument("--serving-jobs", type=int, default=256)
-    ap.add_argument("--serving-budget-gib", type=float, default=2.0)
+    ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM byte counters) and exit")

@@ -5,7 +5,9 @@
 // at single-core memcpy speed, slower still into freshly allocated caller arrays
 // (first-touch page faults), which for long jobs takes longer per round than the
 // device takes to run the round.  A copy here is cut into 1 MiB chunks that the
-// calling thread and the pool's workers claim from a shared counter.
+// calling thread and the pool's workers claim from a shared counter.  A piece
+// may ask for its floats to be checked (finite and >= 0) as they are copied,
+// which costs nothing beside the copy and spares a separate pass over the input.
 #pragma once
 
 #include <algorithm>
@@ -25,6 +27,7 @@ class CopyPool {
     void *dst;
     const void *src;
     size_t bytes;
+    bool check = false;   // the bytes are floats that must be finite and >= 0
   };
 
   explicit CopyPool(int workers) {
@@ -42,20 +45,22 @@ class CopyPool {
   CopyPool &operator=(const CopyPool &) = delete;
 
   // Copy every piece (dst and src ranges must not overlap); returns when all
-  // bytes are in place.  Several threads may call this at once.
-  void run(const Piece *p, int n) {
+  // bytes are in place: true when every checked piece held only finite,
+  // non-negative floats.  Several threads may call this at once.
+  bool run(const Piece *p, int n) {
     Batch b;
     size_t total = 0;
     for (int i = 0; i < n; ++i) {
       if (!p[i].bytes) continue;
       total += p[i].bytes;
-      for (size_t o = 0; o < p[i].bytes; o += kChunk)
+      for (size_t o = 0; o < p[i].bytes; o += kChunk)   // kChunk is a multiple of 4
         b.chunks.push_back({static_cast<char *>(p[i].dst) + o, static_cast<const char *>(p[i].src) + o,
-                            std::min(kChunk, p[i].bytes - o)});
+                            std::min(kChunk, p[i].bytes - o), p[i].check});
     }
     if (th_.empty() || total < 2 * kChunk) {
-      for (const Chunk &c : b.chunks) memcpy(c.d, c.s, c.n);
-      return;
+      int bad = 0;
+      for (const Chunk &c : b.chunks) bad |= copy_chunk(c);
+      return !bad;
     }
     {
       std::lock_guard<std::mutex> lk(mu_);
@@ -68,6 +73,7 @@ class CopyPool {
     if (it != q_.end()) q_.erase(it);
     // every chunk is claimed; wait for the workers still copying theirs
     done_.wait(lk, [&] { return b.users == 0; });
+    return b.bad.load(std::memory_order_relaxed) == 0;
   }
 
  private:
@@ -76,16 +82,30 @@ class CopyPool {
     char *d;
     const char *s;
     size_t n;
+    bool check;
   };
   struct Batch {
     std::vector<Chunk> chunks;
     std::atomic<size_t> next{0};
+    std::atomic<int> bad{0};
     int users = 0;   // workers inside work(); guarded by mu_
   };
 
+  // copy one chunk; 1 if it is checked and holds a negative or non-finite float
+  static int copy_chunk(const Chunk &c) {
+    memcpy(c.d, c.s, c.n);
+    if (!c.check) return 0;
+    const float *x = reinterpret_cast<const float *>(c.d);
+    int bad = 0;
+    for (size_t i = 0; i < c.n / 4; ++i) bad |= !(x[i] >= 0.0f && x[i] <= 3.40282347e38f);
+    return bad;
+  }
+
   static void work(Batch &b) {
+    int bad = 0;
     for (size_t i; (i = b.next.fetch_add(1, std::memory_order_relaxed)) < b.chunks.size();)
-      memcpy(b.chunks[i].d, b.chunks[i].s, b.chunks[i].n);
+      bad |= copy_chunk(b.chunks[i]);
+    if (bad) b.bad.store(1, std::memory_order_relaxed);
   }
 
   void loop() {

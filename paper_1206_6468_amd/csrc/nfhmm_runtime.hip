@@ -163,32 +163,70 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
 }
 
 // ------------------------------------------------------------------ host validation
-nfhmm_status validate_host(const nfhmm_problem *p, std::string *msg) {
+// The checks run over every input element at submit, so their loops are kept
+// free of early exits and calls: one pass of compares and adds that the host
+// compiler turns into vector code; only a failing input is scanned again to
+// name the offending entry.
+
+// finite and >= 0 (NaN fails both compares)
+inline int bad_value(float v) { return !(v >= 0.0f && v <= 3.40282347e38f); }
+
+bool all_finite_nonneg(const float *x, int64_t n) {
+  constexpr int64_t kBlock = 4096;
+  for (int64_t b = 0; b < n; b += kBlock) {
+    const int64_t e = std::min(n, b + kBlock);
+    int bad = 0;
+    for (int64_t i = b; i < e; ++i) bad |= bad_value(x[i]);
+    if (bad) return false;
+  }
+  return true;
+}
+
+// check_V false: the caller checks V itself (the serving path does, while copying it)
+nfhmm_status validate_host(const nfhmm_problem *p, std::string *msg, bool check_V = true) {
   std::string why;
   if (!dims_ok(p, &why)) { *msg = why; return NFHMM_E_INVALID; }
   const int64_t S = p->S, N = p->N, K = p->K, M = S * N * K, F = p->F, T = p->T;
   char buf[256];
-  for (int64_t i = 0; i < T * F; ++i) {
-    const float v = p->V[i];
-    if (!(v >= 0.0f) || !std::isfinite(v)) {
-      snprintf(buf, sizeof buf, "V[%lld][%lld] = %g is not finite and >= 0", (long long)(i / F), (long long)(i % F), v);
-      *msg = buf;
-      return NFHMM_E_INVALID;
-    }
-  }
-  std::vector<char> bin_has(F, 0);
-  for (int64_t k = 0; k < M; ++k) {
-    double s = 0.0;
-    for (int64_t l = 0; l < F; ++l) {
-      const float w = p->W[k * F + l];
-      if (!(w >= 0.0f) || !std::isfinite(w)) {
-        snprintf(buf, sizeof buf, "W[%lld][%lld] = %g is not finite and >= 0", (long long)k, (long long)l, w);
+  if (check_V && !all_finite_nonneg(p->V, T * F)) {
+    for (int64_t i = 0; i < T * F; ++i) {
+      const float v = p->V[i];
+      if (bad_value(v)) {
+        snprintf(buf, sizeof buf, "V[%lld][%lld] = %g is not finite and >= 0", (long long)(i / F), (long long)(i % F), v);
         *msg = buf;
         return NFHMM_E_INVALID;
       }
-      s += w;
-      if (w > 0.0f) bin_has[l] = 1;
     }
+  }
+  std::vector<unsigned char> bin_has(F, 0);
+  for (int64_t k = 0; k < M; ++k) {
+    const float *row = p->W + k * F;
+    // eight independent partial sums (in double) so that the loop vectorises
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int bad = 0;
+    int64_t l = 0;
+    for (; l + 8 <= F; l += 8)
+      for (int q = 0; q < 8; ++q) {
+        const float w = row[l + q];
+        bad |= bad_value(w);
+        acc[q] += w;
+        bin_has[l + q] |= (unsigned char)(w > 0.0f);
+      }
+    for (; l < F; ++l) {
+      const float w = row[l];
+      bad |= bad_value(w);
+      acc[0] += w;
+      bin_has[l] |= (unsigned char)(w > 0.0f);
+    }
+    if (bad) {
+      for (l = 0; l < F; ++l)
+        if (bad_value(row[l])) {
+          snprintf(buf, sizeof buf, "W[%lld][%lld] = %g is not finite and >= 0", (long long)k, (long long)l, row[l]);
+          *msg = buf;
+          return NFHMM_E_INVALID;
+        }
+    }
+    const double s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     if (std::fabs(s - 1.0) > 1e-4) {
       snprintf(buf, sizeof buf, "dictionary element %lld sums to %.7g, not 1", (long long)k, s);
       *msg = buf;
@@ -379,6 +417,11 @@ struct nfhmm_ctx {
   std::vector<std::unique_ptr<Table>> tables;   // ring
   size_t table_next = 0;
   std::map<size_t, std::vector<char *>> arena_cache;   // device path: reusable arenas by size
+
+  // Held while host code issues device work: by a blocking fit or chain call
+  // for its whole length, by the serving scheduler for each round.  The two
+  // share the streams, the table ring and the event pools.
+  std::mutex engine_mu;
 
   // serving state
   std::mutex mu;
@@ -904,7 +947,13 @@ void finish_job_locked(nfhmm_ctx *ctx, Job *j, nfhmm_status st, const std::strin
 
 void scheduler(nfhmm_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
-  hipStream_t st = ctx->stream;
+  // Rounds run on lane 0's streams.  The blocking engine's second lane is idle
+  // here, so its two streams carry the host<->device copies: inputs go up on
+  // one and outputs come down on the other, beside the rounds instead of
+  // between them, ordered by events.
+  hipStream_t st = ctx->stream, up = ctx->lanes[1].main, down = ctx->lanes[1].fb;
+  hipEvent_t ev_up = nullptr;
+  (void)hipEventCreateWithFlags(&ev_up, hipEventDisableTiming);
   struct Pending { Job *job; hipEvent_t ev; };
   std::vector<Pending> pending;        // off the device or cancelled; outputs / last work in flight
   std::deque<hipEvent_t> inflight;     // end markers of the rounds still on the device
@@ -957,13 +1006,14 @@ void scheduler(nfhmm_ctx *ctx) {
         else ++it;
       }
     }
+    std::lock_guard<std::mutex> eng(ctx->engine_mu);
     // start the admitted jobs
     std::vector<Job *> started;
     pin_poll(ctx);
     for (Job *j : admitted) {
       j->start_round = ctx->round;
       fill_desc(*j, j->prob.gamma);
-      nfhmm_status s = upload_staged(ctx, *j, st);
+      nfhmm_status s = upload_staged(ctx, *j, up);
       std::lock_guard<std::mutex> lk(ctx->mu);
       if (s != NFHMM_OK) {   // finished (with this status) once the stream has passed it
         j->status = s;
@@ -973,6 +1023,10 @@ void scheduler(nfhmm_ctx *ctx) {
         j->state = kResident;
         started.push_back(j);
       }
+    }
+    if (!started.empty()) {
+      (void)hipEventRecord(ev_up, up);
+      (void)hipStreamWaitEvent(st, ev_up, 0);
     }
     nfhmm_status s = engine_begin(ctx, started, st);
     std::vector<Job *> zero_iter;
@@ -1000,18 +1054,21 @@ void scheduler(nfhmm_ctx *ctx) {
     for (Job *j : act)
       if (r - j->start_round + 1 == j->d.iters) fin.push_back(j);
     if (s == NFHMM_OK) s = engine_finish(ctx, fin, st);
-    for (Job *j : fin) {
-      if (s == NFHMM_OK) s = download_staged(ctx, *j, st);
-      pending.push_back({j, nullptr});
-    }
-    // one marker for everything queued so far: finished jobs' outputs and the
-    // last work of cancelled ones are complete once it has passed
+    // one marker for everything queued so far: the last work of finished and
+    // cancelled jobs is complete once it has passed; their outputs follow on the
+    // download stream
     hipEvent_t mark = new_event();
     (void)hipEventRecord(mark, st);
+    for (Job *j : fin) pending.push_back({j, nullptr});
+    bool fresh = false;
+    for (auto &pd : pending) fresh |= !pd.ev;
+    if (fresh) (void)hipStreamWaitEvent(down, mark, 0);
+    for (Job *j : fin)
+      if (s == NFHMM_OK) s = download_staged(ctx, *j, down);
     for (auto &pd : pending)
       if (!pd.ev) {
         pd.ev = new_event();
-        (void)hipEventRecord(pd.ev, st);
+        (void)hipEventRecord(pd.ev, down);
       }
     inflight.push_back(mark);
     {
@@ -1030,6 +1087,8 @@ void scheduler(nfhmm_ctx *ctx) {
       spare.push_back(inflight.front());
       inflight.pop_front();
     }
+    if (idle)   // nothing to run: wait for the outputs still coming down
+      for (auto &pd : pending) (void)hipEventSynchronize(pd.ev);
     // retire the jobs whose outputs have landed
     std::vector<Pending> still;
     for (auto &pd : pending) {
@@ -1054,6 +1113,9 @@ void scheduler(nfhmm_ctx *ctx) {
     pending.swap(still);
   }
   (void)hipStreamSynchronize(st);
+  (void)hipStreamSynchronize(up);
+  (void)hipStreamSynchronize(down);
+  (void)hipEventDestroy(ev_up);
   for (hipEvent_t e : inflight) (void)hipEventDestroy(e);
   for (hipEvent_t e : spare) (void)hipEventDestroy(e);
 }
@@ -1189,6 +1251,7 @@ nfhmm_status nfhmm_fit_batch(nfhmm_ctx *ctx, int n, const nfhmm_problem *ps, nfh
     if (s != NFHMM_OK) return s;
     jobs.push_back(&j);
   }
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
   nfhmm_status s = NFHMM_OK;
   for (Job *j : jobs)
     if ((s = arena_alloc(ctx, *j, false)) != NFHMM_OK) break;
@@ -1218,6 +1281,7 @@ nfhmm_status nfhmm_fit_batch_device(nfhmm_ctx *ctx, int n, const nfhmm_problem *
     if (s != NFHMM_OK) return fail(s, "job %d: %s", i, g_err.c_str());
     jobs.push_back(&j);
   }
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
   nfhmm_status s = NFHMM_OK;
   for (Job *j : jobs)
     if ((s = arena_alloc(ctx, *j, true)) != NFHMM_OK) break;
@@ -1236,12 +1300,10 @@ nfhmm_status nfhmm_submit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precisio
                           uint64_t *job_id) {
   if (!ctx || !job_id) return fail(NFHMM_E_INVALID, "ctx or job_id is NULL");
   std::string m;
-  if (validate_host(p, &m) != NFHMM_OK) return fail(NFHMM_E_INVALID, "%s", m.c_str());
+  if (validate_host(p, &m, false) != NFHMM_OK) return fail(NFHMM_E_INVALID, "%s", m.c_str());
   std::unique_ptr<Job> j(new Job());
   nfhmm_status s = make_job(p, prec, r, true, true, *j);
   if (s != NFHMM_OK) return s;
-  if (ctx->budget && j->L.total > ctx->budget)
-    return fail(NFHMM_E_NOMEM, "job needs %zu device bytes, budget is %zu", j->L.total, ctx->budget);
   const Dims &d = j->d;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -1255,10 +1317,17 @@ nfhmm_status nfhmm_submit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precisio
   j->hA.reset(new float[nA]);
   j->hpi.reset(new float[npi]);
   if (ni) j->hinit.reset(new float[ni]);
-  const CopyPool::Piece pc[5] = {{j->hV.get(), p->V, nV * 4}, {j->hW.get(), p->W, nW * 4},
+  const CopyPool::Piece pc[5] = {{j->hV.get(), p->V, nV * 4, true}, {j->hW.get(), p->W, nW * 4},
                                  {j->hA.get(), p->A, nA * 4}, {j->hpi.get(), p->pi, npi * 4},
                                  {j->hinit.get(), p->alpha_init, ni * 4}};
-  ctx->copies->run(pc, 5);
+  if (!ctx->copies->run(pc, 5)) {   // V failed the check made while copying it: name the entry
+    validate_host(p, &m);
+    return fail(NFHMM_E_INVALID, "%s", m.c_str());
+  }
+  // a valid job that can never fit the budget (checked after the inputs, so
+  // that an invalid input is reported as such whatever its size)
+  if (ctx->budget && j->L.total > ctx->budget)
+    return fail(NFHMM_E_NOMEM, "job needs %zu device bytes, budget is %zu", j->L.total, ctx->budget);
   j->prob.V = j->hV.get();
   j->prob.W = j->hW.get();
   j->prob.A = j->hA.get();
@@ -1357,6 +1426,7 @@ nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float
   if (!ctx || !logev || !A || !pi) return fail(NFHMM_E_INVALID, "NULL argument");
   if (N < 1 || N > NFHMM_MAX_STATES || T < 1 || T > (1 << 24)) return fail(NFHMM_E_INVALID, "bad N or T");
   HIP_OK(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
   hipStream_t st = ctx->stream;
   const size_t T_ = (size_t)T;
   // layout: logev, A, pi, phi, ev, sh, fwd, bwd, nrm, post

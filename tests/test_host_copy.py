@@ -1,7 +1,9 @@
 """The serving path's host copy pool (csrc/host_copy.h), built for the host with g++.
 
 Several threads copy pieces of random sizes through one pool at once; every
-byte must arrive.  A second build runs under ThreadSanitizer (host code only).
+byte must arrive, and the float check made while copying must flag exactly the
+copies that hold a planted negative or non-finite value in a checked piece.  A
+second build runs under ThreadSanitizer (host code only).
 """
 import os
 import subprocess
