@@ -319,6 +319,99 @@ __device__ void gemm_nt_f32(const float *__restrict__ A, int lda, int arows, int
   }
 }
 
+// f32 main loop with the operands loaded straight into LDS (global_load_lds,
+// 16 bytes per lane; no staging registers and no LDS store instructions).  A
+// wavefront instruction fills eight rows of 32 floats, contiguous in LDS, so the
+// rows are not padded; instead row r keeps the 16-byte chunk ch of its global
+// row at position ch ^ (r & 7), which lets the fragment reads of eight
+// consecutive rows fall on eight different bank groups.  Rows past the end of
+// an operand read its last row (their outputs are not stored); the k range must
+// be whole stages of 32.
+typedef __attribute__((address_space(1))) const void gcvoid;
+typedef __attribute__((address_space(3))) void lvoid;
+constexpr int kDmaRow = 32;   // floats per LDS row (one k-stage)
+
+template <int ROWS>
+__device__ __forceinline__ void dma_rows(const float *__restrict__ src, int ld, int nrows, int row0, int k,
+                                         float *lds, int wave, int lane) {
+  constexpr int kGroups = ROWS / 32;   // eight-row groups per wavefront
+#pragma unroll
+  for (int h = 0; h < kGroups; ++h) {
+    const int g = wave * kGroups + h;
+    const int r = g * 8 + (lane >> 3);
+    const int ch = (lane & 7) ^ (r & 7);
+    const int grow = min(row0 + r, nrows - 1);
+    __builtin_amdgcn_global_load_lds((gcvoid *)(src + (size_t)grow * ld + k + ch * 4),
+                                     (lvoid *)(lds + g * 8 * kDmaRow), 16, 0, 0);
+  }
+}
+
+template <int WM, int WN>
+__device__ __forceinline__ void mma_stage_f32_dma(const float *As, const float *Bs, const Frag &f,
+                                                  floatx4 (&acc)[WM][WN]) {
+  const int sw = f.lr & 7;   // every fragment row is 16-aligned, so row & 7 = lr & 7
+#pragma unroll
+  for (int kk = 0; kk < kBKf; kk += 16) {
+    const int chunk = ((kk >> 2) + f.lq) ^ sw;
+    float4 a[WM], b[WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+      a[i] = *(const float4 *)(As + (f.wr * 16 * WM + i * 16 + f.lr) * kDmaRow + chunk * 4);
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+      b[j] = *(const float4 *)(Bs + (f.wc * 16 * WN + j * 16 + f.lr) * kDmaRow + chunk * 4);
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+          const float av = p == 0 ? a[i].x : p == 1 ? a[i].y : p == 2 ? a[i].z : a[i].w;
+          const float bv = p == 0 ? b[j].x : p == 1 ? b[j].y : p == 2 ? b[j].z : b[j].w;
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
+        }
+  }
+}
+
+template <int WM, int WN>
+__device__ void gemm_nt_f32_dma(const float *__restrict__ A, int lda, int arows, int row0, const float *__restrict__ B,
+                                int ldb, int bcols, int col0, int kb, int ke, floatx4 (&acc)[WM][WN]) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  // two stages in four separate arrays, and the loop unrolled by two, so that
+  // every access names its buffer and the compiler can tell that the loads in
+  // flight into one stage do not touch the stage being read
+  __shared__ __attribute__((aligned(16))) float As0[BM * kDmaRow], As1[BM * kDmaRow];
+  __shared__ __attribute__((aligned(16))) float Bs0[BN * kDmaRow], Bs1[BN * kDmaRow];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Frag f = frag_of(tid);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  dma_rows<BM>(A, lda, arows, row0, kb, As0, wave, lane);
+  dma_rows<BN>(B, ldb, bcols, col0, kb, Bs0, wave, lane);
+  __syncthreads();
+  for (int k = kb; k < ke; k += 2 * kBKf) {
+    if (k + kBKf < ke) {   // stage 1 was last read before the previous barrier
+      dma_rows<BM>(A, lda, arows, row0, k + kBKf, As1, wave, lane);
+      dma_rows<BN>(B, ldb, bcols, col0, k + kBKf, Bs1, wave, lane);
+    }
+    mma_stage_f32_dma<WM, WN>(As0, Bs0, f, acc);
+    // the MFMAs stay before the barrier (and its wait for the loads in flight),
+    // which the scheduler would otherwise move above them
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();   // each wavefront waits for its own loads first
+    if (k + kBKf >= ke) break;
+    if (k + 2 * kBKf < ke) {
+      dma_rows<BM>(A, lda, arows, row0, k + 2 * kBKf, As0, wave, lane);
+      dma_rows<BN>(B, ldb, bcols, col0, k + 2 * kBKf, Bs0, wave, lane);
+    }
+    mma_stage_f32_dma<WM, WN>(As1, Bs1, f, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+  }
+}
+
 template <int ROWS>
 __device__ __forceinline__ void gload_bf16(const uint16_t *__restrict__ src, int ld, int nrows, int row0, int k,
                                            int kend, int tid, uint4 (&r)[ROWS / 32]) {
@@ -415,7 +508,7 @@ __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
   const int row0 = rt * BM, col0 = ct * BN;
   floatx4 acc[WM][WN];
   if constexpr (kBF16) gemm_nt_bf16<WM, WN>(J.Wfm_h, J.Mp, J.Fm, row0, J.wh, J.Mp, J.T, col0, J.Mp, acc);
-  else gemm_nt_f32<WM, WN, false>(J.Wfm, J.Mp, J.Fm, row0, J.w, J.Mp, J.T, col0, 0, J.Mp, acc);
+  else gemm_nt_f32_dma<WM, WN>(J.Wfm, J.Mp, J.Fm, row0, J.w, J.Mp, J.T, col0, 0, J.Mp, acc);
 
   const Frag f = frag_of(threadIdx.x);
   __shared__ Comp part[2][BN];
@@ -491,7 +584,7 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
   const int row0 = rt * BM, col0 = ct * BN;
   floatx4 acc[WM][WN];
   if constexpr (kBF16) gemm_nt_bf16<WM, WN>(J.Wmf_h, J.Fp, J.Mp, row0, J.Rh, J.Fp, J.T, col0, J.Fm, acc);
-  else gemm_nt_f32<WM, WN, false>(J.Wmf, J.Fp, J.Mp, row0, J.R, J.Fp, J.T, col0, 0, J.Fm, acc);
+  else gemm_nt_f32_dma<WM, WN>(J.Wmf, J.Fp, J.Mp, row0, J.R, J.Fp, J.T, col0, 0, J.Fm, acc);
   const Frag f = frag_of(threadIdx.x);
   __shared__ Comp part[2][BN];
 #pragma unroll
