@@ -223,7 +223,7 @@ __device__ __forceinline__ Frag frag_of(int tid) {
 }
 
 constexpr int kBKf = 32, kLdsF = kBKf + 4;          // f32: 32 k per stage, rows padded
-constexpr int kBKh = 64, kLdsH = kBKh + 8;          // bf16: 64 k per stage
+constexpr int kBKh = 64;                            // bf16: 64 k per stage
 
 // ROWS x 32 floats: thread tid loads rows (tid/8) + 32h, float4 column (tid%8)
 template <int ROWS, bool kMasked>
@@ -412,34 +412,41 @@ __device__ void gemm_nt_f32_dma(const float *__restrict__ A, int lda, int arows,
   }
 }
 
+// bf16 main loop with the same direct-to-LDS scheme: a k-stage of 64 values is
+// again eight 16-byte chunks per row.  kend is a multiple of 32; a final half
+// stage loads the chunks below kend and stores zeros over the rest.
 template <int ROWS>
-__device__ __forceinline__ void gload_bf16(const uint16_t *__restrict__ src, int ld, int nrows, int row0, int k,
-                                           int kend, int tid, uint4 (&r)[ROWS / 32]) {
-  const int rr = tid >> 3, c = (tid & 7) * 8;
+__device__ __forceinline__ void dma_rows_h(const uint16_t *__restrict__ src, int ld, int nrows, int row0, int k,
+                                           int kend, uint16_t *lds, int wave, int lane) {
+  constexpr int kGroups = ROWS / 32;
 #pragma unroll
-  for (int h = 0; h < ROWS / 32; ++h) {
-    const int row = row0 + rr + 32 * h, kk = k + c;
-    r[h] = (row < nrows && kk < kend) ? *(const uint4 *)(src + (size_t)row * ld + kk) : make_uint4(0, 0, 0, 0);
+  for (int h = 0; h < kGroups; ++h) {
+    const int g = wave * kGroups + h;
+    const int r = g * 8 + (lane >> 3);
+    const int ch = (lane & 7) ^ (r & 7);
+    const int grow = min(row0 + r, nrows - 1);
+    uint16_t *base = lds + g * 8 * kBKh;
+    if (k + ch * 8 < kend)
+      __builtin_amdgcn_global_load_lds((gcvoid *)(src + (size_t)grow * ld + k + ch * 8), (lvoid *)base, 16, 0, 0);
+    else
+      *(uint4 *)(base + lane * 8) = make_uint4(0, 0, 0, 0);
   }
 }
-template <int ROWS>
-__device__ __forceinline__ void sstore_bf16(uint16_t *lds, int tid, const uint4 (&r)[ROWS / 32]) {
-  const int rr = tid >> 3, c = (tid & 7) * 8;
-#pragma unroll
-  for (int h = 0; h < ROWS / 32; ++h) *(uint4 *)(lds + (rr + 32 * h) * kLdsH + c) = r[h];
-}
+
 template <int WM, int WN>
-__device__ __forceinline__ void mma_stage_bf16(const uint16_t *As, const uint16_t *Bs, const Frag &f,
-                                               floatx4 (&acc)[WM][WN]) {
+__device__ __forceinline__ void mma_stage_bf16_dma(const uint16_t *As, const uint16_t *Bs, const Frag &f,
+                                                   floatx4 (&acc)[WM][WN]) {
+  const int sw = f.lr & 7;
 #pragma unroll
   for (int kk = 0; kk < kBKh; kk += 32) {
+    const int chunk = ((kk >> 3) + f.lq) ^ sw;
     bf16x8 a[WM], b[WN];
 #pragma unroll
     for (int i = 0; i < WM; ++i)
-      a[i] = *(const bf16x8 *)(As + (f.wr * 16 * WM + i * 16 + f.lr) * kLdsH + kk + f.lq * 8);
+      a[i] = *(const bf16x8 *)(As + (f.wr * 16 * WM + i * 16 + f.lr) * kBKh + chunk * 8);
 #pragma unroll
     for (int j = 0; j < WN; ++j)
-      b[j] = *(const bf16x8 *)(Bs + (f.wc * 16 * WN + j * 16 + f.lr) * kLdsH + kk + f.lq * 8);
+      b[j] = *(const bf16x8 *)(Bs + (f.wc * 16 * WN + j * 16 + f.lr) * kBKh + chunk * 8);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -448,42 +455,39 @@ __device__ __forceinline__ void mma_stage_bf16(const uint16_t *As, const uint16_
 }
 
 template <int WM, int WN>
-__device__ void gemm_nt_bf16(const uint16_t *__restrict__ A, int lda, int arows, int row0,
-                             const uint16_t *__restrict__ B, int ldb, int bcols, int col0, int kend,
-                             floatx4 (&acc)[WM][WN]) {
+__device__ void gemm_nt_bf16_dma(const uint16_t *__restrict__ A, int lda, int arows, int row0,
+                                 const uint16_t *__restrict__ B, int ldb, int bcols, int col0, int kend,
+                                 floatx4 (&acc)[WM][WN]) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
-  __shared__ uint16_t As[2][BM * kLdsH];
-  __shared__ uint16_t Bs[2][BN * kLdsH];
-  const int tid = threadIdx.x;
+  __shared__ __attribute__((aligned(16))) uint16_t As0[BM * kBKh], As1[BM * kBKh];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs0[BN * kBKh], Bs1[BN * kBKh];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const Frag f = frag_of(tid);
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  uint4 ra[BM / 32], rb[BN / 32];
-  gload_bf16<BM>(A, lda, arows, row0, 0, kend, tid, ra);
-  gload_bf16<BN>(B, ldb, bcols, col0, 0, kend, tid, rb);
-  sstore_bf16<BM>(As[0], tid, ra);
-  sstore_bf16<BN>(Bs[0], tid, rb);
+  dma_rows_h<BM>(A, lda, arows, row0, 0, kend, As0, wave, lane);
+  dma_rows_h<BN>(B, ldb, bcols, col0, 0, kend, Bs0, wave, lane);
   __syncthreads();
-  int buf = 0;
-  for (int k = 0; k < kend; k += kBKh) {
-    const int kn = k + kBKh;
-    const bool more = kn < kend;
-    if (more) {
-      gload_bf16<BM>(A, lda, arows, row0, kn, kend, tid, ra);
-      gload_bf16<BN>(B, ldb, bcols, col0, kn, kend, tid, rb);
+  for (int k = 0; k < kend; k += 2 * kBKh) {
+    if (k + kBKh < kend) {
+      dma_rows_h<BM>(A, lda, arows, row0, k + kBKh, kend, As1, wave, lane);
+      dma_rows_h<BN>(B, ldb, bcols, col0, k + kBKh, kend, Bs1, wave, lane);
     }
-    mma_stage_bf16<WM, WN>(As[buf], Bs[buf], f, acc);
-    if (more) {
-      sstore_bf16<BM>(As[buf ^ 1], tid, ra);
-      sstore_bf16<BN>(Bs[buf ^ 1], tid, rb);
-    }
+    mma_stage_bf16_dma<WM, WN>(As0, Bs0, f, acc);
+    __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
-    buf ^= 1;
+    if (k + kBKh >= kend) break;
+    if (k + 2 * kBKh < kend) {
+      dma_rows_h<BM>(A, lda, arows, row0, k + 2 * kBKh, kend, As0, wave, lane);
+      dma_rows_h<BN>(B, ldb, bcols, col0, k + 2 * kBKh, kend, Bs0, wave, lane);
+    }
+    mma_stage_bf16_dma<WM, WN>(As1, Bs1, f, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
   }
 }
-
 
 // ------------------------------------------------------------------ Eq. 7: Lambda, R
 // Rows l (frequency, [0, Fm)), columns t (frames), k over all M elements.
@@ -491,7 +495,11 @@ __device__ void gemm_nt_bf16(const uint16_t *__restrict__ A, int lda, int arows,
 // fill the chip.  Either way the per-frame partials of sum V ln Lambda go to one
 // slot per 64 bins (nsl slots), so the bound does not depend on the tile chosen.
 template <bool kBF16, int WM, int WN>
-__global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
+#ifndef NFHMM_SPEC_WAVES
+#define NFHMM_SPEC_WAVES 2
+#endif
+// two blocks of four wavefronts per CU fit the LDS; hold the registers to that
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NFHMM_SPEC_WAVES))) void k_spectrum(WorkList wl) {
   static_assert(WM == 2 || WM == 4, "a wave row covers 32 or 64 bins");
   constexpr int BM = 32 * WM, BN = 32 * WN;
   const int b = xcd_remap(blockIdx.x, wl.total);
@@ -507,7 +515,7 @@ __global__ __launch_bounds__(256) void k_spectrum(WorkList wl) {
   const int rt = tile % nrt, ct = tile / nrt;
   const int row0 = rt * BM, col0 = ct * BN;
   floatx4 acc[WM][WN];
-  if constexpr (kBF16) gemm_nt_bf16<WM, WN>(J.Wfm_h, J.Mp, J.Fm, row0, J.wh, J.Mp, J.T, col0, J.Mp, acc);
+  if constexpr (kBF16) gemm_nt_bf16_dma<WM, WN>(J.Wfm_h, J.Mp, J.Fm, row0, J.wh, J.Mp, J.T, col0, J.Mp, acc);
   else gemm_nt_f32_dma<WM, WN>(J.Wfm, J.Mp, J.Fm, row0, J.w, J.Mp, J.T, col0, 0, J.Mp, acc);
 
   const Frag f = frag_of(threadIdx.x);
@@ -583,7 +591,7 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
   const int rt = tile % nrt, ct = tile / nrt;
   const int row0 = rt * BM, col0 = ct * BN;
   floatx4 acc[WM][WN];
-  if constexpr (kBF16) gemm_nt_bf16<WM, WN>(J.Wmf_h, J.Fp, J.Mp, row0, J.Rh, J.Fp, J.T, col0, J.Fm, acc);
+  if constexpr (kBF16) gemm_nt_bf16_dma<WM, WN>(J.Wmf_h, J.Fp, J.Mp, row0, J.Rh, J.Fp, J.T, col0, J.Fm, acc);
   else gemm_nt_f32_dma<WM, WN>(J.Wmf, J.Fp, J.Mp, row0, J.R, J.Fp, J.T, col0, 0, J.Fm, acc);
   const Frag f = frag_of(threadIdx.x);
   __shared__ Comp part[2][BN];
