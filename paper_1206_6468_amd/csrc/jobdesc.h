@@ -38,7 +38,7 @@ constexpr int kMaxSources = 8;
 // columns each.  Lambda (spectrum): bins x frames; counts: elements x frames.
 #ifndef NFHMM_SPEC_WM
 #define NFHMM_SPEC_WM 4
-#define NFHMM_SPEC_WN 4
+#define NFHMM_SPEC_WN 2
 #endif
 #ifndef NFHMM_CNT_WM
 #define NFHMM_CNT_WM 2

@@ -491,7 +491,7 @@ __device__ void gemm_nt_bf16_dma(const uint16_t *__restrict__ A, int lda, int ar
 
 // ------------------------------------------------------------------ Eq. 7: Lambda, R
 // Rows l (frequency, [0, Fm)), columns t (frames), k over all M elements.
-// Two block tiles: 128 x 128 for large batches, 64 x 64 when the batch would not
+// Two block tiles: 128 bins x 64 frames for large batches, 64 x 64 when the batch would not
 // fill the chip.  Either way the per-frame partials of sum V ln Lambda go to one
 // slot per 64 bins (nsl slots), so the bound does not depend on the tile chosen.
 template <bool kBF16, int WM, int WN>

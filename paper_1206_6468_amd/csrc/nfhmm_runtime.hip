@@ -365,8 +365,8 @@ struct Table {
   hipEvent_t ready = nullptr;
 };
 
-// below this many 128 x 128 blocks the spectrum runs on 64 x 64 tiles (four
-// times the blocks), so that a small batch still spreads over the 256 CUs
+// below this many 128 x 64 blocks the spectrum runs on 64 x 64 tiles (twice
+// the blocks), so that a small batch still spreads over the 256 CUs
 constexpr int kSmallBatchBlocks = 256;
 
 int spec_blocks(const JobDesc &D, bool small) {

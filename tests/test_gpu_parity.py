@@ -304,7 +304,7 @@ def test_batch_is_bitwise_invariant(L, ctx):
 
 def test_bench_launch_configuration(L, ctx):
     """The bench's configuration: 32 config-1 jobs in one batch (two stream lanes
-    of 16, 128 x 128 spectrum tiles).  One step from oracle alpha-hats: sampled
+    of 16, 128 x 64 spectrum tiles).  One step from oracle alpha-hats: sampled
     jobs against the FP64 oracle at the FP32 bounds, and every job bitwise equal
     to the same job fitted alone (small spectrum tiles, one lane) -- except the
     bound, whose per-64-bin partials are summed in a tile-dependent order."""
