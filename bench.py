@@ -91,7 +91,7 @@ def _gen4(j):
 
 
 def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
-    """Serving form: n_jobs config-4 jobs (S in {2,3}, T in [200, 4000], 50
+    """Serving form: n_jobs serving-mix jobs (S in {2,3}, T in [200, 4000], 50
     iterations, BF16 contraction) through nfhmm_submit / nfhmm_wait on a context
     with a device-memory budget.  First all jobs at once (saturated throughput),
     then Poisson arrivals at `load` x the saturated job rate (latency from the
@@ -102,7 +102,7 @@ def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
 
     import numpy as np
 
-    log(f"serving: generating {n_jobs} config-4 problems")
+    log(f"serving: generating {n_jobs} serving-mix problems")
     with Pool(min(16, os.cpu_count() or 1)) as pool:
         probs = pool.map(_gen4, range(n_jobs))
     work = sum(p["T"] * p["iters"] for p in probs)
@@ -172,7 +172,7 @@ def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
 
 
 def cpu_baseline(seconds_target=15.0, one_thread=False):
-    """The FP64 oracle on the host cores: one config-1 job, one warm-up iteration,
+    """The FP64 oracle on the host cores: one paper-typical job, one warm-up iteration,
     then iterations until about `seconds_target` seconds have passed (all BLAS
     threads, or one)."""
     import contextlib
@@ -207,7 +207,7 @@ def _cpu_run(p, seconds_target, threads, O, np):
     dt = time.perf_counter() - t0
     assert np.all(np.isfinite(alpha))
     return {"value": p["T"] * n / dt, "unit": "frame-iterations/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"config-1 job 0 (S=2,N=40,K=10,F=513,T=1000): 1 warm-up + {n} timed FP64 iterations, "
+            "sample": f"paper-typical job 0 (S=2,N=40,K=10,F=513,T=1000): 1 warm-up + {n} timed FP64 iterations, "
                       f"{dt:.1f} s, {threads} BLAS thread(s)"}
 
 
@@ -216,10 +216,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--jobs", type=int, default=32, help="concurrent config-1 jobs per step")
+    ap.add_argument("--jobs", type=int, default=32, help="concurrent paper-typical jobs (S=2, N=40, K=10, F=513, T=1000) per step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="skip the BF16 and single-job forms")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving (config 4) measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-one-lane", action="store_true", help="skip the one-lane roofline pass")
     ap.add_argument("--serving-jobs", type=int, default=256)
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
@@ -228,7 +228,7 @@ def main():
                          "kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+        print("bench.py measures one GPU: the library runs on a single MI355X and has no "
               "multi-GPU path (--gpus must be 1).", file=sys.stderr)
         sys.exit(2)
 
@@ -247,7 +247,7 @@ def main():
 
     from paper_1206_6468_amd import nfhmm as L
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    log(f"generating {args.jobs} config-1 problems")
+    log(f"generating {args.jobs} paper-typical problems")
     probs = make_jobs(1, args.jobs)
     S, N, K, F, T, iters = (probs[0][k] for k in ("S", "N", "K", "F", "T", "iters"))
     M = S * N * K
@@ -277,7 +277,7 @@ def main():
     n_g, ms_g = prof_c[gemm]
     flops_launch = flops_per_job_iter[gemm] * J * iters * args.steps / max(n_g, 1)
     ach = flops_launch / (ms_g / max(n_g, 1) * 1e-3)
-    workload = f"config1-x{J}"
+    workload = f"S{S}-N{N}-K{K}-F{F}-T{T}-x{J}"   # the paper-typical job, J of them in one batch
     roofline = {"bound": "mfma", "kernel": f"k_{gemm}", "achieved": ach / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": _traffic_for(f"k_{gemm}", workload),
                 "largest_summed_time": f"k_{dom}", "kernels": rows,
@@ -322,7 +322,7 @@ def main():
         sweep["1"] = extra["single_job_fp32"]["value"]
         sweep[str(J)] = value
         extra["jobs_sweep_fp32"] = dict(sorted(sweep.items(), key=lambda kv: int(kv[0])))
-        # config 3 (S=2, N=60, K=20, F=1025, T=4000), one job, timed over 10 iterations
+        # the long precision-form job (S=2, N=60, K=20, F=1025, T=4000), one job, timed over 10 iterations
         p3 = dict(make_jobs(3, 1)[0], iters=10)
         j3 = [L.DeviceJob(p3)]
         c3 = {"iterations_timed": 10}
@@ -330,7 +330,7 @@ def main():
             dt3, pr3 = time_batch(L, ctx, j3, prec, 2, 1, profile=True)
             c3[prec] = {"value": p3["T"] * 10 / dt3, "ms_per_10_iterations": dt3 * 1e3,
                         "kernels_ms": {k: v[1] / 2 for k, v in pr3.items()}}
-        extra["config3_single_job"] = c3
+        extra["precision_form_single_job"] = c3
         del j3
 
     out = {

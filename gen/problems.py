@@ -22,7 +22,11 @@ import numpy as np
 
 SEED_BASE = 12066468
 
-# name -> defaults of each workload.  Config 4 draws S and T per job.
+# workload id -> defaults.  0: the small case the FP64 oracle runs in seconds;
+# 1: the paper-typical job (1024-point STFT, 40 states of 10 elements, 1000
+# frames); 2: the same with three sources; 3: the long precision-form job
+# (2048-point STFT, 60 states of 20 elements, 4000 frames); 4: the serving mix,
+# which draws S and T per job.  The id also seeds every draw.
 CONFIGS = {
     0: dict(S=2, N=5, K=8, F=129, T=100, iters=20, dict_conc=0.5, trans="dense",
             diag=0.8, weights="bayes", loud=False, quanta=10_000),
