@@ -205,9 +205,11 @@ __global__ void k_tail_ones(JobDesc J) {
 // ------------------------------------------------------------------ MFMA tiles
 // C[i][j] = sum_k A[i][k] B[j][k] for a (32*WM) x (32*WN) block tile: 256 threads
 // = 4 waves in a 2x2 grid, each wave (16*WM) x (16*WN) = WM x WN MFMA 16x16 tiles
-// held in accumulator registers.  Operand k-slices are staged through LDS; a
-// larger wave tile reuses every fragment read from LDS across more MFMAs, which
-// keeps the contraction under the LDS bandwidth of a CU.  Within every 16 (f32)
+// held in accumulator registers.  Operand k-slices pass through LDS: loaded
+// straight into it for the two contractions of every iteration (below,
+// gemm_nt_f32_dma / gemm_nt_bf16_dma), through registers with padded rows for the
+// once-per-job reconstruction, whose k range is arbitrary.  A larger wave tile
+// reuses every fragment read from LDS across more MFMAs.  Within every 16 (f32)
 // or 32 (bf16) wide k-chunk lane (r, q) of a fragment supplies the q-th group of
 // consecutive k; A and B use the same grouping, so every k is summed once.
 // Output tile element (row, col) lives in lane (lr, lq) of wave (wr, wc) at
@@ -281,7 +283,9 @@ __device__ __forceinline__ void mma_stage_f32(const float *As, const float *Bs, 
   }
 }
 
-// f32 main loop over k in [kb, ke); kMasked selects the elementwise k mask
+// f32 main loop over k in [kb, ke) through registers (the reconstruction: its k
+// range is one job's elements, in any position); kMasked selects the elementwise
+// k mask
 template <int WM, int WN, bool kMasked>
 __device__ void gemm_nt_f32(const float *__restrict__ A, int lda, int arows, int row0, const float *__restrict__ B,
                             int ldb, int bcols, int col0, int kb, int ke, floatx4 (&acc)[WM][WN]) {
