@@ -171,6 +171,53 @@ def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
     }
 
 
+def stft_bench(L, ctx, jobs=32, sources=2, frames=1000, nfft=1024, hop=256, reps=5):
+    """The time-frequency front and back end at the paper's analysis (16 kHz,
+    64 ms windows, 16 ms hop): the STFT of `jobs` mixtures of `frames` frames in
+    one call, then the inverse of `sources` masked spectrograms per mixture with
+    its phase, all mixtures in one call, on device-resident data, timed with HIP
+    events on the stream the calls use.  Algorithmic bytes: the forward reads
+    every sample once and writes |X| and arg X; the inverse reads the magnitudes
+    and each mixture's phase once and writes the signals."""
+    import torch
+    F = nfft // 2 + 1
+    n = (frames - 1) * hop + nfft
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev).manual_seed(7)
+    x = torch.randn((jobs, n), generator=g, device=dev)
+    mag = torch.empty((jobs, frames, F), device=dev)
+    phase = torch.empty_like(mag)
+    src = torch.rand((jobs, sources, frames, F), generator=g, device=dev)
+    y = torch.empty((jobs, sources, n), device=dev)
+    torch.cuda.synchronize()
+    # a stream of its own: torch's default stream has the handle 0, which the
+    # library reads as "no stream" (its own), and the events would not bracket it
+    st = torch.cuda.Stream()
+    L.stft_device(ctx, x, mag, phase, nfft, hop, stream=st)
+    L.istft_device(ctx, src, phase, y, nfft, hop, stream=st)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record(st)
+    for _ in range(reps):
+        L.stft_device(ctx, x, mag, phase, nfft, hop, stream=st)
+    e[1].record(st)
+    for _ in range(reps):
+        L.istft_device(ctx, src, phase, y, nfft, hop, stream=st)
+    e[2].record(st)
+    torch.cuda.synchronize()
+    ms_f = e[0].elapsed_time(e[1]) / reps
+    ms_i = e[1].elapsed_time(e[2]) / reps
+    bytes_f = jobs * n * 4 + 2 * jobs * frames * F * 4
+    bytes_i = jobs * sources * frames * F * 4 + jobs * frames * F * 4 + jobs * sources * n * 4
+    return {
+        "workload": f"{jobs} mixtures of {n} samples (T={frames}, nfft={nfft}, hop={hop}), {sources} sources each",
+        "stft_ms": ms_f, "stft_frames_per_s": jobs * frames / (ms_f * 1e-3),
+        "stft_gbps": bytes_f / (ms_f * 1e-3) / 1e9, "stft_frac_hbm": bytes_f / (ms_f * 1e-3) / PEAK_HBM,
+        "istft_ms": ms_i, "istft_frames_per_s": jobs * sources * frames / (ms_i * 1e-3),
+        "istft_gbps": bytes_i / (ms_i * 1e-3) / 1e9, "istft_frac_hbm": bytes_i / (ms_i * 1e-3) / PEAK_HBM,
+    }
+
+
 def cpu_baseline(seconds_target=15.0, one_thread=False):
     """The FP64 oracle on the host cores: one paper-typical job, one warm-up iteration,
     then iterations until about `seconds_target` seconds have passed (all BLAS
@@ -332,6 +379,8 @@ def main():
                         "kernels_ms": {k: v[1] / 2 for k, v in pr3.items()}}
         extra["precision_form_single_job"] = c3
         del j3
+        log("time-frequency front and back end")
+        extra["stft"] = stft_bench(L, ctx)
 
     out = {
         "metric": "VI frame-iterations/s at S=2,N=40,F=513 (FP32 contraction)",

@@ -233,6 +233,50 @@ NFHMM_API nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, c
 NFHMM_API nfhmm_status nfhmm_special_functions(nfhmm_ctx *ctx, int64_t n, const float *x, float *psi,
                                      float *lgam);
 
+/* ------------------------------------------------------------------ time domain */
+
+/* The spectrograms the method works on come from a short-time Fourier transform
+ * (Section 5: 16 kHz audio, 64 ms windows, 16 ms hop, i.e. nfft = 1024, hop = 256,
+ * F = 513 bins), and the separated sources are taken back to the time domain with
+ * the phase of the mixture (Section 1).  Conventions:
+ *   window    periodic Hann, w[i] = (1 - cos(2 pi i / nfft)) / 2;
+ *   framing   frame t covers samples [t hop, t hop + nfft) of the signal, no padding,
+ *             so a signal of n >= nfft samples has T = 1 + (n - nfft) / hop frames
+ *             (integer division; the samples after the last frame are not analysed);
+ *   transform X_t[k] = sum_i w[i] x[t hop + i] exp(-2 pi i k i' / nfft), k = 0..nfft/2;
+ *   inverse   weighted overlap-add: y[i] = sum_t w[j] z_t[j] / sum_t w[j]^2 over the
+ *             frames covering i (j = i - t hop), z_t the inverse transform of the
+ *             Hermitian spectrum mag_t exp(i phase_t) (the imaginary parts of bins 0
+ *             and nfft/2 dropped); y[i] = 0 where no window weight covers i.  With
+ *             hop <= nfft / 2 this inverts the transform exactly where at least one
+ *             frame has w[j] > 0.
+ * nfft is a power of two in [64, 4096], 1 <= hop <= nfft, 1 <= B <= 65535 signals
+ * (or mixtures) processed together; arrays are dense, C order, float32; errors are
+ * NFHMM_E_INVALID for bad sizes and NFHMM_E_DEVICE for a failing HIP call. */
+
+/* Frames of a signal of n samples (0 if n < nfft). */
+NFHMM_API int64_t nfhmm_stft_frames(int32_t nfft, int32_t hop, int64_t n);
+
+/* STFT of B signals x[B][n] (host arrays): mag and phase [B][T][nfft/2 + 1] receive
+ * |X| and arg X (radians, (-pi, pi]). */
+NFHMM_API nfhmm_status nfhmm_stft(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, const float *x,
+                                  int64_t n, float *mag, float *phase);
+
+/* Inverse STFT of B mixtures with S magnitude sets each, mag[B][S][T][nfft/2 + 1]
+ * (e.g. the separated sources V* of each mixture), source (b, s) resynthesised with
+ * its mixture's phase[b][T][nfft/2 + 1]: y[B][S][n] (host arrays).  B * S <= 65535;
+ * T may exceed the frame count of n (frames past the end contribute nothing). */
+NFHMM_API nfhmm_status nfhmm_istft(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, int32_t S,
+                                   const float *mag, const float *phase, int64_t T, float *y, int64_t n);
+
+/* The same on device pointers, ordered on hip_stream (NULL: the context's stream);
+ * they return once the work is queued and allocate nothing. */
+NFHMM_API nfhmm_status nfhmm_stft_device(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, const float *x,
+                                         int64_t n, float *mag, float *phase, void *hip_stream);
+NFHMM_API nfhmm_status nfhmm_istft_device(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, int32_t S,
+                                          const float *mag, const float *phase, int64_t T, float *y, int64_t n,
+                                          void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

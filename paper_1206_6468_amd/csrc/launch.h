@@ -29,4 +29,16 @@ hipError_t launch_finish(const WorkList &frames, const WorkList &tiles, const Wo
 hipError_t launch_special(int64_t n, const float *x, float *psi, float *lg, hipStream_t st);
 hipError_t launch_chain_prep(const JobDesc &J, const float *logev, hipStream_t st);
 
+// Short-time Fourier transform (stft_kernels.hip).  B signals x[B][n]; frame t
+// covers samples [t hop, t hop + nfft); nfft is a power of two in [64, 4096].
+// mag, phase: [B][T][nfft/2 + 1].
+hipError_t launch_stft(int nfft, const float *x, int64_t n, int hop, int T, int B, float *mag, float *phase,
+                       hipStream_t st);
+// Inverse of B mixtures' S magnitude sets mag[B][S][T][nfft/2 + 1], source (b, s)
+// with phase[b][T][nfft/2 + 1]: y[B][S][n] by weighted overlap-add.  B * S <= 65535.
+hipError_t launch_istft(int nfft, const float *mag, const float *phase, int T, int B, int S, int hop, int64_t n,
+                        float *y, hipStream_t st);
+// frames per block of the inverse (a multiple of the frames that cover one sample)
+int istft_run(int nfft, int hop);
+
 }  // namespace nfhmm

@@ -1421,6 +1421,94 @@ nfhmm_status nfhmm_profile_read(nfhmm_ctx *ctx, int kind, int64_t *launches, dou
   return NFHMM_OK;
 }
 
+// ------------------------------------------------------------------ time domain
+namespace {
+bool stft_sizes_ok(int32_t nfft, int32_t hop, int32_t B) {
+  return nfft >= 64 && nfft <= 4096 && (nfft & (nfft - 1)) == 0 && hop >= 1 && hop <= nfft && B >= 1 &&
+         B <= 65535;
+}
+}  // namespace
+
+int64_t nfhmm_stft_frames(int32_t nfft, int32_t hop, int64_t n) {
+  if (nfft <= 0 || hop <= 0 || n < nfft) return 0;
+  return 1 + (n - nfft) / hop;
+}
+
+nfhmm_status nfhmm_stft_device(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, const float *x, int64_t n,
+                               float *mag, float *phase, void *hip_stream) {
+  if (!ctx || !x || !mag || !phase) return fail(NFHMM_E_INVALID, "NULL argument");
+  if (!stft_sizes_ok(nfft, hop, B)) return fail(NFHMM_E_INVALID, "bad nfft, hop or B");
+  const int64_t T = nfhmm_stft_frames(nfft, hop, n);
+  if (T < 1 || T > INT32_MAX) return fail(NFHMM_E_INVALID, "the signal has no whole frame (n < nfft) or too many");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
+  HIP_OK(launch_stft(nfft, x, n, hop, (int)T, B, mag, phase, st));
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_istft_device(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, int32_t S, const float *mag,
+                                const float *phase, int64_t T, float *y, int64_t n, void *hip_stream) {
+  if (!ctx || !mag || !phase || !y) return fail(NFHMM_E_INVALID, "NULL argument");
+  if (!stft_sizes_ok(nfft, hop, B) || S < 1 || (int64_t)B * S > 65535)
+    return fail(NFHMM_E_INVALID, "bad nfft, hop, B or S");
+  if (T < 1 || T > INT32_MAX || n < 1) return fail(NFHMM_E_INVALID, "bad T or n");
+  HIP_OK(hipSetDevice(ctx->device));
+  hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
+  HIP_OK(launch_istft(nfft, mag, phase, (int)T, B, S, hop, n, y, st));
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_stft(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, const float *x, int64_t n,
+                        float *mag, float *phase) {
+  if (!ctx || !x || !mag || !phase) return fail(NFHMM_E_INVALID, "NULL argument");
+  if (!stft_sizes_ok(nfft, hop, B)) return fail(NFHMM_E_INVALID, "bad nfft, hop or B");
+  const int64_t T = nfhmm_stft_frames(nfft, hop, n);
+  if (T < 1 || T > INT32_MAX) return fail(NFHMM_E_INVALID, "the signal has no whole frame (n < nfft) or too many");
+  HIP_OK(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
+  hipStream_t st = ctx->stream;
+  const size_t bx = (size_t)B * n * 4, bo = (size_t)B * T * (nfft / 2 + 1) * 4;
+  char *d = nullptr;
+  HIP_OK(hipMallocAsync((void **)&d, bx + 2 * bo, st));
+  float *dx = reinterpret_cast<float *>(d), *dm = reinterpret_cast<float *>(d + bx),
+        *dp = reinterpret_cast<float *>(d + bx + bo);
+  hipError_t e = hipMemcpyAsync(dx, x, bx, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_stft(nfft, dx, n, hop, (int)T, B, dm, dp, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(mag, dm, bo, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(phase, dp, bo, hipMemcpyDeviceToHost, st);
+  (void)hipFreeAsync(d, st);
+  const hipError_t es = hipStreamSynchronize(st);
+  HIP_OK(e);
+  HIP_OK(es);
+  return NFHMM_OK;
+}
+
+nfhmm_status nfhmm_istft(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, int32_t S, const float *mag,
+                         const float *phase, int64_t T, float *y, int64_t n) {
+  if (!ctx || !mag || !phase || !y) return fail(NFHMM_E_INVALID, "NULL argument");
+  if (!stft_sizes_ok(nfft, hop, B) || S < 1 || (int64_t)B * S > 65535)
+    return fail(NFHMM_E_INVALID, "bad nfft, hop, B or S");
+  if (T < 1 || T > INT32_MAX || n < 1) return fail(NFHMM_E_INVALID, "bad T or n");
+  HIP_OK(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
+  hipStream_t st = ctx->stream;
+  const size_t F = nfft / 2 + 1, bm = (size_t)B * S * T * F * 4, bp = (size_t)B * T * F * 4,
+               by = (size_t)B * S * n * 4;
+  char *d = nullptr;
+  HIP_OK(hipMallocAsync((void **)&d, bm + bp + by, st));
+  float *dm = reinterpret_cast<float *>(d), *dp = reinterpret_cast<float *>(d + bm),
+        *dy = reinterpret_cast<float *>(d + bm + bp);
+  hipError_t e = hipMemcpyAsync(dm, mag, bm, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(dp, phase, bp, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = launch_istft(nfft, dm, dp, (int)T, B, S, hop, n, dy, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(y, dy, by, hipMemcpyDeviceToHost, st);
+  (void)hipFreeAsync(d, st);
+  const hipError_t es = hipStreamSynchronize(st);
+  HIP_OK(e);
+  HIP_OK(es);
+  return NFHMM_OK;
+}
+
 nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float *logev, const float *A,
                                    const float *pi, float *post, double *lnZ) {
   if (!ctx || !logev || !A || !pi) return fail(NFHMM_E_INVALID, "NULL argument");

@@ -40,6 +40,7 @@ SYMBOLS = [
     "nfhmm_fit_batch_device", "nfhmm_fit_device", "nfhmm_submit", "nfhmm_poll",
     "nfhmm_wait", "nfhmm_cancel", "nfhmm_chain_posterior", "nfhmm_special_functions",
     "nfhmm_profile_enable", "nfhmm_profile_read", "nfhmm_profile_select", "nfhmm_set_lanes",
+    "nfhmm_stft_frames", "nfhmm_stft", "nfhmm_istft", "nfhmm_stft_device", "nfhmm_istft_device",
 ]
 K_SPECTRUM, K_COUNTS, K_CHAINS, K_UPDATE, K_POSTERIOR = 0, 1, 2, 3, 4
 KERNEL_KINDS = {"spectrum": K_SPECTRUM, "counts": K_COUNTS, "chains": K_CHAINS, "update": K_UPDATE,
@@ -96,6 +97,20 @@ _lib.nfhmm_chain_posterior.argtypes = [C.c_void_p, C.c_int, C.c_int64, C.c_void_
 _lib.nfhmm_chain_posterior.restype = C.c_int
 _lib.nfhmm_special_functions.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
 _lib.nfhmm_special_functions.restype = C.c_int
+_lib.nfhmm_stft_frames.argtypes = [C.c_int32, C.c_int32, C.c_int64]
+_lib.nfhmm_stft_frames.restype = C.c_int64
+_lib.nfhmm_stft.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64, C.c_void_p,
+                            C.c_void_p]
+_lib.nfhmm_stft.restype = C.c_int
+_lib.nfhmm_istft.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                             C.c_int64, C.c_void_p, C.c_int64]
+_lib.nfhmm_istft.restype = C.c_int
+_lib.nfhmm_stft_device.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_int64,
+                                   C.c_void_p, C.c_void_p, C.c_void_p]
+_lib.nfhmm_stft_device.restype = C.c_int
+_lib.nfhmm_istft_device.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]
+_lib.nfhmm_istft_device.restype = C.c_int
 _lib.nfhmm_profile_select.argtypes = [C.c_void_p, C.c_uint]
 _lib.nfhmm_set_lanes.argtypes = [C.c_void_p, C.c_int]
 _lib.nfhmm_set_lanes.restype = C.c_int
@@ -315,6 +330,67 @@ def special_functions(ctx: Context, x):
     psi, lg = np.empty_like(x), np.empty_like(x)
     _check(_lib.nfhmm_special_functions(ctx.handle, x.size, _ptr(x), _ptr(psi), _ptr(lg)), ctx.handle)
     return psi, lg
+
+
+def stft_frames(nfft: int, hop: int, n: int) -> int:
+    """nfhmm_stft_frames: frames of a signal of n samples."""
+    return int(_lib.nfhmm_stft_frames(int(nfft), int(hop), int(n)))
+
+
+def stft(ctx: Context, x, nfft=1024, hop=256):
+    """nfhmm_stft on host arrays: x [n] or [B][n] -> (mag, phase), each [B][T][nfft/2+1]
+    (the leading B dropped for a 1-d x)."""
+    x = _f32(x)
+    one = x.ndim == 1
+    x2 = x.reshape(1, -1) if one else x
+    B, n = x2.shape
+    T = stft_frames(nfft, hop, n)
+    mag = np.empty((B, max(T, 0), nfft // 2 + 1), dtype=np.float32)
+    phase = np.empty_like(mag)
+    _check(_lib.nfhmm_stft(ctx.handle, nfft, hop, B, _ptr(x2), n, _ptr(mag), _ptr(phase)), ctx.handle)
+    return (mag[0], phase[0]) if one else (mag, phase)
+
+
+def istft(ctx: Context, mag, phase, n, nfft=1024, hop=256):
+    """nfhmm_istft on host arrays.  mag [T][F] with phase [T][F] -> y [n]; mag [S][T][F]
+    (S sources of one mixture) with phase [T][F] -> y [S][n]; mag [B][S][T][F] with
+    phase [B][T][F] -> y [B][S][n]."""
+    mag, phase = _f32(mag), _f32(phase)
+    m4 = mag.reshape((1, 1) + mag.shape) if mag.ndim == 2 else mag.reshape((1,) + mag.shape) if mag.ndim == 3 \
+        else mag
+    B, S, T, F = m4.shape
+    if phase.shape != (T, F) and phase.shape != (B, T, F):
+        raise ValueError(f"phase shape {phase.shape} does not match mag {mag.shape}")
+    y = np.empty((B, S, int(n)), dtype=np.float32)
+    _check(_lib.nfhmm_istft(ctx.handle, nfft, hop, B, S, _ptr(m4), _ptr(phase), T, _ptr(y), int(n)), ctx.handle)
+    return y.reshape(mag.shape[:-2] + (int(n),))
+
+
+def _dev_f32(t, shape, name):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: want a contiguous float32 cuda tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+    return C.c_void_p(t.data_ptr())
+
+
+def stft_device(ctx: Context, x, mag, phase, nfft=1024, hop=256, stream=None):
+    """nfhmm_stft_device on torch tensors: x [B][n], mag / phase [B][T][nfft/2+1] (float32, cuda)."""
+    B, n = x.shape
+    shp = (B, stft_frames(nfft, hop, n), nfft // 2 + 1)
+    h = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(_lib.nfhmm_stft_device(ctx.handle, nfft, hop, B, _dev_f32(x, (B, n), "x"), n,
+                                  _dev_f32(mag, shp, "mag"), _dev_f32(phase, shp, "phase"), h), ctx.handle)
+
+
+def istft_device(ctx: Context, mag, phase, y, nfft=1024, hop=256, stream=None):
+    """nfhmm_istft_device on torch tensors: mag [B][S][T][F], phase [B][T][F], y [B][S][n]."""
+    B, S, T, F = mag.shape
+    n = y.shape[-1]
+    h = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(_lib.nfhmm_istft_device(ctx.handle, nfft, hop, B, S, _dev_f32(mag, (B, S, T, nfft // 2 + 1), "mag"),
+                                   _dev_f32(phase, (B, T, F), "phase"), T, _dev_f32(y, (B, S, n), "y"), n, h),
+           ctx.handle)
 
 
 def profile_enable(ctx: Context, enable: bool = True):

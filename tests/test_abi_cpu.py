@@ -102,3 +102,11 @@ def test_admission_fifo_budget_and_slots(L):
     # no budget: only slots limit
     k, adm = L.admission_plan([10**12] * 3, 0, 0, 0, 2)
     assert (k, adm) == (2, [1, 1, 0])
+
+
+def test_stft_frame_count(L):
+    """nfhmm_stft_frames: T = 1 + (n - nfft) // hop, 0 without a whole frame."""
+    assert L.stft_frames(1024, 256, 256_768) == 1000
+    assert L.stft_frames(1024, 256, 1024) == 1
+    assert L.stft_frames(1024, 256, 1023) == 0
+    assert L.stft_frames(2048, 512, 2048 + 3 * 512 + 511) == 4
