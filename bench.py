@@ -273,6 +273,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the reference "
                          "kernel for scaling HBM byte counters) and exit")
+    ap.add_argument("--stft-only", action="store_true",
+                    help="only time the time-frequency front and back end (STFT of 32 mixtures of "
+                         "1000 frames, inverse of 2 sources each) and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs on a single MI355X and has no "
@@ -294,6 +297,11 @@ def main():
 
     from paper_1206_6468_amd import nfhmm as L
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.stft_only:
+        ctx = L.Context(0)
+        print(json.dumps(stft_bench(L, ctx, reps=max(args.steps, 1))), flush=True)
+        ctx.close()
+        return
     log(f"generating {args.jobs} paper-typical problems")
     probs = make_jobs(1, args.jobs)
     S, N, K, F, T, iters = (probs[0][k] for k in ("S", "N", "K", "F", "T", "iters"))

@@ -34,12 +34,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("nfhmm_kernels.hip", "special.h", "jobdesc.h", "launch.h")
 
 
-def kernel_source_hash() -> str:
-    """SHA-256 prefix over the device-side sources (the kernels and the headers
-    they include; the host runtime is not part of it)."""
+def kernel_source_hash(files=KERNEL_SOURCES) -> str:
+    """SHA-256 prefix over device-side sources (by default the iteration kernels
+    and the headers they include; the host runtime is not part of it)."""
     h = hashlib.sha256()
     csrc = os.path.join(HERE, "csrc")
-    for f in KERNEL_SOURCES:
+    for f in files:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -48,10 +48,16 @@ def kernel_source_hash() -> str:
 def short_name(full: str) -> str:
     """'void nfhmm::k_counts<false>(nfhmm::WorkList)' -> 'k_counts';
     the BF16 instantiation (template argument true) gets a '_bf16' suffix;
-    the forward-backward keeps its state-count argument ('k_chain_fb<40>')."""
-    m = re.search(r"nfhmm::(\w+)(<([^>]*)>)?\(", full)
+    other template arguments are kept ('k_chain_fb<40>', 'k_stft<1024>');
+    kernels from outside the library keep their bare name and their namespace's
+    first part ('distribution_elementwise_grid_stride_kernel (at)')."""
+    m = re.search(r"nfhmm::(?:\(anonymous namespace\)::)?(\w+)(<([^>]*)>)?\(", full)
     if not m:
-        return full
+        q = re.match(r"(?:void )?([\w:]+)", full.replace("(anonymous namespace)::", ""))
+        if not q:
+            return full
+        parts = q.group(1).split("::")
+        return f"{parts[-1]} ({parts[0]})" if len(parts) > 1 else parts[-1]
     base, targ = m.group(1), m.group(3)
     if targ is None:
         return base
@@ -94,7 +100,8 @@ def cmd_kernels(a):
     lines = [f"# Kernel dispatch statistics: {a.title}", "",
              f"Command (run from /tmp with TMPDIR=/tmp; `$R` is the repository root):", "",
              f"    {a.command}", "",
-             f"GPU: {gpu}; kernel sources {kernel_source_hash()}.", "",
+             f"GPU: {gpu}; kernel sources {kernel_source_hash(tuple(a.sources))}"
+             + ("" if tuple(a.sources) == KERNEL_SOURCES else f" ({', '.join(a.sources)})") + ".", "",
              "| kernel | calls | total ms | average us | share of GPU time |",
              "|---|---:|---:|---:|---:|"]
     for name, calls, total, avg, pct in rows:
@@ -134,7 +141,8 @@ def cmd_traffic(a):
             "fetch_bytes_per_launch": fk * 1024 * f_fac, "write_bytes_per_launch": wk * 1024 * w_fac,
             "bytes_per_launch": fk * 1024 * f_fac + wk * 1024 * w_fac,
         }
-    out = {"kernel_source_hash": kernel_source_hash(), "workload": a.workload,
+    out = {"kernel_source_hash": kernel_source_hash(tuple(a.sources)), "kernel_sources": a.sources,
+           "workload": a.workload,
            "calibration": {"copy_bytes": copy_bytes, "fetch_scale": f_fac, "write_scale": w_fac,
                            "copy_dispatches": [nf, nw]},
            "commands": a.commands, "kernels": kernels}
@@ -145,7 +153,7 @@ def cmd_traffic(a):
         lines = [f"# HBM traffic per launch: {a.workload}", "",
                  "Commands (run from /tmp with TMPDIR=/tmp; `$R` is the repository root):", ""]
         lines += [f"    {c}" for c in a.commands]
-        lines += ["", f"Kernel sources {out['kernel_source_hash']}.  Calibration: a {copy_bytes / 2**20:.0f} MiB "
+        lines += ["", f"Kernel sources {out['kernel_source_hash']} ({', '.join(a.sources)}).  Calibration: a {copy_bytes / 2**20:.0f} MiB "
                   f"device copy reads FETCH_SIZE x {f_fac:.4f} and WRITE_SIZE x {w_fac:.4f} of its true bytes; "
                   "the figures below are scaled by those factors.", "",
                   "| kernel | dispatches | fetched MB / launch | written MB / launch | total MB / launch |",
@@ -170,7 +178,9 @@ def cmd_counters(a):
         acc[name][cn].append(float(v))
     lines = [f"# Hardware counters per dispatch: {a.title}", "",
              "Command (run from /tmp with TMPDIR=/tmp; `$R` is the repository root):", "", f"    {a.command}", "",
-             f"Kernel sources {kernel_source_hash()}.  GRBM_GUI_ACTIVE is summed over the {a.xcds} XCDs; MFMA busy = "
+             f"Kernel sources {kernel_source_hash(tuple(a.sources))}"
+             + ("" if tuple(a.sources) == KERNEL_SOURCES else f" ({', '.join(a.sources)})")
+             + f".  GRBM_GUI_ACTIVE is summed over the {a.xcds} XCDs; MFMA busy = "
              f"SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {a.xcds} x {a.simds} SIMDs).", ""]
     names = sorted({c for d in acc.values() for c in d})
     lines += ["| kernel | dispatches | " + " | ".join(names) + " | MFMA busy | LDS conflict / access |",
@@ -202,6 +212,8 @@ def main():
     k.add_argument("--command", required=True)
     k.add_argument("--title", default="")
     k.add_argument("--note", default="")
+    k.add_argument("--sources", nargs="+", default=list(KERNEL_SOURCES),
+                   help="files under csrc/ whose hash the record carries")
     k.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     for n in ("fetch", "write", "copy_fetch", "copy_write"):
@@ -211,12 +223,16 @@ def main():
     t.add_argument("--commands", nargs="+", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--md", default="", help="also write a markdown table here")
+    t.add_argument("--sources", nargs="+", default=list(KERNEL_SOURCES),
+                   help="files under csrc/ whose hash the record carries")
     q = sub.add_parser("counters")
     q.add_argument("db")
     q.add_argument("--command", required=True)
     q.add_argument("--title", default="")
     q.add_argument("--xcds", type=int, default=8)
     q.add_argument("--simds", type=int, default=1024)
+    q.add_argument("--sources", nargs="+", default=list(KERNEL_SOURCES),
+                   help="files under csrc/ whose hash the record carries")
     q.add_argument("--out", required=True)
     a = ap.parse_args()
     {"kernels": cmd_kernels, "traffic": cmd_traffic, "counters": cmd_counters}[a.what](a)
