@@ -3,23 +3,31 @@
 // F = 513 bins; Section 1 resynthesises each separated source with the phase
 // of the mixture).
 //
+// The FFT is a Stockham (self-sorting) transform in LDS: radix-4 passes, with
+// one radix-2 pass first when log2 NFFT is odd.  The pass combining transforms
+// of size ns takes butterfly j (< NFFT/R) from the R inputs j + r NFFT/R,
+// multiplies input r by exp(sign 2 pi i r k / (R ns)), k = j mod ns, does an
+// R-point DFT and writes output r to (j - k) R + k + r ns.  The first pass
+// (ns = 1, no twiddles) reads its inputs where they are, and the last pass
+// (ns = NFFT/4) leaves output r of butterfly j in registers as bin j + r NFFT/4,
+// so only the passes between touch LDS on both sides: 3 of 5 at NFFT = 1024.
+//
 //   k_stft   one block per (signal, run of kStftFrames frames): per frame, the
-//            frame times a periodic Hann window, an NFFT-point complex FFT in LDS
-//            (radix-2, Stockham order, so no bit reversal), |X| and arg X of bins
-//            0..NFFT/2.  The window and the twiddles are tabulated in LDS once per
-//            block.
+//            windowed frame goes straight from HBM into the first pass; the last
+//            pass writes |X| and arg X of bins 0..NFFT/2 to HBM.  The window and
+//            the twiddles are tabulated in LDS once per block.
 //   k_istft  one block per (source, run of G consecutive frames): per frame, the
-//            Hermitian spectrum mag * exp(i phase), the inverse FFT, the window;
-//            the windowed frame and the squared window are added into two rings
-//            of NFFT samples in LDS (sample i at slot i mod NFFT).  Once frame t is
-//            in, no later frame touches the samples [t hop, (t + 1) hop): they are
-//            final, written out as sum / weight (weighted overlap-add), and their
-//            slots cleared for the samples NFFT further on.  A block starts
-//            ceil(NFFT / hop) - 1 frames before its run so that its first samples
-//            see every frame covering them; those lead-in frames are computed but
-//            write nothing.  Every sample is summed over its frames in increasing
-//            t in one block: no atomics, no frame scratch in HBM, and a fixed
-//            summation order.
+//            Hermitian spectrum mag * exp(i phase) into LDS, the inverse FFT,
+//            whose last pass adds the windowed samples and the squared window
+//            into two rings of NFFT samples in LDS (sample i at slot i mod NFFT).
+//            Once frame t is in, no later frame touches the samples
+//            [t hop, (t + 1) hop): they are final, written out as sum / weight
+//            (weighted overlap-add), and their slots cleared for the samples NFFT
+//            further on.  A block starts ceil(NFFT / hop) - 1 frames before its
+//            run so that its first samples see every frame covering them; those
+//            lead-in frames are computed but write nothing.  Every sample is
+//            summed over its frames in increasing t in one block: no atomics, no
+//            frame scratch in HBM, and a fixed summation order.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -40,62 +48,12 @@ constexpr int kStftThreads = 256;
 constexpr int kStftFrames = NFHMM_STFT_FRAMES;    // frames per block of the transform
 constexpr int kIstftRunPerLead = NFHMM_ISTFT_RUN; // inverse: run length per (lead-in + 1) frames
 
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+
 // periodic Hann window: w[i] = (1 - cos(2 pi i / NFFT)) / 2
 template <int NFFT>
 __device__ __forceinline__ float hann(int i) {
   return 0.5f - 0.5f * cospif(2.0f * (float)i / (float)NFFT);
-}
-
-// Twiddles into LDS, stage by stage: the stage combining transforms of size ns
-// (1, 2, ..., NFFT/2) uses exp(sign i pi k / ns), k < ns, and finds them at
-// tw[ns - 1 + k], so the lanes of a wave read consecutive words (one strided
-// table of the NFFT/2 roots would put a wave's reads in one bank in the middle
-// stages).  NFFT - 1 entries.
-template <int NFFT>
-__device__ __forceinline__ void twiddles(float *twr, float *twi, float sign) {
-  for (int e = threadIdx.x; e < NFFT - 1; e += kStftThreads) {
-    const int ns = 1 << (31 - __clz(e + 1));   // the largest power of two <= e + 1
-    const int k = e + 1 - ns;
-    float s, c;
-    sincospif(sign * (float)k / (float)ns, &s, &c);
-    twr[e] = c;
-    twi[e] = s;
-  }
-}
-
-// In-place NFFT-point FFT of (re, im) in LDS with the twiddles of its sign
-// (forward -1, inverse +1, unscaled).  Stage s combines pairs of transforms of
-// size ns = 2^s; butterfly j reads j and j + NFFT/2 and writes (j / ns) * 2 ns +
-// j % ns and that + ns.  Expects the inputs and the table written before a
-// barrier; ends with a barrier; the result is in (re, im).
-template <int NFFT>
-__device__ void fft_lds(float *re, float *im, float *re2, float *im2, const float *twr, const float *twi) {
-  constexpr int kHalf = NFFT / 2;
-  float *sr = re, *si = im, *dr = re2, *di = im2;
-  for (int ns = 1; ns < NFFT; ns <<= 1) {
-    for (int j = threadIdx.x; j < kHalf; j += kStftThreads) {
-      const int k = j & (ns - 1);
-      const float c = twr[ns - 1 + k], s = twi[ns - 1 + k];
-      const float ar = sr[j], ai = si[j];
-      const float br0 = sr[j + kHalf], bi0 = si[j + kHalf];
-      const float br = br0 * c - bi0 * s, bi = br0 * s + bi0 * c;
-      const int d = (j - k) * 2 + k;
-      dr[d] = ar + br;
-      di[d] = ai + bi;
-      dr[d + ns] = ar - br;
-      di[d + ns] = ai - bi;
-    }
-    __syncthreads();
-    float *tr = sr, *ti = si;
-    sr = dr; si = di; dr = tr; di = ti;
-  }
-  if (sr != re) {   // an odd number of stages left the result in the second buffer
-    for (int i = threadIdx.x; i < NFFT; i += kStftThreads) {
-      re[i] = sr[i];
-      im[i] = si[i];
-    }
-    __syncthreads();
-  }
 }
 
 // the window w[i] into LDS
@@ -104,28 +62,192 @@ __device__ __forceinline__ void window(float *win) {
   for (int i = threadIdx.x; i < NFFT; i += kStftThreads) win[i] = hann<NFFT>(i);
 }
 
+// ns of the first radix-4 pass that has twiddles (4, or 2 after a radix-2 pass)
+template <int NFFT>
+constexpr int first_twiddled() { return ilog2(NFFT) % 2 ? 2 : 4; }
+
+// Word a of a transform buffer is kept at sw(a): bits 2-3 and 4-5 of a are
+// XORed with bits 6-7.  The stores of the passes of size 4 and 16 (groups of 4
+// or 16 words, 16 or 64 apart) then spread over every bank, for 32 or 64 banks,
+// and 64 consecutive words stay conflict-free.  Bits 0-1 are kept, so the 2- and
+// 4-word stores of the first pass stay contiguous and aligned.
+__device__ __forceinline__ int sw(int a) { return a ^ (((a >> 6) & 3) * 20); }
+
+// Twiddles of the radix-4 passes with ns > 1, pass by pass in the order they run:
+// the pass of size ns keeps exp(sign i pi r k / (2 ns)) for r = 1, 2, 3 and
+// k < ns at off + (r - 1) ns + k (off = 3 x the sizes of the passes before), so a
+// wave's lanes read consecutive words.  Fewer than NFFT entries.
+template <int NFFT, int SIGN>
+__device__ __forceinline__ void twiddles(float *twr, float *twi) {
+  int off = 0;
+  for (int ns = first_twiddled<NFFT>(); ns < NFFT; ns *= 4) {
+    for (int e = threadIdx.x; e < 3 * ns; e += kStftThreads) {
+      const int r = e / ns + 1, k = e - (r - 1) * ns;
+      float s, c;
+      sincospif((float)SIGN * (float)(r * k) / (float)(2 * ns), &s, &c);
+      twr[off + e] = c;
+      twi[off + e] = s;
+    }
+    off += 3 * ns;
+  }
+}
+
+// 4-point DFT in place, exp(SIGN 2 pi i / 4) = SIGN i
+template <int SIGN>
+__device__ __forceinline__ void dft4(float (&vr)[4], float (&vi)[4]) {
+  const float ar = vr[0] + vr[2], ai = vi[0] + vi[2];
+  const float br = vr[0] - vr[2], bi = vi[0] - vi[2];
+  const float cr = vr[1] + vr[3], ci = vi[1] + vi[3];
+  const float dr = (float)-SIGN * (vi[1] - vi[3]), di = (float)SIGN * (vr[1] - vr[3]);   // (v1 - v3) SIGN i
+  vr[0] = ar + cr;
+  vi[0] = ai + ci;
+  vr[1] = br + dr;
+  vi[1] = bi + di;
+  vr[2] = ar - cr;
+  vi[2] = ai - ci;
+  vr[3] = br - dr;
+  vi[3] = bi - di;
+}
+
+// inputs r = 1..3 of butterfly k of the pass of size ns times their twiddles
+__device__ __forceinline__ void twiddle3(float (&vr)[4], float (&vi)[4], const float *twr, const float *twi,
+                                         int off, int ns, int k) {
+#pragma unroll
+  for (int r = 1; r < 4; ++r) {
+    const float c = twr[off + (r - 1) * ns + k], s = twi[off + (r - 1) * ns + k];
+    const float x = vr[r], y = vi[r];
+    vr[r] = x * c - y * s;
+    vi[r] = x * s + y * c;
+  }
+}
+
+// One radix-4 pass of size ns from (sr, si) to (dr, di), both in LDS.
+template <int NFFT, int SIGN>
+__device__ __forceinline__ void pass4(const float *sr, const float *si, float *dr, float *di, const float *twr,
+                                      const float *twi, int off, int ns) {
+  constexpr int Q = NFFT / 4;
+  for (int j = threadIdx.x; j < Q; j += kStftThreads) {
+    const int k = j & (ns - 1);
+    float vr[4], vi[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      vr[r] = sr[sw(j + r * Q)];
+      vi[r] = si[sw(j + r * Q)];
+    }
+    twiddle3(vr, vi, twr, twi, off, ns, k);
+    dft4<SIGN>(vr, vi);
+    const int d = (j - k) * 4 + k;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      dr[sw(d + r * ns)] = vr[r];
+      di[sw(d + r * ns)] = vi[r];
+    }
+  }
+}
+
+// The passes between the first and the last.  The first pass has left its output
+// in (sr, si) before a barrier; on return (sr, si) hold the input of the last pass
+// (ns = NFFT/4), written before a barrier, and the result is that pass's twiddle
+// offset.
+template <int NFFT, int SIGN>
+__device__ __forceinline__ int middle_passes(float *&sr, float *&si, float *&dr, float *&di, const float *twr,
+                                             const float *twi) {
+  int off = 0;
+  for (int ns = first_twiddled<NFFT>(); ns < NFFT / 4; ns *= 4) {
+    pass4<NFFT, SIGN>(sr, si, dr, di, twr, twi, off, ns);
+    off += 3 * ns;
+    __syncthreads();
+    float *tr = sr, *ti = si;
+    sr = dr;
+    si = di;
+    dr = tr;
+    di = ti;
+  }
+  return off;
+}
+
+// The last pass's butterfly j: inputs j + r NFFT/4 from (sr, si); on return
+// (vr[r], vi[r]) is bin j + r NFFT/4.
+template <int NFFT, int SIGN>
+__device__ __forceinline__ void last_pass(const float *sr, const float *si, const float *twr, const float *twi,
+                                          int off, int j, float (&vr)[4], float (&vi)[4]) {
+  constexpr int Q = NFFT / 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    vr[r] = sr[sw(j + r * Q)];
+    vi[r] = si[sw(j + r * Q)];
+  }
+  twiddle3(vr, vi, twr, twi, off, Q, j);
+  dft4<SIGN>(vr, vi);
+}
+
 template <int NFFT>
 __global__ __launch_bounds__(kStftThreads) void k_stft(const float *__restrict__ x, int64_t n, int hop, int T,
                                                        float *__restrict__ mag, float *__restrict__ phase) {
-  constexpr int F = NFFT / 2 + 1;
-  __shared__ float re[NFFT], im[NFFT], re2[NFFT], im2[NFFT], twr[NFFT], twi[NFFT], win[NFFT];
+  constexpr int F = NFFT / 2 + 1, Q = NFFT / 4;
+  constexpr bool kOdd = ilog2(NFFT) % 2 == 1;
+  // the first pass writes 2 or 4 consecutive words per lane
+  __shared__ __align__(16) float re[NFFT];
+  __shared__ __align__(16) float im[NFFT];
+  __shared__ __align__(16) float re2[NFFT];
+  __shared__ __align__(16) float im2[NFFT];
+  __shared__ float twr[NFFT], twi[NFFT], win[NFFT];
   const int b = blockIdx.y;
   const int t0 = blockIdx.x * kStftFrames, t1 = min(T, t0 + kStftFrames);
-  twiddles<NFFT>(twr, twi, -1.0f);
+  twiddles<NFFT, -1>(twr, twi);
   window<NFFT>(win);
-  for (int t = t0; t < t1; ++t) {
+  // first pass: radix 4 (radix 2 when log2 NFFT is odd) over NFFT / kR butterflies;
+  // each thread holds its butterflies' inputs for the next frame in registers,
+  // loaded while the current frame's passes run
+  constexpr int kR = kOdd ? 2 : 4, kBf = NFFT / kR, kPer = (kBf + kStftThreads - 1) / kStftThreads;
+  float xv[kPer][kR];
+  auto load = [&](int t) {
     const float *xs = x + (size_t)b * n + (size_t)t * hop;
-    __syncthreads();   // the tables are written; the previous frame's bins are read
-    for (int i = threadIdx.x; i < NFFT; i += kStftThreads) {
-      re[i] = xs[i] * win[i];
-      im[i] = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int j = threadIdx.x + q * kStftThreads;
+#pragma unroll
+      for (int r = 0; r < kR; ++r) xv[q][r] = j < kBf ? xs[j + r * kBf] : 0.0f;
     }
+  };
+  if (t0 < t1) load(t0);
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();   // the tables are written; the previous frame's last pass has read its input
+    // first pass (ns = 1, twiddles 1) on the windowed frame
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int j = threadIdx.x + q * kStftThreads;
+      if (j >= kBf) break;
+      if constexpr (kOdd) {
+        const float a = xv[q][0] * win[j], c = xv[q][1] * win[j + kBf];
+        reinterpret_cast<float2 *>(re)[sw(2 * j) >> 1] = make_float2(a + c, a - c);
+        reinterpret_cast<float2 *>(im)[sw(2 * j) >> 1] = make_float2(0.0f, 0.0f);
+      } else {
+        float vr[4], vi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) vr[r] = xv[q][r] * win[j + r * Q];
+        dft4<-1>(vr, vi);
+        reinterpret_cast<float4 *>(re)[sw(4 * j) >> 2] = make_float4(vr[0], vr[1], vr[2], vr[3]);
+        reinterpret_cast<float4 *>(im)[sw(4 * j) >> 2] = make_float4(vi[0], vi[1], vi[2], vi[3]);
+      }
+    }
+    if (t + 1 < t1) load(t + 1);
     __syncthreads();
-    fft_lds<NFFT>(re, im, re2, im2, twr, twi);
+    float *sr = re, *si = im, *dr = re2, *di = im2;
+    const int off = middle_passes<NFFT, -1>(sr, si, dr, di, twr, twi);
+    // last pass: bins j and j + NFFT/4 (and NFFT/2 from butterfly 0) to HBM
     const size_t o = ((size_t)b * T + t) * F;
-    for (int k = threadIdx.x; k < F; k += kStftThreads) {
-      mag[o + k] = hypotf(re[k], im[k]);
-      phase[o + k] = atan2f(im[k], re[k]);
+    for (int j = threadIdx.x; j < Q; j += kStftThreads) {
+      float vr[4], vi[4];
+      last_pass<NFFT, -1>(sr, si, twr, twi, off, j, vr, vi);
+      mag[o + j] = hypotf(vr[0], vi[0]);
+      phase[o + j] = atan2f(vi[0], vr[0]);
+      mag[o + j + Q] = hypotf(vr[1], vi[1]);
+      phase[o + j + Q] = atan2f(vi[1], vr[1]);
+      if (j == 0) {
+        mag[o + 2 * Q] = hypotf(vr[2], vi[2]);
+        phase[o + 2 * Q] = atan2f(vi[2], vr[2]);
+      }
     }
   }
 }
@@ -134,44 +256,95 @@ template <int NFFT>
 __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict__ mag, const float *__restrict__ phase,
                                                         int S, int T, int hop, int G, int64_t n,
                                                         float *__restrict__ y) {
-  constexpr int F = NFFT / 2 + 1;
-  __shared__ float re[NFFT], im[NFFT], re2[NFFT], im2[NFFT], twr[NFFT], twi[NFFT], win[NFFT];
+  constexpr int F = NFFT / 2 + 1, Q = NFFT / 4;
+  constexpr bool kOdd = ilog2(NFFT) % 2 == 1;
+  // the first pass writes 2 or 4 consecutive words per lane
+  __shared__ __align__(16) float re[NFFT];
+  __shared__ __align__(16) float im[NFFT];
+  __shared__ __align__(16) float re2[NFFT];
+  __shared__ __align__(16) float im2[NFFT];
+  __shared__ float twr[NFFT], twi[NFFT], win[NFFT];
   __shared__ float acc[NFFT], wacc[NFFT];   // rings: slot i mod NFFT holds sample i
   const int sig = blockIdx.y, mix = sig / S;
   const int t0 = blockIdx.x * G, t1 = min(T, t0 + G);
   const int lead = (NFFT + hop - 1) / hop - 1;   // frames before t0 that cover samples >= t0 hop
   const int ts = max(0, t0 - lead);
-  twiddles<NFFT>(twr, twi, 1.0f);
+  twiddles<NFFT, 1>(twr, twi);
   window<NFFT>(win);
   for (int i = threadIdx.x; i < NFFT; i += kStftThreads) {
     acc[i] = 0.0f;
     wacc[i] = 0.0f;
   }
   float *ys = y + (size_t)sig * n;
-  for (int t = ts; t < t1; ++t) {
+  // each thread's bins of the next frame, loaded while the current frame's passes run
+  constexpr int kPerF = (F + kStftThreads - 1) / kStftThreads;
+  float mv[kPerF], pv[kPerF];
+  auto load = [&](int t) {
     const float *ms = mag + ((size_t)sig * T + t) * F, *ps = phase + ((size_t)mix * T + t) * F;
+#pragma unroll
+    for (int q = 0; q < kPerF; ++q) {
+      const int k = threadIdx.x + q * kStftThreads;
+      mv[q] = k < F ? ms[k] : 0.0f;
+      pv[q] = k < F ? ps[k] : 0.0f;
+    }
+  };
+  if (ts < t1) load(ts);
+  for (int t = ts; t < t1; ++t) {
     __syncthreads();   // the tables and rings are written; the previous frame is folded in
-    for (int k = threadIdx.x; k < F; k += kStftThreads) {
+#pragma unroll
+    for (int q = 0; q < kPerF; ++q) {
+      const int k = threadIdx.x + q * kStftThreads;
+      if (k >= F) break;
       float s, c;
-      sincosf(ps[k], &s, &c);
-      const float a = ms[k];
+      sincosf(pv[q], &s, &c);
+      const float a = mv[q];
       // a real signal: bins 0 and NFFT/2 are real (their imaginary parts are dropped)
       const float yr = a * c, yi = (k == 0 || k == F - 1) ? 0.0f : a * s;
-      re[k] = yr;
-      im[k] = yi;
+      re[sw(k)] = yr;
+      im[sw(k)] = yi;
       if (k > 0 && k < F - 1) {   // Hermitian half
-        re[NFFT - k] = yr;
-        im[NFFT - k] = -yi;
+        re[sw(NFFT - k)] = yr;
+        im[sw(NFFT - k)] = -yi;
+      }
+    }
+    if (t + 1 < t1) load(t + 1);
+    __syncthreads();
+    // first pass (ns = 1, twiddles 1) from (re, im) to (re2, im2)
+    if constexpr (kOdd) {
+      for (int j = threadIdx.x; j < NFFT / 2; j += kStftThreads) {
+        const float ar = re[sw(j)], ai = im[sw(j)], cr = re[sw(j + NFFT / 2)], ci = im[sw(j + NFFT / 2)];
+        reinterpret_cast<float2 *>(re2)[sw(2 * j) >> 1] = make_float2(ar + cr, ar - cr);
+        reinterpret_cast<float2 *>(im2)[sw(2 * j) >> 1] = make_float2(ai + ci, ai - ci);
+      }
+    } else {
+      for (int j = threadIdx.x; j < Q; j += kStftThreads) {
+        float vr[4], vi[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          vr[r] = re[sw(j + r * Q)];
+          vi[r] = im[sw(j + r * Q)];
+        }
+        dft4<1>(vr, vi);
+        reinterpret_cast<float4 *>(re2)[sw(4 * j) >> 2] = make_float4(vr[0], vr[1], vr[2], vr[3]);
+        reinterpret_cast<float4 *>(im2)[sw(4 * j) >> 2] = make_float4(vi[0], vi[1], vi[2], vi[3]);
       }
     }
     __syncthreads();
-    fft_lds<NFFT>(re, im, re2, im2, twr, twi);
+    float *sr = re2, *si = im2, *dr = re, *di = im;
+    const int off = middle_passes<NFFT, 1>(sr, si, dr, di, twr, twi);
+    // last pass: sample j + r NFFT/4 of the frame, scaled and windowed, into the rings
     const int64_t base = (int64_t)t * hop;
-    for (int j = threadIdx.x; j < NFFT; j += kStftThreads) {
-      const int r = (int)((base + j) & (NFFT - 1));
-      const float w = win[j];
-      acc[r] += re[j] * (1.0f / (float)NFFT) * w;
-      wacc[r] += w * w;
+    for (int j = threadIdx.x; j < Q; j += kStftThreads) {
+      float vr[4], vi[4];
+      last_pass<NFFT, 1>(sr, si, twr, twi, off, j, vr, vi);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = j + r * Q;
+        const int slot = (int)((base + i) & (NFFT - 1));
+        const float w = win[i];
+        acc[slot] += vr[r] * (1.0f / (float)NFFT) * w;
+        wacc[slot] += w * w;
+      }
     }
     __syncthreads();
     // samples [t hop, t hop + hop) are final (the last frame also owns the rest of
