@@ -141,3 +141,33 @@ def test_stft_rejects_bad_sizes(L, ctx):
         L.istft(ctx, np.zeros((256, 257, 1, 33), dtype=np.float32), np.zeros((256, 1, 33), dtype=np.float32),
                 64, 64, 16)
     assert e.value.status == L.E_INVALID
+
+
+def test_separation_pipeline_sources_sum_to_the_mixture(L, ctx):
+    # the whole separation on the GPU: STFT of a mixture, the VI fit on its
+    # magnitudes, the separated spectrograms back to signals with the mixture's
+    # phase.  The separated magnitudes of every bin sum to the mixture's, so the
+    # resynthesised sources sum to the mixture wherever a window covers.
+    from gen import make_tiny
+    nfft, hop = 256, 64
+    p = make_tiny(S=2, N=5, K=8, F=nfft // 2 + 1, T=100, seed=3, iters=8)
+    n = (p["T"] - 1) * hop + nfft
+    rng = np.random.default_rng(17)
+    i = np.arange(n)
+    # two sources: a tone whose pitch steps every 1600 samples, and noise bursts
+    s1 = np.sin(2 * np.pi * (0.02 + 0.01 * (i // 1600 % 3)) * i)
+    s2 = rng.normal(size=n) * (np.sin(2 * np.pi * i / 2000) > 0)
+    x = (s1 + 0.5 * s2).astype(np.float32)
+    mag, phase = L.stft(ctx, x, nfft, hop)
+    assert mag.shape == (p["T"], p["F"])
+    p["V"] = mag
+    out = L.fit(ctx, p)
+    sep = out["sep"]
+    assert np.all(np.isfinite(sep)) and np.all(sep >= 0)
+    assert np.max(np.abs(sep.sum(0) - mag)) <= 1e-5 * np.max(mag)
+    y = L.istft(ctx, sep, phase, n, nfft, hop)
+    assert y.shape == (2, n) and np.all(np.isfinite(y))
+    ws = SO.window_weight(n, p["T"], nfft, hop)
+    ok = ws >= 0.1
+    assert np.max(np.abs(y.sum(0)[ok] - x[ok])) < 2e-5 * np.max(np.abs(x))
+    assert np.max(np.abs(y[0])) > 0 and np.max(np.abs(y[1])) > 0
