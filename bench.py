@@ -218,10 +218,10 @@ def stft_bench(L, ctx, jobs=32, sources=2, frames=1000, nfft=1024, hop=256, reps
     }
 
 
-def cpu_baseline(seconds_target=15.0, one_thread=False):
-    """The FP64 oracle on the host cores: one paper-typical job, one warm-up iteration,
-    then iterations until about `seconds_target` seconds have passed (all BLAS
-    threads, or one)."""
+def cpu_baseline(seconds_target=15.0, one_thread=False, config=1):
+    """The FP64 oracle on the host cores: job 0 of the given workload (1 =
+    paper-typical), one warm-up iteration, then iterations until about
+    `seconds_target` seconds have passed (all BLAS threads, or one)."""
     import contextlib
 
     import numpy as np
@@ -237,7 +237,7 @@ def cpu_baseline(seconds_target=15.0, one_thread=False):
     except Exception:
         threads = 1 if one_thread else os.cpu_count()
     with limit:
-        return _cpu_run(make_problem(1, 0), seconds_target, threads, O, np)
+        return _cpu_run(make_problem(config, 0), seconds_target, threads, O, np)
 
 
 def _cpu_run(p, seconds_target, threads, O, np):
@@ -253,9 +253,10 @@ def _cpu_run(p, seconds_target, threads, O, np):
         n += 1
     dt = time.perf_counter() - t0
     assert np.all(np.isfinite(alpha))
+    shape = f"S={S},N={N},K={K},F={p['F']},T={p['T']}"
     return {"value": p["T"] * n / dt, "unit": "frame-iterations/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"paper-typical job 0 (S=2,N=40,K=10,F=513,T=1000): 1 warm-up + {n} timed FP64 iterations, "
-                      f"{dt:.1f} s, {threads} BLAS thread(s)"}
+            "sample": f"job 0 ({shape}): 1 warm-up + {n} timed FP64 iterations, {dt:.1f} s, "
+                      f"{threads} BLAS thread(s)"}
 
 
 def main():
@@ -387,6 +388,24 @@ def main():
                         "kernels_ms": {k: v[1] / 2 for k, v in pr3.items()}}
         extra["precision_form_single_job"] = c3
         del j3
+        # the host-buffer form: nfhmm_fit_batch on host arrays, so the copies of V and
+        # W in and of the outputs back are inside the time (never the headline value)
+        log("host-buffer fit of the batch")
+        import numpy as np
+        hp = [{k: (np.ascontiguousarray(v, dtype=np.float32) if isinstance(v, np.ndarray) and v.dtype.kind == "f"
+                   else v) for k, v in p.items()} for p in probs]
+        L.fit_batch(ctx, hp, "fp32")
+        th = []
+        for _ in range(2):
+            t0 = time.perf_counter()
+            L.fit_batch(ctx, hp, "fp32")
+            th.append(time.perf_counter() - t0)
+        dth = min(th)
+        extra["host_buffer_fit_fp32"] = {"value": J * T * iters / dth, "ms_per_fit": dth * 1e3,
+                                         "copied_mb": sum(p["V"].nbytes + p["W"].nbytes for p in hp) / 1e6,
+                                         "note": "nfhmm_fit_batch on host arrays (V, W in; alpha, posteriors, "
+                                                 "separated spectrograms, bounds out), best of 2"}
+        del hp
         log("time-frequency front and back end")
         extra["stft"] = stft_bench(L, ctx)
 
@@ -414,6 +433,9 @@ def main():
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline_1thread"] = cpu_baseline(10.0, one_thread=True)
+        # the oracle on the small and the long workloads too, each a bounded sample
+        out["cpu_baseline_other_workloads"] = {"S2-N5-K8-F129-T100": cpu_baseline(3.0, config=0),
+                                               "S2-N60-K20-F1025-T4000": cpu_baseline(10.0, config=3)}
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -144,7 +144,10 @@ NFHMM_API int nfhmm_admission_plan(int n_queued, const size_t *footprints, size_
 
 /* Blocking fit of one problem whose arrays are in host memory.  Inputs are
  * validated (nfhmm_validate) and copied; the caller may reuse them on return.
- * Outputs are written to the host arrays of *r. */
+ * Outputs are written to the host arrays of *r.  Copies go through a pinned host
+ * ring of the context (1 GiB, allocated on first use; pageable copies when it has
+ * no room), and the device working memory stays cached in the context for the
+ * next call of the same shapes. */
 NFHMM_API nfhmm_status nfhmm_fit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precision prec,
                        nfhmm_result *r);
 

@@ -416,7 +416,7 @@ struct nfhmm_ctx {
   struct Lane { hipStream_t main, fb; hipEvent_t fork, join, done; } lanes[kMaxGroups] = {};
   std::vector<std::unique_ptr<Table>> tables;   // ring
   size_t table_next = 0;
-  std::map<size_t, std::vector<char *>> arena_cache;   // device path: reusable arenas by size
+  std::map<size_t, std::vector<char *>> arena_cache;   // fit paths: reusable arenas by size
 
   // Held while host code issues device work: by a blocking fit or chain call
   // for its whole length, by the serving scheduler for each round.  The two
@@ -440,16 +440,17 @@ struct nfhmm_ctx {
   char *slab = nullptr;
   bool slab_tried = false;
   std::map<size_t, size_t> slab_free;   // offset -> bytes of each free range
-  // serving copies: one pinned host ring, so that host<->device copies are
-  // asynchronous (a copy from or to pageable memory holds the calling thread
-  // until the stream reaches it, which would drain the device between rounds)
+  // host-array copies (serving and host fits): one pinned host ring, so that
+  // host<->device copies are asynchronous (a copy from or to pageable memory
+  // holds the calling thread until the stream reaches it, which would drain the
+  // device between rounds)
   struct PinRegion { size_t off, len; hipEvent_t ev; bool done; };
   char *pin = nullptr;
   size_t pin_size = 0, pin_head = 0;
   bool pin_tried = false;
   std::deque<PinRegion> pin_regs;
-  // host copies of the serving path (inputs at submit, the ring on both sides),
-  // made on first submit
+  // host copies (serving inputs at submit; the ring on both sides), made on the
+  // first submit or host-array fit
   static constexpr int kCopyWorkers = 7;
   std::unique_ptr<CopyPool> copies;
 
@@ -681,8 +682,8 @@ nfhmm_status download_outputs(Job &j, hipStream_t st) {
   return NFHMM_OK;
 }
 
-// Serving forms of the two copies, through the pinned ring (pageable copies if
-// the ring has no room).
+// Staged forms of the two copies (serving and host-array fits), through the
+// pinned ring (pageable copies if the ring has no room).
 nfhmm_status upload_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
   const Dims &d = j.d;
   const size_t nb[5] = {(size_t)d.T * d.F * 4, (size_t)d.M * d.F * 4, (size_t)d.S * d.N * d.N * 4,
@@ -870,8 +871,10 @@ nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t 
     max_it = std::max(max_it, j->d.iters);
   }
   nfhmm_status s;
+  // host inputs through the pinned ring (the copy pool fills it while the DMA of
+  // the previous job's arrays runs); pageable copies when the ring has no room
   for (Job *j : jobs)
-    if (j->host_in && (s = upload_inputs(*j, st)) != NFHMM_OK) return s;
+    if (j->host_in && (s = upload_staged(ctx, *j, st)) != NFHMM_OK) return s;
   if ((s = engine_begin(ctx, jobs, st)) != NFHMM_OK) return s;
   std::vector<Job *> done0;
   for (Job *j : jobs)
@@ -898,9 +901,23 @@ nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t 
     HIP_OK(hipEventRecord(ctx->lanes[g].done, ctx->lanes[g].main));
     HIP_OK(hipStreamWaitEvent(st, ctx->lanes[g].done, 0));
   }
+  // host outputs through the pinned ring, then the copy pool into the caller's
+  // arrays; every region taken here is given back before returning
+  nfhmm_status ds = NFHMM_OK;
   for (Job *j : jobs)
-    if (j->host_out && (s = download_outputs(*j, st)) != NFHMM_OK) return s;
-  HIP_OK(hipStreamSynchronize(st));
+    if (j->host_out && ds == NFHMM_OK) ds = download_staged(ctx, *j, st);
+  const hipError_t se = hipStreamSynchronize(st);
+  for (Job *j : jobs) {
+    if (se == hipSuccess && ds == NFHMM_OK) {
+      deliver_staged(ctx, *j);
+    } else if (j->out_pin != ~size_t(0)) {
+      pin_release(ctx, j->out_pin);
+      j->out_pin = ~size_t(0);
+    }
+  }
+  pin_poll(ctx);   // the upload regions, whose copies are done
+  if (ds != NFHMM_OK) return ds;
+  HIP_OK(se);
   nfhmm_status first = NFHMM_OK;
   for (Job *j : jobs) {
     int flag = 0;
@@ -1251,13 +1268,17 @@ nfhmm_status nfhmm_fit_batch(nfhmm_ctx *ctx, int n, const nfhmm_problem *ps, nfh
     if (s != NFHMM_OK) return s;
     jobs.push_back(&j);
   }
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    if (!ctx->copies) ctx->copies.reset(new CopyPool(nfhmm_ctx::kCopyWorkers));
+  }
   std::lock_guard<std::mutex> eng(ctx->engine_mu);
   nfhmm_status s = NFHMM_OK;
   for (Job *j : jobs)
-    if ((s = arena_alloc(ctx, *j, false)) != NFHMM_OK) break;
+    if ((s = arena_alloc(ctx, *j, true)) != NFHMM_OK) break;
   if (s == NFHMM_OK) s = run_blocking(ctx, jobs, ctx->stream);
   (void)hipStreamSynchronize(ctx->stream);
-  for (Job *j : jobs) arena_release(ctx, *j, false);
+  for (Job *j : jobs) arena_release(ctx, *j, true);
   return s;
 }
 
