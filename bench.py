@@ -218,6 +218,58 @@ def stft_bench(L, ctx, jobs=32, sources=2, frames=1000, nfft=1024, hop=256, reps
     }
 
 
+def measured_peaks():
+    """What library code reaches on this GPU, beside the nominal peaks: a plain
+    FP32 GEMM through torch (the vendor BLAS) at 8192^3 and on the shape of one
+    k_counts launch, and a 1 GiB device copy, each timed with events after a
+    warm-up."""
+    import torch
+    out = {}
+    n = 8192
+    a = torch.rand((n, n), device="cuda")
+    b = torch.rand((n, n), device="cuda")
+    torch.matmul(a, b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        torch.matmul(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["fp32_gemm_vendor_tflops"] = 2.0 * n ** 3 / (ms * 1e-3) / 1e12
+    out["fp32_gemm_vendor_frac"] = out["fp32_gemm_vendor_tflops"] * 1e12 / PEAK_FP32_MFMA
+    del a, b
+    # the same library on the shape of one k_counts launch: 16 jobs, each an
+    # (M = 800) x (F = 512) by (F x T = 1000) product (plain GEMM, no epilogue)
+    a = torch.rand((16, 800, 512), device="cuda")
+    b = torch.rand((16, 512, 1000), device="cuda").contiguous()
+    torch.bmm(a, b)
+    e0.record()
+    for _ in range(reps):
+        torch.bmm(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["fp32_gemm_vendor_counts_shape_tflops"] = 2.0 * 16 * 800 * 512 * 1000 / (ms * 1e-3) / 1e12
+    out["fp32_gemm_vendor_counts_shape_frac"] = out["fp32_gemm_vendor_counts_shape_tflops"] * 1e12 / PEAK_FP32_MFMA
+    del a, b
+    src = torch.empty((1 << 28,), device="cuda")   # 1 GiB of float32
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out["hbm_copy_gbps"] = 2.0 * src.numel() * 4 / (ms * 1e-3) / 1e9   # read + write
+    out["hbm_copy_frac"] = out["hbm_copy_gbps"] * 1e9 / PEAK_HBM
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(seconds_target=15.0, one_thread=False, config=1):
     """The FP64 oracle on the host cores: job 0 of the given workload (1 =
     paper-typical), one warm-up iteration, then iterations until about
@@ -408,6 +460,8 @@ def main():
         del hp
         log("time-frequency front and back end")
         extra["stft"] = stft_bench(L, ctx)
+        log("library GEMM and copy on this GPU")
+        extra["measured_peaks"] = measured_peaks()
 
     out = {
         "metric": "VI frame-iterations/s at S=2,N=40,F=513 (FP32 contraction)",
