@@ -171,3 +171,39 @@ def test_separation_pipeline_sources_sum_to_the_mixture(L, ctx):
     ok = ws >= 0.1
     assert np.max(np.abs(y.sum(0)[ok] - x[ok])) < 2e-5 * np.max(np.abs(x))
     assert np.max(np.abs(y[0])) > 0 and np.max(np.abs(y[1])) > 0
+
+
+def test_bench_launch_configuration(L, ctx):
+    # the launches bench.py times: device forms on a stream of their own, 32
+    # mixtures of 1000 frames (nfft 1024, hop 256), then 2 masked sources per
+    # mixture in one inverse call; sampled mixtures checked against the reference
+    import torch
+    jobs, S, frames, nfft, hop = 32, 2, 1000, 1024, 256
+    F = nfft // 2 + 1
+    n = (frames - 1) * hop + nfft
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(31)
+    x = rng.normal(size=(jobs, n)).astype(np.float32)
+    masks = rng.uniform(size=(jobs, S, frames, F)).astype(np.float32)
+    dx = torch.as_tensor(x, device=dev)
+    mag = torch.empty((jobs, frames, F), device=dev)
+    phase = torch.empty_like(mag)
+    y = torch.empty((jobs, S, n), device=dev)
+    torch.cuda.synchronize()   # the input copy (torch's stream) before the library's stream reads it
+    st = torch.cuda.Stream()
+    L.stft_device(ctx, dx, mag, phase, nfft, hop, stream=st)
+    st.synchronize()
+    src = (torch.as_tensor(masks, device=dev) * mag[:, None]).contiguous()
+    torch.cuda.synchronize()
+    L.istft_device(ctx, src, phase, y, nfft, hop, stream=st)
+    st.synchronize()
+    mg, ph, yg, sg = mag.cpu().numpy(), phase.cpu().numpy(), y.cpu().numpy(), src.cpu().numpy()
+    ws = SO.window_weight(n, frames, nfft, hop)
+    ok = ws >= 0.1
+    for b in (0, 13, 31):
+        rm, rp = SO.stft(x[b].astype(np.float64), nfft, hop)
+        Xg = mg[b].astype(np.float64) * np.exp(1j * ph[b].astype(np.float64))
+        assert np.max(np.abs(Xg - rm * np.exp(1j * rp))) < 2e-6 * np.max(rm)
+        yr = SO.istft(sg[b].astype(np.float64), ph[b].astype(np.float64), n, nfft, hop)
+        assert np.max(np.abs(yg[b][:, ok] - yr[:, ok])) < 1e-5 * np.max(np.abs(yr[:, ok]))
+    assert np.all(np.isfinite(yg))
