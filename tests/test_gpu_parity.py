@@ -177,6 +177,9 @@ ONE_STEP_CASES = [
     ("K1-M-odd", lambda: make_tiny(S=3, N=3, K=1, F=9, T=64, seed=5, quanta=80), 2),
     ("N64", lambda: make_tiny(S=2, N=64, K=1, F=100, T=90, seed=6, quanta=2000, trans="sparse", diag=0.9), 2),
     ("S8-max-sources", lambda: make_tiny(S=8, N=3, K=2, F=50, T=40, seed=7, quanta=400), 2),
+    # the largest problem the ABI admits in elements: S N K = 12288 (8 sources of
+    # 64 states with 24 elements each)
+    ("M-max", lambda: make_tiny(S=8, N=64, K=24, F=33, T=24, seed=8, quanta=3000, trans="sparse", diag=0.9), 2),
     ("silent-frames", lambda: _silence(make_problem(0, 1), [0, 1, 37, 38, 39, 99]), 2),
 ]
 
