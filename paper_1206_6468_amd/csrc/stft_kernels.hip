@@ -13,13 +13,18 @@
 // so only the passes between touch LDS on both sides: 3 of 5 at NFFT = 1024.
 //
 //   k_stft   one block per (signal, run of kStftFrames frames): per frame, the
-//            windowed frame goes straight from HBM into the first pass; the last
-//            pass writes |X| and arg X of bins 0..NFFT/2 to HBM.  The window and
-//            the twiddles are tabulated in LDS once per block.
+//            windowed frame, read from HBM as NFFT/2 complex values (even samples
+//            real, odd imaginary), goes straight into the first pass of an
+//            NFFT/2-point FFT; a last step unfolds bins k and NFFT/2 - k of the
+//            real frame's transform from that FFT's bins k and NFFT/2 - k and
+//            writes |X| and arg X of bins 0..NFFT/2 to HBM.  The window and the
+//            twiddles are tabulated in LDS once per block.
 //   k_istft  one block per (source, run of G consecutive frames): per frame, the
-//            Hermitian spectrum mag * exp(i phase) into LDS, the inverse FFT,
-//            whose last pass adds the windowed samples and the squared window
-//            into two rings of NFFT samples in LDS (sample i at slot i mod NFFT).
+//            Hermitian spectrum mag * exp(i phase) folded into NFFT/2 complex
+//            values whose NFFT/2-point inverse FFT holds the even samples in its
+//            real and the odd samples in its imaginary parts; the last pass adds
+//            the windowed samples and the squared window into two rings of NFFT
+//            samples in LDS (sample i at slot i mod NFFT).
 //            Once frame t is in, no later frame touches the samples
 //            [t hop, (t + 1) hop): they are final, written out as sum / weight
 //            (weighted overlap-add), and their slots cleared for the samples NFFT
@@ -184,48 +189,60 @@ __device__ __forceinline__ void last_pass(const float *sr, const float *si, cons
 template <int NFFT>
 __global__ __launch_bounds__(kStftThreads) void k_stft(const float *__restrict__ x, int64_t n, int hop, int T,
                                                        float *__restrict__ mag, float *__restrict__ phase) {
-  constexpr int F = NFFT / 2 + 1, Q = NFFT / 4;
-  constexpr bool kOdd = ilog2(NFFT) % 2 == 1;
+  // The real windowed frame u is transformed as z[m] = u[2m] + i u[2m+1] with an
+  // H = NFFT/2 point FFT Z; with Ze = (Z[k] + conj Z[H-k]) / 2 and Zo = (Z[k] -
+  // conj Z[H-k]) / 2i, X[k] = Ze + exp(-2 pi i k / NFFT) Zo and X[H-k] = conj(Ze -
+  // exp(-2 pi i k / NFFT) Zo).
+  constexpr int H = NFFT / 2, F = H + 1, Q = H / 4, P = H / 2 + 1;
+  constexpr bool kOdd = ilog2(H) % 2 == 1;
   // the first pass writes 2 or 4 consecutive words per lane
-  __shared__ __align__(16) float re[NFFT];
-  __shared__ __align__(16) float im[NFFT];
-  __shared__ __align__(16) float re2[NFFT];
-  __shared__ __align__(16) float im2[NFFT];
-  __shared__ float twr[NFFT], twi[NFFT], win[NFFT];
+  __shared__ __align__(16) float re[H];
+  __shared__ __align__(16) float im[H];
+  __shared__ __align__(16) float re2[H];
+  __shared__ __align__(16) float im2[H];
+  __shared__ float twr[H], twi[H], win[NFFT], er[P], ei[P];
   const int b = blockIdx.y;
   const int t0 = blockIdx.x * kStftFrames, t1 = min(T, t0 + kStftFrames);
-  twiddles<NFFT, -1>(twr, twi);
+  twiddles<H, -1>(twr, twi);
   window<NFFT>(win);
-  // first pass: radix 4 (radix 2 when log2 NFFT is odd) over NFFT / kR butterflies;
-  // each thread holds its butterflies' inputs for the next frame in registers,
-  // loaded while the current frame's passes run
-  constexpr int kR = kOdd ? 2 : 4, kBf = NFFT / kR, kPer = (kBf + kStftThreads - 1) / kStftThreads;
-  float xv[kPer][kR];
+  for (int k = threadIdx.x; k < P; k += kStftThreads) sincospif(-2.0f * (float)k / (float)NFFT, &ei[k], &er[k]);
+  // first pass: radix 4 (radix 2 when log2 H is odd) over H / kR butterflies,
+  // input r of butterfly j being z[j + r H / kR]; each thread holds its
+  // butterflies' samples for the next frame in registers, loaded while the
+  // current frame's passes run
+  constexpr int kR = kOdd ? 2 : 4, kBf = H / kR, kPer = (kBf + kStftThreads - 1) / kStftThreads;
+  float xv[kPer][kR][2];
   auto load = [&](int t) {
     const float *xs = x + (size_t)b * n + (size_t)t * hop;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int j = threadIdx.x + q * kStftThreads;
 #pragma unroll
-      for (int r = 0; r < kR; ++r) xv[q][r] = j < kBf ? xs[j + r * kBf] : 0.0f;
+      for (int r = 0; r < kR; ++r) {
+        const int m = j + r * kBf;
+        xv[q][r][0] = j < kBf ? xs[2 * m] : 0.0f;
+        xv[q][r][1] = j < kBf ? xs[2 * m + 1] : 0.0f;
+      }
     }
   };
   if (t0 < t1) load(t0);
   for (int t = t0; t < t1; ++t) {
-    __syncthreads();   // the tables are written; the previous frame's last pass has read its input
-    // first pass (ns = 1, twiddles 1) on the windowed frame
+    __syncthreads();   // the tables are written; the previous frame's bins are read
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int j = threadIdx.x + q * kStftThreads;
       if (j >= kBf) break;
-      if constexpr (kOdd) {
-        const float a = xv[q][0] * win[j], c = xv[q][1] * win[j + kBf];
-        reinterpret_cast<float2 *>(re)[sw(2 * j) >> 1] = make_float2(a + c, a - c);
-        reinterpret_cast<float2 *>(im)[sw(2 * j) >> 1] = make_float2(0.0f, 0.0f);
-      } else {
-        float vr[4], vi[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      float vr[kR], vi[kR];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) vr[r] = xv[q][r] * win[j + r * Q];
+      for (int r = 0; r < kR; ++r) {
+        const int m = j + r * kBf;
+        vr[r] = xv[q][r][0] * win[2 * m];
+        vi[r] = xv[q][r][1] * win[2 * m + 1];
+      }
+      if constexpr (kOdd) {
+        reinterpret_cast<float2 *>(re)[sw(2 * j) >> 1] = make_float2(vr[0] + vr[1], vr[0] - vr[1]);
+        reinterpret_cast<float2 *>(im)[sw(2 * j) >> 1] = make_float2(vi[0] + vi[1], vi[0] - vi[1]);
+      } else {
         dft4<-1>(vr, vi);
         reinterpret_cast<float4 *>(re)[sw(4 * j) >> 2] = make_float4(vr[0], vr[1], vr[2], vr[3]);
         reinterpret_cast<float4 *>(im)[sw(4 * j) >> 2] = make_float4(vi[0], vi[1], vi[2], vi[3]);
@@ -234,19 +251,33 @@ __global__ __launch_bounds__(kStftThreads) void k_stft(const float *__restrict__
     if (t + 1 < t1) load(t + 1);
     __syncthreads();
     float *sr = re, *si = im, *dr = re2, *di = im2;
-    const int off = middle_passes<NFFT, -1>(sr, si, dr, di, twr, twi);
-    // last pass: bins j and j + NFFT/4 (and NFFT/2 from butterfly 0) to HBM
-    const size_t o = ((size_t)b * T + t) * F;
+    const int off = middle_passes<H, -1>(sr, si, dr, di, twr, twi);
+    // last pass: Z[j + r H/4] into the free buffer, for the pairs (k, H - k)
     for (int j = threadIdx.x; j < Q; j += kStftThreads) {
       float vr[4], vi[4];
-      last_pass<NFFT, -1>(sr, si, twr, twi, off, j, vr, vi);
-      mag[o + j] = hypotf(vr[0], vi[0]);
-      phase[o + j] = atan2f(vi[0], vr[0]);
-      mag[o + j + Q] = hypotf(vr[1], vi[1]);
-      phase[o + j + Q] = atan2f(vi[1], vr[1]);
-      if (j == 0) {
-        mag[o + 2 * Q] = hypotf(vr[2], vi[2]);
-        phase[o + 2 * Q] = atan2f(vi[2], vr[2]);
+      last_pass<H, -1>(sr, si, twr, twi, off, j, vr, vi);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        dr[sw(j + r * Q)] = vr[r];
+        di[sw(j + r * Q)] = vi[r];
+      }
+    }
+    __syncthreads();
+    const size_t o = ((size_t)b * T + t) * F;
+    for (int k = threadIdx.x; k < P; k += kStftThreads) {
+      const int h = k == 0 ? 0 : H - k;
+      const float zkr = dr[sw(k)], zki = di[sw(k)], zhr = dr[sw(h)], zhi = di[sw(h)];
+      const float eer = 0.5f * (zkr + zhr), eei = 0.5f * (zki - zhi);      // Ze
+      const float oor = 0.5f * (zki + zhi), ooi = -0.5f * (zkr - zhr);     // Zo
+      const float c = er[k], s = ei[k];
+      const float pr = c * oor - s * ooi, pi = c * ooi + s * oor;        // exp(-2 pi i k / NFFT) Zo
+      const float xr = eer + pr, xi = eei + pi;
+      mag[o + k] = hypotf(xr, xi);
+      phase[o + k] = atan2f(xi, xr);
+      if (k == 0 || k < H - k) {   // X[H] = Ze - Zo at k = 0, else X[H - k] = conj(Ze - e Zo)
+        const float yr = eer - pr, yi = k == 0 ? eei - pi : -(eei - pi);
+        mag[o + H - k] = hypotf(yr, yi);
+        phase[o + H - k] = atan2f(yi, yr);
       }
     }
   }
@@ -256,65 +287,81 @@ template <int NFFT>
 __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict__ mag, const float *__restrict__ phase,
                                                         int S, int T, int hop, int G, int64_t n,
                                                         float *__restrict__ y) {
-  constexpr int F = NFFT / 2 + 1, Q = NFFT / 4;
-  constexpr bool kOdd = ilog2(NFFT) % 2 == 1;
+  // The real frame of a Hermitian spectrum X comes from an H = NFFT/2 point
+  // complex inverse transform: with Z[k] = (X[k] + conj X[H-k]) + i e_k (X[k] -
+  // conj X[H-k]), e_k = exp(2 pi i k / NFFT), its inverse z gives z[m] =
+  // y[2m] + i y[2m+1].
+  constexpr int H = NFFT / 2, F = H + 1, Q = H / 4, P = H / 2 + 1;   // P pairs (k, H - k), k <= H/2
+  constexpr bool kOdd = ilog2(H) % 2 == 1;
   // the first pass writes 2 or 4 consecutive words per lane
-  __shared__ __align__(16) float re[NFFT];
-  __shared__ __align__(16) float im[NFFT];
-  __shared__ __align__(16) float re2[NFFT];
-  __shared__ __align__(16) float im2[NFFT];
-  __shared__ float twr[NFFT], twi[NFFT], win[NFFT];
+  __shared__ __align__(16) float re[H];
+  __shared__ __align__(16) float im[H];
+  __shared__ __align__(16) float re2[H];
+  __shared__ __align__(16) float im2[H];
+  __shared__ float twr[H], twi[H], win[NFFT], er[P], ei[P];
   __shared__ float acc[NFFT], wacc[NFFT];   // rings: slot i mod NFFT holds sample i
   const int sig = blockIdx.y, mix = sig / S;
   const int t0 = blockIdx.x * G, t1 = min(T, t0 + G);
   const int lead = (NFFT + hop - 1) / hop - 1;   // frames before t0 that cover samples >= t0 hop
   const int ts = max(0, t0 - lead);
-  twiddles<NFFT, 1>(twr, twi);
+  twiddles<H, 1>(twr, twi);
   window<NFFT>(win);
+  for (int k = threadIdx.x; k < P; k += kStftThreads) sincospif(2.0f * (float)k / (float)NFFT, &ei[k], &er[k]);
   for (int i = threadIdx.x; i < NFFT; i += kStftThreads) {
     acc[i] = 0.0f;
     wacc[i] = 0.0f;
   }
   float *ys = y + (size_t)sig * n;
-  // each thread's bins of the next frame, loaded while the current frame's passes run
-  constexpr int kPerF = (F + kStftThreads - 1) / kStftThreads;
-  float mv[kPerF], pv[kPerF];
+  // each thread's pairs of bins (k, H - k) of the next frame, loaded while the
+  // current frame's passes run
+  constexpr int kPerP = (P + kStftThreads - 1) / kStftThreads;
+  float ma[kPerP], pa[kPerP], mb[kPerP], pb[kPerP];
   auto load = [&](int t) {
     const float *ms = mag + ((size_t)sig * T + t) * F, *ps = phase + ((size_t)mix * T + t) * F;
 #pragma unroll
-    for (int q = 0; q < kPerF; ++q) {
+    for (int q = 0; q < kPerP; ++q) {
       const int k = threadIdx.x + q * kStftThreads;
-      mv[q] = k < F ? ms[k] : 0.0f;
-      pv[q] = k < F ? ps[k] : 0.0f;
+      const bool in = k < P;
+      ma[q] = in ? ms[k] : 0.0f;
+      pa[q] = in ? ps[k] : 0.0f;
+      mb[q] = in ? ms[H - k] : 0.0f;
+      pb[q] = in ? ps[H - k] : 0.0f;
     }
   };
   if (ts < t1) load(ts);
   for (int t = ts; t < t1; ++t) {
     __syncthreads();   // the tables and rings are written; the previous frame is folded in
 #pragma unroll
-    for (int q = 0; q < kPerF; ++q) {
+    for (int q = 0; q < kPerP; ++q) {
       const int k = threadIdx.x + q * kStftThreads;
-      if (k >= F) break;
-      float s, c;
-      sincosf(pv[q], &s, &c);
-      const float a = mv[q];
-      // a real signal: bins 0 and NFFT/2 are real (their imaginary parts are dropped)
-      const float yr = a * c, yi = (k == 0 || k == F - 1) ? 0.0f : a * s;
-      re[sw(k)] = yr;
-      im[sw(k)] = yi;
-      if (k > 0 && k < F - 1) {   // Hermitian half
-        re[sw(NFFT - k)] = yr;
-        im[sw(NFFT - k)] = -yi;
+      if (k >= P) break;
+      float sa, ca, sb, cb;
+      sincosf(pa[q], &sa, &ca);
+      sincosf(pb[q], &sb, &cb);
+      // a = X[k], b = X[H - k]; bins 0 and H of a real signal are real (their
+      // imaginary parts are dropped)
+      const float ar = ma[q] * ca, ai = k == 0 ? 0.0f : ma[q] * sa;
+      const float br = mb[q] * cb, bi = k == 0 ? 0.0f : mb[q] * sb;
+      const float c = er[k], d = ei[k];
+      // Z[k] = u + i e v, u = a + conj b, v = a - conj b
+      const float ur = ar + br, ui = ai - bi, vr = ar - br, vi = ai + bi;
+      re[sw(k)] = ur - (c * vi + d * vr);
+      im[sw(k)] = ui + (c * vr - d * vi);
+      if (k > 0 && k < H - k) {
+        // Z[H - k] from the same pair: roles of a and b swapped, e_{H-k} = -conj e_k
+        const float ur2 = br + ar, ui2 = bi - ai, vr2 = br - ar, vi2 = bi + ai;
+        re[sw(H - k)] = ur2 - (-c * vi2 + d * vr2);
+        im[sw(H - k)] = ui2 + (-c * vr2 - d * vi2);
       }
     }
     if (t + 1 < t1) load(t + 1);
     __syncthreads();
     // first pass (ns = 1, twiddles 1) from (re, im) to (re2, im2)
     if constexpr (kOdd) {
-      for (int j = threadIdx.x; j < NFFT / 2; j += kStftThreads) {
-        const float ar = re[sw(j)], ai = im[sw(j)], cr = re[sw(j + NFFT / 2)], ci = im[sw(j + NFFT / 2)];
-        reinterpret_cast<float2 *>(re2)[sw(2 * j) >> 1] = make_float2(ar + cr, ar - cr);
-        reinterpret_cast<float2 *>(im2)[sw(2 * j) >> 1] = make_float2(ai + ci, ai - ci);
+      for (int j = threadIdx.x; j < H / 2; j += kStftThreads) {
+        const float xr = re[sw(j)], xi = im[sw(j)], zr = re[sw(j + H / 2)], zi = im[sw(j + H / 2)];
+        reinterpret_cast<float2 *>(re2)[sw(2 * j) >> 1] = make_float2(xr + zr, xr - zr);
+        reinterpret_cast<float2 *>(im2)[sw(2 * j) >> 1] = make_float2(xi + zi, xi - zi);
       }
     } else {
       for (int j = threadIdx.x; j < Q; j += kStftThreads) {
@@ -331,19 +378,22 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
     }
     __syncthreads();
     float *sr = re2, *si = im2, *dr = re, *di = im;
-    const int off = middle_passes<NFFT, 1>(sr, si, dr, di, twr, twi);
-    // last pass: sample j + r NFFT/4 of the frame, scaled and windowed, into the rings
+    const int off = middle_passes<H, 1>(sr, si, dr, di, twr, twi);
+    // last pass: z[m], m = j + r H/4, is samples 2m (real part) and 2m + 1
+    // (imaginary part) of the frame; scaled and windowed into the rings
     const int64_t base = (int64_t)t * hop;
     for (int j = threadIdx.x; j < Q; j += kStftThreads) {
       float vr[4], vi[4];
-      last_pass<NFFT, 1>(sr, si, twr, twi, off, j, vr, vi);
+      last_pass<H, 1>(sr, si, twr, twi, off, j, vr, vi);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = j + r * Q;
-        const int slot = (int)((base + i) & (NFFT - 1));
-        const float w = win[i];
-        acc[slot] += vr[r] * (1.0f / (float)NFFT) * w;
-        wacc[slot] += w * w;
+        const int i = 2 * (j + r * Q);
+        const int s0 = (int)((base + i) & (NFFT - 1)), s1 = (int)((base + i + 1) & (NFFT - 1));
+        const float w0 = win[i], w1 = win[i + 1];
+        acc[s0] += vr[r] * (1.0f / (float)NFFT) * w0;
+        wacc[s0] += w0 * w0;
+        acc[s1] += vi[r] * (1.0f / (float)NFFT) * w1;
+        wacc[s1] += w1 * w1;
       }
     }
     __syncthreads();
