@@ -3,14 +3,18 @@
 // F = 513 bins; Section 1 resynthesises each separated source with the phase
 // of the mixture).
 //
-// The FFT is a Stockham (self-sorting) transform in LDS: radix-4 passes, with
-// one radix-2 pass first when log2 NFFT is odd.  The pass combining transforms
-// of size ns takes butterfly j (< NFFT/R) from the R inputs j + r NFFT/R,
-// multiplies input r by exp(sign 2 pi i r k / (R ns)), k = j mod ns, does an
-// R-point DFT and writes output r to (j - k) R + k + r ns.  The first pass
-// (ns = 1, no twiddles) reads its inputs where they are, and the last pass
-// (ns = NFFT/4) leaves output r of butterfly j in registers as bin j + r NFFT/4,
-// so only the passes between touch LDS on both sides: 3 of 5 at NFFT = 1024.
+// A real frame of NFFT samples is transformed as NFFT/2 complex points (even
+// samples in the real, odd samples in the imaginary parts), with a pairwise
+// fold or unfold between that transform and the real frame's bins.  The complex
+// FFT of size L (the helpers' template parameter, L = NFFT/2 here) is a Stockham
+// (self-sorting) transform in LDS: radix-4 passes, with one radix-2 pass first
+// when log2 L is odd.  The pass combining transforms of size ns takes butterfly
+// j (< L/R) from the R inputs j + r L/R, multiplies input r by
+// exp(sign 2 pi i r k / (R ns)), k = j mod ns, does an R-point DFT and writes
+// output r to (j - k) R + k + r ns.  The first pass (ns = 1, no twiddles) reads
+// its inputs where they are, and the last pass (ns = L/4) leaves output r of
+// butterfly j in registers as bin j + r L/4, so only the passes between touch
+// LDS on both sides: 3 of 5 at L = 512 (NFFT = 1024).
 //
 //   k_stft   one block per (signal, run of kStftFrames frames): per frame, the
 //            windowed frame, read from HBM as NFFT/2 complex values (even samples
@@ -68,8 +72,8 @@ __device__ __forceinline__ void window(float *win) {
 }
 
 // ns of the first radix-4 pass that has twiddles (4, or 2 after a radix-2 pass)
-template <int NFFT>
-constexpr int first_twiddled() { return ilog2(NFFT) % 2 ? 2 : 4; }
+template <int L>
+constexpr int first_twiddled() { return ilog2(L) % 2 ? 2 : 4; }
 
 // Word a of a transform buffer is kept at sw(a): bits 2-3 and 4-5 of a are
 // XORed with bits 6-7.  The stores of the passes of size 4 and 16 (groups of 4
@@ -81,11 +85,11 @@ __device__ __forceinline__ int sw(int a) { return a ^ (((a >> 6) & 3) * 20); }
 // Twiddles of the radix-4 passes with ns > 1, pass by pass in the order they run:
 // the pass of size ns keeps exp(sign i pi r k / (2 ns)) for r = 1, 2, 3 and
 // k < ns at off + (r - 1) ns + k (off = 3 x the sizes of the passes before), so a
-// wave's lanes read consecutive words.  Fewer than NFFT entries.
-template <int NFFT, int SIGN>
+// wave's lanes read consecutive words.  Fewer than L entries.
+template <int L, int SIGN>
 __device__ __forceinline__ void twiddles(float *twr, float *twi) {
   int off = 0;
-  for (int ns = first_twiddled<NFFT>(); ns < NFFT; ns *= 4) {
+  for (int ns = first_twiddled<L>(); ns < L; ns *= 4) {
     for (int e = threadIdx.x; e < 3 * ns; e += kStftThreads) {
       const int r = e / ns + 1, k = e - (r - 1) * ns;
       float s, c;
@@ -127,10 +131,10 @@ __device__ __forceinline__ void twiddle3(float (&vr)[4], float (&vi)[4], const f
 }
 
 // One radix-4 pass of size ns from (sr, si) to (dr, di), both in LDS.
-template <int NFFT, int SIGN>
+template <int L, int SIGN>
 __device__ __forceinline__ void pass4(const float *sr, const float *si, float *dr, float *di, const float *twr,
                                       const float *twi, int off, int ns) {
-  constexpr int Q = NFFT / 4;
+  constexpr int Q = L / 4;
   for (int j = threadIdx.x; j < Q; j += kStftThreads) {
     const int k = j & (ns - 1);
     float vr[4], vi[4];
@@ -152,14 +156,14 @@ __device__ __forceinline__ void pass4(const float *sr, const float *si, float *d
 
 // The passes between the first and the last.  The first pass has left its output
 // in (sr, si) before a barrier; on return (sr, si) hold the input of the last pass
-// (ns = NFFT/4), written before a barrier, and the result is that pass's twiddle
+// (ns = L/4), written before a barrier, and the result is that pass's twiddle
 // offset.
-template <int NFFT, int SIGN>
+template <int L, int SIGN>
 __device__ __forceinline__ int middle_passes(float *&sr, float *&si, float *&dr, float *&di, const float *twr,
                                              const float *twi) {
   int off = 0;
-  for (int ns = first_twiddled<NFFT>(); ns < NFFT / 4; ns *= 4) {
-    pass4<NFFT, SIGN>(sr, si, dr, di, twr, twi, off, ns);
+  for (int ns = first_twiddled<L>(); ns < L / 4; ns *= 4) {
+    pass4<L, SIGN>(sr, si, dr, di, twr, twi, off, ns);
     off += 3 * ns;
     __syncthreads();
     float *tr = sr, *ti = si;
@@ -171,12 +175,12 @@ __device__ __forceinline__ int middle_passes(float *&sr, float *&si, float *&dr,
   return off;
 }
 
-// The last pass's butterfly j: inputs j + r NFFT/4 from (sr, si); on return
-// (vr[r], vi[r]) is bin j + r NFFT/4.
-template <int NFFT, int SIGN>
+// The last pass's butterfly j: inputs j + r L/4 from (sr, si); on return
+// (vr[r], vi[r]) is bin j + r L/4.
+template <int L, int SIGN>
 __device__ __forceinline__ void last_pass(const float *sr, const float *si, const float *twr, const float *twi,
                                           int off, int j, float (&vr)[4], float (&vi)[4]) {
-  constexpr int Q = NFFT / 4;
+  constexpr int Q = L / 4;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     vr[r] = sr[sw(j + r * Q)];
