@@ -254,7 +254,7 @@ NFHMM_API nfhmm_status nfhmm_special_functions(nfhmm_ctx *ctx, int64_t n, const 
  *             hop <= nfft / 2 this inverts the transform exactly where at least one
  *             frame has w[j] > 0.
  * nfft is a power of two in [64, 4096], 1 <= hop <= nfft, 1 <= B <= 65535 signals
- * (or mixtures) processed together; arrays are dense, C order, float32; errors are
+ * (or mixtures) processed together, 1 <= T <= 2^30 frames; arrays are dense, C order, float32; errors are
  * NFHMM_E_INVALID for bad sizes and NFHMM_E_DEVICE for a failing HIP call. */
 
 /* Frames of a signal of n samples (0 if n < nfft). */

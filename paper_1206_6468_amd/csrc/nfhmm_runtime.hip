@@ -1444,6 +1444,7 @@ nfhmm_status nfhmm_profile_read(nfhmm_ctx *ctx, int kind, int64_t *launches, dou
 
 // ------------------------------------------------------------------ time domain
 namespace {
+constexpr int64_t kMaxFrames = int64_t(1) << 30;   // frame indices and run ends stay in int
 bool stft_sizes_ok(int32_t nfft, int32_t hop, int32_t B) {
   return nfft >= 64 && nfft <= 4096 && (nfft & (nfft - 1)) == 0 && hop >= 1 && hop <= nfft && B >= 1 &&
          B <= 65535;
@@ -1460,7 +1461,7 @@ nfhmm_status nfhmm_stft_device(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_
   if (!ctx || !x || !mag || !phase) return fail(NFHMM_E_INVALID, "NULL argument");
   if (!stft_sizes_ok(nfft, hop, B)) return fail(NFHMM_E_INVALID, "bad nfft, hop or B");
   const int64_t T = nfhmm_stft_frames(nfft, hop, n);
-  if (T < 1 || T > INT32_MAX) return fail(NFHMM_E_INVALID, "the signal has no whole frame (n < nfft) or too many");
+  if (T < 1 || T > kMaxFrames) return fail(NFHMM_E_INVALID, "the signal has no whole frame (n < nfft) or too many");
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
   HIP_OK(launch_stft(nfft, x, n, hop, (int)T, B, mag, phase, st));
@@ -1472,7 +1473,7 @@ nfhmm_status nfhmm_istft_device(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32
   if (!ctx || !mag || !phase || !y) return fail(NFHMM_E_INVALID, "NULL argument");
   if (!stft_sizes_ok(nfft, hop, B) || S < 1 || (int64_t)B * S > 65535)
     return fail(NFHMM_E_INVALID, "bad nfft, hop, B or S");
-  if (T < 1 || T > INT32_MAX || n < 1) return fail(NFHMM_E_INVALID, "bad T or n");
+  if (T < 1 || T > kMaxFrames || n < 1) return fail(NFHMM_E_INVALID, "bad T or n");
   HIP_OK(hipSetDevice(ctx->device));
   hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
   HIP_OK(launch_istft(nfft, mag, phase, (int)T, B, S, hop, n, y, st));
@@ -1484,7 +1485,7 @@ nfhmm_status nfhmm_stft(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, co
   if (!ctx || !x || !mag || !phase) return fail(NFHMM_E_INVALID, "NULL argument");
   if (!stft_sizes_ok(nfft, hop, B)) return fail(NFHMM_E_INVALID, "bad nfft, hop or B");
   const int64_t T = nfhmm_stft_frames(nfft, hop, n);
-  if (T < 1 || T > INT32_MAX) return fail(NFHMM_E_INVALID, "the signal has no whole frame (n < nfft) or too many");
+  if (T < 1 || T > kMaxFrames) return fail(NFHMM_E_INVALID, "the signal has no whole frame (n < nfft) or too many");
   HIP_OK(hipSetDevice(ctx->device));
   std::lock_guard<std::mutex> eng(ctx->engine_mu);
   hipStream_t st = ctx->stream;
@@ -1509,7 +1510,7 @@ nfhmm_status nfhmm_istft(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, i
   if (!ctx || !mag || !phase || !y) return fail(NFHMM_E_INVALID, "NULL argument");
   if (!stft_sizes_ok(nfft, hop, B) || S < 1 || (int64_t)B * S > 65535)
     return fail(NFHMM_E_INVALID, "bad nfft, hop, B or S");
-  if (T < 1 || T > INT32_MAX || n < 1) return fail(NFHMM_E_INVALID, "bad T or n");
+  if (T < 1 || T > kMaxFrames || n < 1) return fail(NFHMM_E_INVALID, "bad T or n");
   HIP_OK(hipSetDevice(ctx->device));
   std::lock_guard<std::mutex> eng(ctx->engine_mu);
   hipStream_t st = ctx->stream;
