@@ -110,3 +110,13 @@ def test_stft_frame_count(L):
     assert L.stft_frames(1024, 256, 1024) == 1
     assert L.stft_frames(1024, 256, 1023) == 0
     assert L.stft_frames(2048, 512, 2048 + 3 * 512 + 511) == 4
+
+
+def test_istft_binding_checks_shapes_before_the_call(L):
+    """The host inverse takes mag [T][F], [S][T][F] or [B][S][T][F] with phase
+    [T][F] or [B][T][F]; a phase of another shape is refused before anything
+    reaches the library (no context is needed to see it)."""
+    with pytest.raises(ValueError):
+        L.istft(None, np.zeros((2, 3, 10, 33), np.float32), np.zeros((3, 10, 33), np.float32), 300, 64, 16)
+    with pytest.raises(ValueError):
+        L.istft(None, np.zeros((2, 10, 33), np.float32), np.zeros((10, 32), np.float32), 300, 64, 16)
