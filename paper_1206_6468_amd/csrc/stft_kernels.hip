@@ -23,7 +23,8 @@
 //            real frame's transform from that FFT's bins k and NFFT/2 - k and
 //            writes |X| and arg X of bins 0..NFFT/2 to HBM.  The window and the
 //            twiddles are tabulated in LDS once per block.
-//   k_istft  one block per (source, run of G consecutive frames): per frame, the
+//   k_istft  one block per (two sources of a mixture, run of G consecutive
+//            frames; the sources share the phase's loads and sincos): per frame, the
 //            Hermitian spectrum mag * exp(i phase) folded into NFFT/2 complex
 //            values whose NFFT/2-point inverse FFT holds the even samples in its
 //            real and the odd samples in its imaginary parts; the last pass adds
@@ -56,6 +57,7 @@ constexpr int kStftThreads = 256;
 #endif
 constexpr int kStftFrames = NFHMM_STFT_FRAMES;    // frames per block of the transform
 constexpr int kIstftRunPerLead = NFHMM_ISTFT_RUN; // inverse: run length per (lead-in + 1) frames
+constexpr int kIstftPair = 2;                     // inverse: sources of one mixture per block
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
 
@@ -294,7 +296,8 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
   // The real frame of a Hermitian spectrum X comes from an H = NFFT/2 point
   // complex inverse transform: with Z[k] = (X[k] + conj X[H-k]) + i e_k (X[k] -
   // conj X[H-k]), e_k = exp(2 pi i k / NFFT), its inverse z gives z[m] =
-  // y[2m] + i y[2m+1].
+  // y[2m] + i y[2m+1].  A block takes kIstftPair sources of one mixture, which
+  // share the phase: its loads and sincos, and the squared-window ring.
   constexpr int H = NFFT / 2, F = H + 1, Q = H / 4, P = H / 2 + 1;   // P pairs (k, H - k), k <= H/2
   constexpr bool kOdd = ilog2(H) % 2 == 1;
   // the first pass writes 2 or 4 consecutive words per lane
@@ -303,8 +306,10 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
   __shared__ __align__(16) float re2[H];
   __shared__ __align__(16) float im2[H];
   __shared__ float twr[H], twi[H], win[NFFT], er[P], ei[P];
-  __shared__ float acc[NFFT], wacc[NFFT];   // rings: slot i mod NFFT holds sample i
-  const int sig = blockIdx.y, mix = sig / S;
+  __shared__ float acc[kIstftPair][NFFT], wacc[NFFT];   // rings: slot i mod NFFT holds sample i
+  const int groups = (S + kIstftPair - 1) / kIstftPair;
+  const int mix = blockIdx.y / groups, s0 = (blockIdx.y - mix * groups) * kIstftPair;
+  const int ns = min(kIstftPair, S - s0);
   const int t0 = blockIdx.x * G, t1 = min(T, t0 + G);
   const int lead = (NFFT + hop - 1) / hop - 1;   // frames before t0 that cover samples >= t0 hop
   const int ts = max(0, t0 - lead);
@@ -312,92 +317,113 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
   window<NFFT>(win);
   for (int k = threadIdx.x; k < P; k += kStftThreads) sincospif(2.0f * (float)k / (float)NFFT, &ei[k], &er[k]);
   for (int i = threadIdx.x; i < NFFT; i += kStftThreads) {
-    acc[i] = 0.0f;
+#pragma unroll
+    for (int s = 0; s < kIstftPair; ++s) acc[s][i] = 0.0f;
     wacc[i] = 0.0f;
   }
-  float *ys = y + (size_t)sig * n;
   // each thread's pairs of bins (k, H - k) of the next frame, loaded while the
   // current frame's passes run
   constexpr int kPerP = (P + kStftThreads - 1) / kStftThreads;
-  float ma[kPerP], pa[kPerP], mb[kPerP], pb[kPerP];
+  float ma[kPerP][kIstftPair], mb[kPerP][kIstftPair], pa[kPerP], pb[kPerP];
   auto load = [&](int t) {
-    const float *ms = mag + ((size_t)sig * T + t) * F, *ps = phase + ((size_t)mix * T + t) * F;
+    const float *ps = phase + ((size_t)mix * T + t) * F;
 #pragma unroll
     for (int q = 0; q < kPerP; ++q) {
       const int k = threadIdx.x + q * kStftThreads;
       const bool in = k < P;
-      ma[q] = in ? ms[k] : 0.0f;
       pa[q] = in ? ps[k] : 0.0f;
-      mb[q] = in ? ms[H - k] : 0.0f;
       pb[q] = in ? ps[H - k] : 0.0f;
+#pragma unroll
+      for (int s = 0; s < kIstftPair; ++s) {
+        const float *ms = mag + (((size_t)mix * S + s0 + s) * T + t) * F;
+        ma[q][s] = in && s < ns ? ms[k] : 0.0f;
+        mb[q][s] = in && s < ns ? ms[H - k] : 0.0f;
+      }
     }
   };
   if (ts < t1) load(ts);
   for (int t = ts; t < t1; ++t) {
     __syncthreads();   // the tables and rings are written; the previous frame is folded in
+    // this frame's bins: the phase's sincos once for every source of the block
+    float ca[kPerP], sa[kPerP], cb[kPerP], sb[kPerP], mca[kPerP][kIstftPair], mcb[kPerP][kIstftPair];
 #pragma unroll
     for (int q = 0; q < kPerP; ++q) {
-      const int k = threadIdx.x + q * kStftThreads;
-      if (k >= P) break;
-      float sa, ca, sb, cb;
-      sincosf(pa[q], &sa, &ca);
-      sincosf(pb[q], &sb, &cb);
-      // a = X[k], b = X[H - k]; bins 0 and H of a real signal are real (their
-      // imaginary parts are dropped)
-      const float ar = ma[q] * ca, ai = k == 0 ? 0.0f : ma[q] * sa;
-      const float br = mb[q] * cb, bi = k == 0 ? 0.0f : mb[q] * sb;
-      const float c = er[k], d = ei[k];
-      // Z[k] = u + i e v, u = a + conj b, v = a - conj b
-      const float ur = ar + br, ui = ai - bi, vr = ar - br, vi = ai + bi;
-      re[sw(k)] = ur - (c * vi + d * vr);
-      im[sw(k)] = ui + (c * vr - d * vi);
-      if (k > 0 && k < H - k) {
-        // Z[H - k] from the same pair: roles of a and b swapped, e_{H-k} = -conj e_k
-        const float ur2 = br + ar, ui2 = bi - ai, vr2 = br - ar, vi2 = bi + ai;
-        re[sw(H - k)] = ur2 - (-c * vi2 + d * vr2);
-        im[sw(H - k)] = ui2 + (-c * vr2 - d * vi2);
+      sincosf(pa[q], &sa[q], &ca[q]);
+      sincosf(pb[q], &sb[q], &cb[q]);
+#pragma unroll
+      for (int s = 0; s < kIstftPair; ++s) {
+        mca[q][s] = ma[q][s];
+        mcb[q][s] = mb[q][s];
       }
     }
     if (t + 1 < t1) load(t + 1);
-    __syncthreads();
-    // first pass (ns = 1, twiddles 1) from (re, im) to (re2, im2)
-    if constexpr (kOdd) {
-      for (int j = threadIdx.x; j < H / 2; j += kStftThreads) {
-        const float xr = re[sw(j)], xi = im[sw(j)], zr = re[sw(j + H / 2)], zi = im[sw(j + H / 2)];
-        reinterpret_cast<float2 *>(re2)[sw(2 * j) >> 1] = make_float2(xr + zr, xr - zr);
-        reinterpret_cast<float2 *>(im2)[sw(2 * j) >> 1] = make_float2(xi + zi, xi - zi);
+    const int64_t base = (int64_t)t * hop;
+#pragma unroll
+    for (int s = 0; s < kIstftPair; ++s) {
+      if (s >= ns) break;
+      if (s > 0) __syncthreads();   // the previous source's last pass has read the buffers
+#pragma unroll
+      for (int q = 0; q < kPerP; ++q) {
+        const int k = threadIdx.x + q * kStftThreads;
+        if (k >= P) break;
+        // a = X[k], b = X[H - k]; bins 0 and H of a real signal are real (their
+        // imaginary parts are dropped)
+        const float ar = mca[q][s] * ca[q], ai = k == 0 ? 0.0f : mca[q][s] * sa[q];
+        const float br = mcb[q][s] * cb[q], bi = k == 0 ? 0.0f : mcb[q][s] * sb[q];
+        const float c = er[k], d = ei[k];
+        // Z[k] = u + i e v, u = a + conj b, v = a - conj b
+        const float ur = ar + br, ui = ai - bi, vr = ar - br, vi = ai + bi;
+        re[sw(k)] = ur - (c * vi + d * vr);
+        im[sw(k)] = ui + (c * vr - d * vi);
+        if (k > 0 && k < H - k) {
+          // Z[H - k] from the same pair: roles of a and b swapped, e_{H-k} = -conj e_k
+          const float ur2 = br + ar, ui2 = bi - ai, vr2 = br - ar, vi2 = bi + ai;
+          re[sw(H - k)] = ur2 - (-c * vi2 + d * vr2);
+          im[sw(H - k)] = ui2 + (-c * vr2 - d * vi2);
+        }
       }
-    } else {
+      __syncthreads();
+      // first pass (ns = 1, twiddles 1) from (re, im) to (re2, im2)
+      if constexpr (kOdd) {
+        for (int j = threadIdx.x; j < H / 2; j += kStftThreads) {
+          const float xr = re[sw(j)], xi = im[sw(j)], zr = re[sw(j + H / 2)], zi = im[sw(j + H / 2)];
+          reinterpret_cast<float2 *>(re2)[sw(2 * j) >> 1] = make_float2(xr + zr, xr - zr);
+          reinterpret_cast<float2 *>(im2)[sw(2 * j) >> 1] = make_float2(xi + zi, xi - zi);
+        }
+      } else {
+        for (int j = threadIdx.x; j < Q; j += kStftThreads) {
+          float vr[4], vi[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            vr[r] = re[sw(j + r * Q)];
+            vi[r] = im[sw(j + r * Q)];
+          }
+          dft4<1>(vr, vi);
+          reinterpret_cast<float4 *>(re2)[sw(4 * j) >> 2] = make_float4(vr[0], vr[1], vr[2], vr[3]);
+          reinterpret_cast<float4 *>(im2)[sw(4 * j) >> 2] = make_float4(vi[0], vi[1], vi[2], vi[3]);
+        }
+      }
+      __syncthreads();
+      float *sr = re2, *si = im2, *dr = re, *di = im;
+      const int off = middle_passes<H, 1>(sr, si, dr, di, twr, twi);
+      // last pass: z[m], m = j + r H/4, is samples 2m (real part) and 2m + 1
+      // (imaginary part) of the frame; scaled and windowed into the rings (the
+      // squared window once, with the first source)
       for (int j = threadIdx.x; j < Q; j += kStftThreads) {
         float vr[4], vi[4];
+        last_pass<H, 1>(sr, si, twr, twi, off, j, vr, vi);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          vr[r] = re[sw(j + r * Q)];
-          vi[r] = im[sw(j + r * Q)];
+          const int i = 2 * (j + r * Q);
+          const int q0 = (int)((base + i) & (NFFT - 1)), q1 = (int)((base + i + 1) & (NFFT - 1));
+          const float w0 = win[i], w1 = win[i + 1];
+          acc[s][q0] += vr[r] * (1.0f / (float)NFFT) * w0;
+          acc[s][q1] += vi[r] * (1.0f / (float)NFFT) * w1;
+          if (s == 0) {
+            wacc[q0] += w0 * w0;
+            wacc[q1] += w1 * w1;
+          }
         }
-        dft4<1>(vr, vi);
-        reinterpret_cast<float4 *>(re2)[sw(4 * j) >> 2] = make_float4(vr[0], vr[1], vr[2], vr[3]);
-        reinterpret_cast<float4 *>(im2)[sw(4 * j) >> 2] = make_float4(vi[0], vi[1], vi[2], vi[3]);
-      }
-    }
-    __syncthreads();
-    float *sr = re2, *si = im2, *dr = re, *di = im;
-    const int off = middle_passes<H, 1>(sr, si, dr, di, twr, twi);
-    // last pass: z[m], m = j + r H/4, is samples 2m (real part) and 2m + 1
-    // (imaginary part) of the frame; scaled and windowed into the rings
-    const int64_t base = (int64_t)t * hop;
-    for (int j = threadIdx.x; j < Q; j += kStftThreads) {
-      float vr[4], vi[4];
-      last_pass<H, 1>(sr, si, twr, twi, off, j, vr, vi);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 2 * (j + r * Q);
-        const int s0 = (int)((base + i) & (NFFT - 1)), s1 = (int)((base + i + 1) & (NFFT - 1));
-        const float w0 = win[i], w1 = win[i + 1];
-        acc[s0] += vr[r] * (1.0f / (float)NFFT) * w0;
-        wacc[s0] += w0 * w0;
-        acc[s1] += vi[r] * (1.0f / (float)NFFT) * w1;
-        wacc[s1] += w1 * w1;
       }
     }
     __syncthreads();
@@ -407,11 +433,17 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
     for (int64_t i = base + threadIdx.x; i < hi; i += kStftThreads) {
       if (i < base + NFFT) {
         const int r = (int)(i & (NFFT - 1));
-        if (t >= t0) ys[i] = wacc[r] > 0.0f ? acc[r] / wacc[r] : 0.0f;
-        acc[r] = 0.0f;
+        const float w = wacc[r];
+#pragma unroll
+        for (int s = 0; s < kIstftPair; ++s) {
+          if (s < ns && t >= t0) y[((size_t)mix * S + s0 + s) * n + i] = w > 0.0f ? acc[s][r] / w : 0.0f;
+          acc[s][r] = 0.0f;
+        }
         wacc[r] = 0.0f;
       } else if (t >= t0) {
-        ys[i] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < kIstftPair; ++s)
+          if (s < ns) y[((size_t)mix * S + s0 + s) * n + i] = 0.0f;
       }
     }
   }
@@ -441,7 +473,7 @@ int istft_run(int nfft, int hop) {
 hipError_t launch_istft(int nfft, const float *mag, const float *phase, int T, int B, int S, int hop, int64_t n,
                         float *y, hipStream_t st) {
   const int G = istft_run(nfft, hop);
-  const dim3 grid((unsigned)((T + G - 1) / G), B * S);
+  const dim3 grid((unsigned)((T + G - 1) / G), B * ((S + kIstftPair - 1) / kIstftPair));
   switch (nfft) {
 #define NFHMM_ISTFT_CASE(P) \
   case P: k_istft<P><<<grid, kStftThreads, 0, st>>>(mag, phase, S, T, hop, G, n, y); break;
