@@ -359,8 +359,9 @@ def istft(ctx: Context, mag, phase, n, nfft=1024, hop=256):
     m4 = mag.reshape((1, 1) + mag.shape) if mag.ndim == 2 else mag.reshape((1,) + mag.shape) if mag.ndim == 3 \
         else mag
     B, S, T, F = m4.shape
-    if phase.shape != (T, F) and phase.shape != (B, T, F):
-        raise ValueError(f"phase shape {phase.shape} does not match mag {mag.shape}")
+    # one phase per mixture: [T][F] only when there is one mixture
+    if phase.shape != (B, T, F) and not (B == 1 and phase.shape == (T, F)):
+        raise ValueError(f"phase shape {phase.shape} does not match mag {mag.shape} (want {(B, T, F)})")
     y = np.empty((B, S, int(n)), dtype=np.float32)
     _check(_lib.nfhmm_istft(ctx.handle, nfft, hop, B, S, _ptr(m4), _ptr(phase), T, _ptr(y), int(n)), ctx.handle)
     return y.reshape(mag.shape[:-2] + (int(n),))

@@ -120,3 +120,5 @@ def test_istft_binding_checks_shapes_before_the_call(L):
         L.istft(None, np.zeros((2, 3, 10, 33), np.float32), np.zeros((3, 10, 33), np.float32), 300, 64, 16)
     with pytest.raises(ValueError):
         L.istft(None, np.zeros((2, 10, 33), np.float32), np.zeros((10, 32), np.float32), 300, 64, 16)
+    with pytest.raises(ValueError):   # several mixtures need one phase each
+        L.istft(None, np.zeros((2, 3, 10, 33), np.float32), np.zeros((10, 33), np.float32), 300, 64, 16)
