@@ -50,7 +50,7 @@ namespace {
 
 constexpr int kStftThreads = 256;
 #ifndef NFHMM_STFT_FRAMES
-#define NFHMM_STFT_FRAMES 4
+#define NFHMM_STFT_FRAMES 8
 #endif
 #ifndef NFHMM_ISTFT_RUN
 #define NFHMM_ISTFT_RUN 8
