@@ -98,3 +98,29 @@ def test_serving_rejects_job_over_budget(L):
         assert e.value.status == L.E_INVALID
     finally:
         ctx.close()
+
+
+def test_host_fits_beside_serving(L):
+    # host-array fits and the serving loop share the context's pinned copy ring
+    # and its engine: fits made while submitted jobs are queued and resident must
+    # still equal the same fits alone, and so must the served jobs
+    probs = _mix()
+    extra = [dict(make_problem(0, 30), iters=4), dict(make_tiny(S=2, N=6, K=3, F=90, T=200, seed=31,
+                                                               quanta=1500), iters=5)]
+    alone_ctx = L.Context(0)
+    alone = [L.fit(alone_ctx, p, "fp32") for p in probs]
+    alone_extra = L.fit_batch(alone_ctx, extra, "fp32")
+    alone_ctx.close()
+    fps = [L.footprint_bytes(p, "fp32") for p in probs]
+    ctx = L.Context(0, hbm_budget_bytes=sorted(fps)[-1] + sorted(fps)[-2], max_slots=3)
+    try:
+        subs = [L.submit(ctx, p, "fp32") for p in probs]
+        got_extra = [L.fit_batch(ctx, extra, "fp32") for _ in range(3)]   # while the jobs run
+        for s, a in zip(subs, alone):
+            out, _ = L.wait(ctx, s)
+            _same(out, a)
+        for ge in got_extra:
+            for g, a in zip(ge, alone_extra):
+                _same(g, a)
+    finally:
+        ctx.close()
