@@ -26,18 +26,18 @@ PEAK_BF16_MFMA = 2.5e15       # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12             # B/s
 
 
-def _traffic_for(kernel, workload):
+def _traffic_for(kernel, workload, record="hbm_traffic.json"):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
-    a plain copy) from the committed counter record, if it was taken on the
-    current kernel sources and this workload; else None."""
-    from paper_1206_6468_amd.rocprof_summary import kernel_source_hash
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    a plain copy) from a committed counter record, if it was taken on the
+    current sources of the kernels it covers and on this workload; else None."""
+    from paper_1206_6468_amd.rocprof_summary import KERNEL_SOURCES, kernel_source_hash
+    path = os.path.join(ROOT, "profiles", record)
     try:
         with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_hash") != kernel_source_hash():
+    if d.get("kernel_source_hash") != kernel_source_hash(tuple(d.get("kernel_sources", KERNEL_SOURCES))):
         return None
     e = d.get("kernels", {}).get(kernel, {})
     if e.get("workload") != workload:
@@ -209,7 +209,17 @@ def stft_bench(L, ctx, jobs=32, sources=2, frames=1000, nfft=1024, hop=256, reps
     ms_i = e[1].elapsed_time(e[2]) / reps
     bytes_f = jobs * n * 4 + 2 * jobs * frames * F * 4
     bytes_i = jobs * sources * frames * F * 4 + jobs * frames * F * 4 + jobs * sources * n * 4
+    rec, wl = f"stft_hbm_traffic_T{frames}-nfft{nfft}-hop{hop}_x{jobs}.json", \
+        f"stft-T{frames}-nfft{nfft}-hop{hop}-x{jobs}-S{sources}"
+
+    def roof(kernel, nbytes, ms):
+        # HBM-bound in principle; LDS and barriers bound it in practice
+        return {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": nbytes / (ms * 1e-3) / PEAK_HBM, "algorithmic_bytes_per_launch": nbytes,
+                "traffic": _traffic_for(kernel, wl, rec)}
     return {
+        "roofline": {"k_stft": roof(f"k_stft<{nfft}>", bytes_f, ms_f),
+                     "k_istft": roof(f"k_istft<{nfft}>", bytes_i, ms_i)},
         "workload": f"{jobs} mixtures of {n} samples (T={frames}, nfft={nfft}, hop={hop}), {sources} sources each",
         "stft_ms": ms_f, "stft_frames_per_s": jobs * frames / (ms_f * 1e-3),
         "stft_gbps": bytes_f / (ms_f * 1e-3) / 1e9, "stft_frac_hbm": bytes_f / (ms_f * 1e-3) / PEAK_HBM,
