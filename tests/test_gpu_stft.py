@@ -28,10 +28,10 @@ def ctx(L):
     c.close()
 
 
-# (nfft, hop, B, n): several blocks of frames each, hops that do and do not divide
-# nfft, a hop with a long lead-in (256 / 7), no overlap (hop = nfft)
+# (nfft, hop, B, n): every supported nfft, several blocks of frames each, hops that
+# do and do not divide nfft, a hop with a long lead-in (256 / 7), no overlap (hop = nfft)
 CASES = [(1024, 256, 3, 40_000), (64, 16, 2, 1000), (2048, 512, 2, 30_000), (256, 100, 1, 5001),
-         (4096, 1024, 1, 20_000), (128, 128, 2, 999), (256, 7, 1, 3000)]
+         (4096, 1024, 1, 20_000), (128, 128, 2, 999), (256, 7, 1, 3000), (512, 128, 2, 9001)]
 
 
 @pytest.mark.parametrize("nfft,hop,B,n", CASES)
