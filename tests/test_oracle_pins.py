@@ -323,3 +323,53 @@ def test_P12_recovery_report():
     acc = float((out["post"].argmax(-1) == p["states"]).mean())
     print(f"P12: config-0 argmax state recovery {acc:.3f}")
     assert acc > 0.5
+
+
+# ------------------------------------------------------------------ P13 (the default start, reading R1)
+def check_default_start(init_alpha):
+    """Reading R1 (Eq. 6 with z-hat proportional to beta and d-hat = 1/N) against two
+    things it fixes: (a) sum_k alpha0[t, k] = v_t + gamma S K + M, since the counts
+    of a frame sum to v_t and each source's N state weights 1/N cover K elements
+    each; (b) alpha0 - 1 - gamma/N equals sum_l V[l, t] z[t, l, k] with Eq. 7's
+    responsibilities written out element by element at equal expected log-weights
+    (brute.zhat_explicit at E = 0)."""
+    for seed, (S, N, K), gamma in ((0, (2, 3, 2), 1.0), (1, (3, 4, 1), 0.5), (2, (2, 5, 3), 2.5)):
+        p = make_tiny(S=S, N=N, K=K, F=7, T=6, seed=40 + seed, quanta=60)
+        V, beta, A, pi = O.paper_arrays(p)
+        M = S * N * K
+        a0 = init_alpha(V, beta, O.mask_B(S, N, K), gamma, N)
+        assert a0.shape == (p["T"], M)
+        np.testing.assert_allclose(a0.sum(1), V.sum(0) + gamma * S * K + M, rtol=1e-12)
+        z = brute.zhat_explicit(np.zeros((p["T"], M)), beta)            # T x F x M
+        np.testing.assert_allclose(a0 - 1.0 - gamma / N, np.einsum("lt,tlk->tk", V, z), rtol=1e-12, atol=1e-12)
+
+
+def test_P13_default_start():
+    check_default_start(O.init_alpha)
+
+
+# ------------------------------------------------------------------ P14 (Section 4, worked examples)
+def _golden_separation_cases():
+    import json
+    import os
+    from fractions import Fraction
+    with open(os.path.join(os.path.dirname(__file__), "golden", "separation_mask.json")) as f:
+        d = json.load(f)
+    fr = lambda a: np.array([[float(Fraction(x)) for x in row] for row in a])  # noqa: E731
+    for c in d["cases"]:
+        Vstar = np.stack([fr(s) for s in c["Vstar"]])                       # S x T x F
+        yield c, fr(c["beta"]).T, fr(c["alpha"]), fr(c["V"]).T, Vstar
+
+
+def check_separation_golden(separate):
+    """Section 4's split on hand-derived cases (tests/golden/separation_mask.json):
+    the right block of elements per source, the posterior-mean weights of reading
+    R6, and the zero cases of reading R7."""
+    for c, beta, alpha, V, Vstar in _golden_separation_cases():
+        out = separate(alpha, beta, V, c["S"], c["N"], c["K"])             # S x F x T
+        np.testing.assert_allclose(np.transpose(out, (0, 2, 1)), Vstar, rtol=1e-14, atol=1e-14,
+                                   err_msg=c["name"])
+
+
+def test_P14_separation_worked_examples():
+    check_separation_golden(O.separate)
