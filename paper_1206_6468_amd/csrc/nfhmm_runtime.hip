@@ -29,6 +29,7 @@
 #include "host_copy.h"
 #include "jobdesc.h"
 #include "launch.h"
+#include "table_ring.h"
 
 using namespace nfhmm;
 
@@ -101,15 +102,6 @@ struct Layout {
 };
 
 }  // namespace
-
-int nfhmm::fb_chunk_frames() {
-  static const int len = [] {
-    const char *e = getenv("NFHMM_FB_CHUNK");
-    const int v = e ? atoi(e) : 0;
-    return v > 0 ? v : kFbChunk;
-  }();
-  return len;
-}
 
 namespace {
 
@@ -356,14 +348,24 @@ void fill_desc(Job &j, float gamma) {
 enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFBR, kFB, kPost, kChain, kUpd, kFrames, kRecon, kIters, kNumLists };
 
 struct Table {
-  std::vector<uint64_t> key;
   WorkList lists[kNumLists];
   int nmax = 1, mpmax = 32, upd_stride = 32;
   bool spec_small = false;   // 64 x 64 spectrum tiles (the batch would not fill the chip)
   char *dev = nullptr, *host = nullptr;
   size_t cap = 0;
-  hipEvent_t ready = nullptr;
 };
+
+// Stream and event operations of the table ring (table_ring.h).
+struct HipRingOps {
+  using Stream = hipStream_t;
+  using Event = hipEvent_t;
+  bool create(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableTiming) == hipSuccess; }
+  bool record(hipEvent_t e, hipStream_t st) { return hipEventRecord(e, st) == hipSuccess; }
+  bool sync(hipEvent_t e) { return hipEventSynchronize(e) == hipSuccess; }
+  bool stream_wait(hipStream_t st, hipEvent_t e) { return hipStreamWaitEvent(st, e, 0) == hipSuccess; }
+  void destroy(hipEvent_t e) { (void)hipEventDestroy(e); }
+};
+constexpr int kTableSlots = 16;
 
 // below this many 128 x 64 blocks the spectrum runs on 64 x 64 tiles (twice
 // the blocks), so that a small batch still spreads over the 256 CUs
@@ -414,8 +416,10 @@ struct nfhmm_ctx {
   static constexpr int kMaxGroups = 2;
   int groups = 2;
   struct Lane { hipStream_t main, fb; hipEvent_t fork, join, done; } lanes[kMaxGroups] = {};
-  std::vector<std::unique_ptr<Table>> tables;   // ring
-  size_t table_next = 0;
+  // work-list tables: data per slot, reuse and recycling by the ring
+  Table tables[kTableSlots];
+  HipRingOps ring_ops;
+  TableRing<HipRingOps> ring{ring_ops, kTableSlots};
   std::map<size_t, std::vector<char *>> arena_cache;   // fit paths: reusable arenas by size
 
   // Held while host code issues device work: by a blocking fit or chain call
@@ -479,17 +483,35 @@ hipError_t table_reserve(Table &t, size_t bytes) {
   return hipSuccess;
 }
 
-// Build (or reuse) the table for `jobs`, ordered on `st`.
-nfhmm_status get_table(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st, Table **out) {
+// Build (or reuse) the table for `jobs`, to be read by launches on `st`.  The
+// caller holds the returned lease until its last launch reading the table has
+// been queued on `st`; the lease then records that use, and the ring rewrites the
+// slot only after every recorded use has finished.
+struct TableLease {
+  nfhmm_ctx *ctx = nullptr;
+  int slot = -1;
+  hipStream_t st = nullptr;
+  TableLease() = default;
+  TableLease(const TableLease &) = delete;
+  TableLease &operator=(const TableLease &) = delete;
+  ~TableLease() {
+    if (slot >= 0) (void)ctx->ring.used(slot, st);
+  }
+};
+
+nfhmm_status get_table(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st, Table **out,
+                       TableLease &lease) {
   std::vector<uint64_t> key;
   for (Job *j : jobs) key.push_back(j->id);
-  for (auto &t : ctx->tables)
-    if (t && t->key == key && !key.empty()) { *out = t.get(); return NFHMM_OK; }
-  if (ctx->tables.size() < 16) ctx->tables.emplace_back(new Table());
-  Table &t = *ctx->tables[ctx->table_next % ctx->tables.size()];
-  ctx->table_next++;
-  if (t.ready) HIP_OK(hipEventSynchronize(t.ready));   // a previous use may still be copying
-  else HIP_OK(hipEventCreateWithFlags(&t.ready, hipEventDisableTiming));
+  bool rewrite = false;
+  const int slot = ctx->ring.acquire(key, st, &rewrite);
+  if (slot < 0) return fail(NFHMM_E_DEVICE, "work-list table ring: a stream or event operation failed");
+  Table &t = ctx->tables[slot];
+  lease.ctx = ctx;
+  lease.slot = slot;
+  lease.st = st;
+  *out = &t;
+  if (!rewrite) return NFHMM_OK;
   const int n = (int)jobs.size();
   const size_t desc_bytes = rup((int64_t)n * sizeof(JobDesc), 256);
   const size_t list_bytes = rup((int64_t)(n + 1) * sizeof(int), 256);
@@ -523,9 +545,7 @@ nfhmm_status get_table(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream
     t.lists[k].total = acc;
   }
   HIP_OK(hipMemcpyAsync(t.dev, t.host, total, hipMemcpyHostToDevice, st));
-  HIP_OK(hipEventRecord(t.ready, st));
-  t.key = key;
-  *out = &t;
+  if (!ctx->ring.written(slot, st)) return fail(NFHMM_E_DEVICE, "work-list table ring: event record failed");
   return NFHMM_OK;
 }
 
@@ -767,7 +787,8 @@ nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStr
   }
   if (!uni.empty()) {
     Table *t;
-    nfhmm_status s = get_table(ctx, uni, st, &t);
+    TableLease lease;
+    nfhmm_status s = get_table(ctx, uni, st, &t, lease);
     if (s != NFHMM_OK) return s;
     HIP_OK(launch_spectrum(t->lists[kSpecF], false, t->spec_small, st));
     HIP_OK(launch_spectrum(t->lists[kSpecH], true, t->spec_small, st));
@@ -777,7 +798,8 @@ nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStr
   }
   if (!warm.empty()) {
     Table *t;
-    nfhmm_status s = get_table(ctx, warm, st, &t);
+    TableLease lease;
+    nfhmm_status s = get_table(ctx, warm, st, &t, lease);
     if (s != NFHMM_OK) return s;
     HIP_OK(launch_update(t->lists[kUpd], kUpdFromAlpha, 0, t->upd_stride, st));
   }
@@ -820,7 +842,8 @@ nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int 
                             hipStream_t fb, hipEvent_t ev_fork, hipEvent_t ev_join) {
   if (jobs.empty()) return NFHMM_OK;
   Table *t;
-  nfhmm_status s = get_table(ctx, jobs, st, &t);
+  TableLease lease;   // the chains on fb are covered: st waits for them before the update
+  nfhmm_status s = get_table(ctx, jobs, st, &t, lease);
   if (s != NFHMM_OK) return s;
   HIP_OK(hipEventRecord(ev_fork, st));
   HIP_OK(hipStreamWaitEvent(fb, ev_fork, 0));
@@ -854,7 +877,8 @@ nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int 
 nfhmm_status engine_finish(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st) {
   if (jobs.empty()) return NFHMM_OK;
   Table *t;
-  nfhmm_status s = get_table(ctx, jobs, st, &t);
+  TableLease lease;
+  nfhmm_status s = get_table(ctx, jobs, st, &t, lease);
   if (s != NFHMM_OK) return s;
   HIP_OK(launch_finish(t->lists[kFrames], t->lists[kRecon], t->lists[kIters], st));
   return NFHMM_OK;
@@ -1155,7 +1179,6 @@ nfhmm_status nfhmm_create(nfhmm_ctx **out, int device, size_t hbm_budget_bytes, 
   c->max_slots = max_slots > 0 ? max_slots : 64;
   HIP_OK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
-  if (const char *g = getenv("NFHMM_GROUPS")) c->groups = std::max(1, std::min(nfhmm_ctx::kMaxGroups, atoi(g)));
   for (auto &ln : c->lanes) {
     HIP_OK(hipStreamCreateWithFlags(&ln.main, hipStreamNonBlocking));
     HIP_OK(hipStreamCreateWithFlags(&ln.fb, hipStreamNonBlocking));
@@ -1194,10 +1217,8 @@ void nfhmm_destroy(nfhmm_ctx *ctx) {
   }
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   for (auto &t : ctx->tables) {
-    if (!t) continue;
-    if (t->dev) (void)hipFree(t->dev);
-    if (t->host) (void)hipHostFree(t->host);
-    if (t->ready) (void)hipEventDestroy(t->ready);
+    if (t.dev) (void)hipFree(t.dev);
+    if (t.host) (void)hipHostFree(t.host);
   }
   (void)hipEventDestroy(ctx->ev_fork);
   (void)hipEventDestroy(ctx->ev_join);
