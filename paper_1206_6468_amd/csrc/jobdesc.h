@@ -36,16 +36,8 @@ constexpr int kMaxSources = 8;
 
 // Block tiles of the two contractions: 2 x 2 wavefronts of 16*W rows x 16*W
 // columns each.  Lambda (spectrum): bins x frames; counts: elements x frames.
-#ifndef NFHMM_SPEC_WM
-#define NFHMM_SPEC_WM 4
-#define NFHMM_SPEC_WN 2
-#endif
-#ifndef NFHMM_CNT_WM
-#define NFHMM_CNT_WM 2
-#define NFHMM_CNT_WN 2
-#endif
-constexpr int kSpecWM = NFHMM_SPEC_WM, kSpecWN = NFHMM_SPEC_WN;
-constexpr int kCntWM = NFHMM_CNT_WM, kCntWN = NFHMM_CNT_WN;
+constexpr int kSpecWM = 4, kSpecWN = 2;
+constexpr int kCntWM = 2, kCntWN = 2;
 constexpr int kSpecBM = 32 * kSpecWM, kSpecBN = 32 * kSpecWN;
 constexpr int kCntBM = 32 * kCntWM, kCntBN = 32 * kCntWN;
 constexpr int kSpecSmallBM = 64, kSpecSmallBN = 64;   // spectrum tile for small batches
@@ -56,10 +48,8 @@ constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
 // results do not depend on what else runs beside it.
 constexpr int kFbChunk = 64;
 constexpr int kFbMaxChunks = 256;
-int fb_chunk_frames();   // kFbChunk, or the NFHMM_FB_CHUNK environment variable (tuning)
 inline void fb_geometry(int T, int *C, int *L) {
-  const int len = fb_chunk_frames();
-  int c = (T + len - 1) / len;
+  int c = (T + kFbChunk - 1) / kFbChunk;
   c = c < 1 ? 1 : (c > kFbMaxChunks ? kFbMaxChunks : c);
   const int l = (T + c - 1) / c;
   *L = l;

@@ -498,12 +498,9 @@ __device__ void gemm_nt_bf16_dma(const uint16_t *__restrict__ A, int lda, int ar
 // Two block tiles: 128 bins x 64 frames for large batches, 64 x 64 when the batch would not
 // fill the chip.  Either way the per-frame partials of sum V ln Lambda go to one
 // slot per 64 bins (nsl slots), so the bound does not depend on the tile chosen.
+// Two blocks of four wavefronts per CU fit the LDS; the registers are held to that.
 template <bool kBF16, int WM, int WN>
-#ifndef NFHMM_SPEC_WAVES
-#define NFHMM_SPEC_WAVES 2
-#endif
-// two blocks of four wavefronts per CU fit the LDS; hold the registers to that
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NFHMM_SPEC_WAVES))) void k_spectrum(WorkList wl) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_spectrum(WorkList wl) {
   static_assert(WM == 2 || WM == 4, "a wave row covers 32 or 64 bins");
   constexpr int BM = 32 * WM, BN = 32 * WN;
   const int b = xcd_remap(blockIdx.x, wl.total);
@@ -700,21 +697,14 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
 constexpr float kRescue = 9.5367431640625e-07f;      // 2^-20
 constexpr float kChunkTol = 9.5367431640625e-07f;    // 2^-20
 constexpr float kChunkFloor = 8.673617379884035e-19f;  // 2^-60
-#ifndef NFHMM_FB_BLOCK
-#define NFHMM_FB_BLOCK 8
-#endif
-constexpr int kFbBlock = NFHMM_FB_BLOCK;
+constexpr int kFbBlock = 8;
 
 // One recursion step: every lane publishes x through LDS, then forms
 // y = sum_m x_m coef[m]; tot is the normaliser (lane N's row, or a reduction).
-#ifndef NFHMM_FB_LDS
-#define NFHMM_FB_LDS 1
-#endif
 template <int NR>
 __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&coef)[NR], float x, int lane, int N,
                                              bool sumlane, bool live, bool fwd, float &tot) {
   float y0 = 0.0f, y1 = 0.0f, y2 = 0.0f, y3 = 0.0f;
-#if NFHMM_FB_LDS
   if (lane < NR) buf[p * NR + lane] = x;
   // The block is one wavefront and LDS executes a wavefront's operations in issue
   // order, so the reads below see every lane's write; only the compiler must not
@@ -732,19 +722,6 @@ __device__ __forceinline__ float chain_apply(float *buf, int &p, const float (&c
     y2 = fmaf(v[q].z, coef[4 * q + 2], y2);
     y3 = fmaf(v[q].w, coef[4 * q + 3], y3);
   }
-#else
-  // Every lane needs the whole message: read it lane by lane into scalar
-  // registers (no LDS round trip, whose latency grows with the LDS traffic of
-  // other waves on the same CU).
-  const int xi = __float_as_int(x);
-#pragma unroll
-  for (int m = 0; m < NR; m += 4) {
-    y0 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m)), coef[m], y0);
-    y1 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m + 1)), coef[m + 1], y1);
-    y2 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m + 2)), coef[m + 2], y2);
-    y3 = fmaf(__int_as_float(__builtin_amdgcn_readlane(xi, m + 3)), coef[m + 3], y3);
-  }
-#endif
   const float y = (y0 + y1) + (y2 + y3);
   if (sumlane) tot = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), N));
   else tot = wave_sum(live ? (fwd ? x : y) : 0.0f);
@@ -1252,13 +1229,7 @@ __global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
 // it is c + gamma B'd + 1 and nothing else reads it.
 __device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
 
-#ifndef NFHMM_UPD_U
-#define NFHMM_UPD_U 4
-#endif
-#ifndef NFHMM_UPD_ATTR
-#define NFHMM_UPD_ATTR
-#endif
-constexpr int kUpdU = NFHMM_UPD_U;   // elements per lane whose loads are issued together
+constexpr int kUpdU = 4;   // elements per lane whose loads are issued together
 constexpr int kMaxTail = 4;   // tail bins handled here (F mod 64 <= 4)
 
 template <bool kBF16>
@@ -1463,7 +1434,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
   if (lane == 0 && Ft > 0) vll[(size_t)nsl * T + t] = vf2{vl.hi, vl.lo};
 }
 
-__global__ __launch_bounds__(256) NFHMM_UPD_ATTR void k_update(WorkList wl, int mode, int round, int stride) {
+__global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round, int stride) {
   extern __shared__ float smem[];   // per wave: [Mp] alpha, then psi(alpha); then [S N] d-hat
   const int b = blockIdx.x;
   const int jb = find_job(wl.start, wl.njobs, b);

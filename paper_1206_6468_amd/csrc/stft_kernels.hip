@@ -49,14 +49,8 @@ namespace nfhmm {
 namespace {
 
 constexpr int kStftThreads = 256;
-#ifndef NFHMM_STFT_FRAMES
-#define NFHMM_STFT_FRAMES 8
-#endif
-#ifndef NFHMM_ISTFT_RUN
-#define NFHMM_ISTFT_RUN 8
-#endif
-constexpr int kStftFrames = NFHMM_STFT_FRAMES;    // frames per block of the transform
-constexpr int kIstftRunPerLead = NFHMM_ISTFT_RUN; // inverse: run length per (lead-in + 1) frames
+constexpr int kStftFrames = 8;         // frames per block of the transform
+constexpr int kIstftRunPerLead = 8;    // inverse: run length per (lead-in + 1) frames
 constexpr int kIstftPair = 2;                     // inverse: sources of one mixture per block
 
 constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
