@@ -85,12 +85,18 @@ def time_batch(L, ctx, jobs, precision, steps, warmup, profile=False, kinds=None
     return dt, prof
 
 
-def _gen4(j):
+def serving_problems(n_jobs):
+    """The serving-mix problems, drawn on host threads (no child processes: the
+    bench process holds GPU state once it has run a fit)."""
+    from concurrent.futures import ThreadPoolExecutor
+
     from gen import make_problem
-    return make_problem(4, j)
+    log(f"serving: generating {n_jobs} serving-mix problems")
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(lambda j: make_problem(4, j), range(n_jobs)))
 
 
-def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
+def serving(L, probs, budget_bytes, max_slots, load=0.8, seed=4):
     """Serving form: n_jobs serving-mix jobs (S in {2,3}, T in [200, 4000], 50
     iterations, BF16 contraction) through nfhmm_submit / nfhmm_wait on a context
     with a device-memory budget.  First all jobs at once (saturated throughput),
@@ -98,13 +104,10 @@ def serving(L, n_jobs, budget_bytes, max_slots, load=0.8, seed=4):
     scheduled arrival to the outputs in host memory), then the same jobs one at a
     time with nfhmm_fit in FP32 as the sequential baseline."""
     import threading
-    from multiprocessing import Pool
 
     import numpy as np
 
-    log(f"serving: generating {n_jobs} serving-mix problems")
-    with Pool(min(16, os.cpu_count() or 1)) as pool:
-        probs = pool.map(_gen4, range(n_jobs))
+    n_jobs = len(probs)
     work = sum(p["T"] * p["iters"] for p in probs)
     ctx = L.Context(0, hbm_budget_bytes=budget_bytes, max_slots=max_slots)
     try:
@@ -365,6 +368,8 @@ def main():
         print(json.dumps(stft_bench(L, ctx, reps=max(args.steps, 1))), flush=True)
         ctx.close()
         return
+    # host-side inputs first, before anything touches the GPU
+    serving_probs = None if args.no_serving else serving_problems(args.serving_jobs)
     log(f"generating {args.jobs} paper-typical problems")
     probs = make_jobs(1, args.jobs)
     S, N, K, F, T, iters = (probs[0][k] for k in ("S", "N", "K", "F", "T", "iters"))
@@ -492,7 +497,7 @@ def main():
     }
     out.update(extra)
     if not args.no_serving:
-        out["serving"] = serving(L, args.serving_jobs, int(args.serving_budget_gib * (1 << 30)), 64)
+        out["serving"] = serving(L, serving_probs, int(args.serving_budget_gib * (1 << 30)), 64)
     if not args.no_cpu:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline()

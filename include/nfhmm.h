@@ -152,14 +152,18 @@ NFHMM_API nfhmm_status nfhmm_fit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_p
                        nfhmm_result *r);
 
 /* Blocking fit of n independent problems (host memory) that run together: every
- * iteration's kernels cover all n jobs in the same launches.  Each job's results are
- * bitwise identical to fitting it alone.  Returns the first failing job's status. */
+ * iteration's kernels cover all n jobs in the same launches.  Each job's alpha, post
+ * and sep are bitwise identical to fitting it alone.  Its elbo trace may differ in
+ * the last bits (relative 1e-12 at most): a batch that fills the chip takes the
+ * spectrum contraction in larger tiles, which sums the bound's per-bin terms in
+ * another order.  Returns the first failing job's status; the other jobs' outputs
+ * are complete. */
 NFHMM_API nfhmm_status nfhmm_fit_batch(nfhmm_ctx *ctx, int n, const nfhmm_problem *ps,
                              nfhmm_precision prec, nfhmm_result *rs);
 
 /* As nfhmm_fit_batch, but every array pointer in ps[] and rs[] is a device pointer
  * on the context's device (the structs themselves are in host memory) and the work
- * is ordered on `hip_stream` (a hipStream_t; NULL = the null stream).  Only the dims
+ * is ordered on `hip_stream` (a hipStream_t; NULL = the context's own stream).  Only the dims
  * are checked on the host; V >= 0 / finite and W rows summing to 1 are checked on the
  * device and reported as NFHMM_E_INVALID.  Blocks until the work is done.
  * Working memory stays cached in the context for the next call of the same shapes. */
