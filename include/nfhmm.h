@@ -174,6 +174,23 @@ NFHMM_API nfhmm_status nfhmm_fit_batch_device(nfhmm_ctx *ctx, int n, const nfhmm
 NFHMM_API nfhmm_status nfhmm_fit_device(nfhmm_ctx *ctx, const nfhmm_problem *dev_p,
                               nfhmm_precision prec, nfhmm_result *dev_r, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): nfhmm_fit_device for one
+ * problem, with every intermediate array in a fixed working area that the library
+ * holds on each device for the life of the process (96 MiB, a static device array)
+ * instead of memory it allocates.  The call allocates nothing: no hipMalloc, no
+ * hipFree, no event or stream creation; the caller passes the device inputs and
+ * outputs as for nfhmm_fit_device, and the work runs on `hip_stream` (NULL: the
+ * context's stream) in order, one kernel after another.  Blocks until done and
+ * returns the job's status as nfhmm_fit_device does.
+ * Limits: the job's working set (the sum of its arrays, about 25 MB for S=2, N=40,
+ * K=10, F=513, T=1000) must fit the 96 MiB, else NFHMM_E_NOMEM with nothing run.
+ * Every call on one device (from any context of the process) uses the same area and
+ * overwrites what the last call left there: calls that overlap in time on one GPU
+ * race and must be serialised by the caller. */
+NFHMM_API nfhmm_status nfhmm_fit_device_noalloc(nfhmm_ctx *ctx, const nfhmm_problem *dev_p,
+                                                nfhmm_precision prec, nfhmm_result *dev_r, void *hip_stream);
+
 /* ------------------------------------------------------------------ serving */
 
 /* Queue one job (host memory; validated and copied before return).  Jobs are

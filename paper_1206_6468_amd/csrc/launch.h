@@ -8,6 +8,17 @@ namespace nfhmm {
 
 enum UpdateMode : int { kUpdMessages = 0, kUpdUniform = 1, kUpdFromAlpha = 2 };
 
+// The work-list table of a single job as one image: its descriptor and, per launch
+// kind, the block range [0, blocks).  launch_put_table writes it to device memory
+// from the kernel's own argument (no host staging buffer) and clears the job's
+// status word.
+constexpr int kOneJobLists = 16;
+struct OneJobTable {
+  JobDesc desc;
+  int start[kOneJobLists][2];
+};
+hipError_t launch_put_table(const OneJobTable &img, void *dst, hipStream_t st);
+
 hipError_t launch_pack(const JobDesc &J, hipStream_t st);
 hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st);
 // small: 64 x 64 block tiles (work lists built with kSpecSmallBM / BN) instead of

@@ -1572,8 +1572,22 @@ __global__ void k_chain_prep(JobDesc J, const float *logev) {
   if (lane == 0) J.sh[t] = mx - kEvHeadroomLog;
 }
 
+// One job's table image -> dst (4-byte words), and the job's status word cleared.
+__global__ void k_put_table(OneJobTable img, int *dst) {
+  constexpr int kWords = (int)(sizeof(OneJobTable) / 4);
+  const int *src = reinterpret_cast<const int *>(&img);
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x) dst[i] = src[i];
+  if (threadIdx.x == 0) *img.desc.status = 0;
+}
+
 // ------------------------------------------------------------------ launchers
 static inline hipError_t last() { return hipGetLastError(); }
+
+hipError_t launch_put_table(const OneJobTable &img, void *dst, hipStream_t st) {
+  static_assert(sizeof(OneJobTable) % 4 == 0, "the image is copied in 4-byte words");
+  k_put_table<<<1, 64, 0, st>>>(img, reinterpret_cast<int *>(dst));
+  return last();
+}
 
 hipError_t launch_pack(const JobDesc &J, hipStream_t st) {
   k_pack_v<<<J.T, 256, 0, st>>>(J);

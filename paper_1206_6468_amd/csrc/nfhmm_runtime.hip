@@ -12,6 +12,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
@@ -32,6 +33,10 @@
 #include "table_ring.h"
 
 using namespace nfhmm;
+
+// Working memory of nfhmm_fit_device_noalloc (see "scratch of the no-alloc fit" below).
+constexpr size_t kNoAllocScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
 
 namespace {
 
@@ -58,6 +63,34 @@ double now_s() {
 }
 
 inline int64_t rup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// ------------------------------------------------------------------ scratch of the no-alloc fit
+// Working memory of nfhmm_fit_device_noalloc: one static device array per GPU,
+// held until the process ends.  In host code `scratch` names a host-side stand-in,
+// not the device array: its device address is taken once per device with
+// hipGetSymbolAddress (in nfhmm_create, with that device current) and only that
+// address is passed to kernels.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// Take the current device's scratch address (device `dev` must be current).
+hipError_t scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = static_cast<char *>(ptr);
+  return hipSuccess;
+}
+
+char *scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
 
 // ------------------------------------------------------------------ dims / layout
 struct Dims {
@@ -464,6 +497,8 @@ struct nfhmm_ctx {
   struct Rec { int kind; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> event_pool;
+  // pinned word for the no-alloc fit's status read-back (allocated at create)
+  int *status_host = nullptr;
 };
 
 namespace {
@@ -1173,7 +1208,9 @@ nfhmm_status nfhmm_create(nfhmm_ctx **out, int device, size_t hbm_budget_bytes, 
   HIP_OK(hipGetDeviceCount(&n));
   if (device < 0 || device >= n) return fail(NFHMM_E_DEVICE, "device %d not present (%d devices)", device, n);
   HIP_OK(hipSetDevice(device));
+  HIP_OK(scratch_setup(device));
   std::unique_ptr<nfhmm_ctx> c(new nfhmm_ctx());
+  HIP_OK(hipHostMalloc((void **)&c->status_host, 256, hipHostMallocDefault));
   c->device = device;
   c->budget = hbm_budget_bytes;
   c->max_slots = max_slots > 0 ? max_slots : 64;
@@ -1220,6 +1257,7 @@ void nfhmm_destroy(nfhmm_ctx *ctx) {
     if (t.dev) (void)hipFree(t.dev);
     if (t.host) (void)hipHostFree(t.host);
   }
+  if (ctx->status_host) (void)hipHostFree(ctx->status_host);
   (void)hipEventDestroy(ctx->ev_fork);
   (void)hipEventDestroy(ctx->ev_join);
   for (auto &ln : ctx->lanes) {
@@ -1336,6 +1374,76 @@ nfhmm_status nfhmm_fit_batch_device(nfhmm_ctx *ctx, int n, const nfhmm_problem *
 nfhmm_status nfhmm_fit_device(nfhmm_ctx *ctx, const nfhmm_problem *dev_p, nfhmm_precision prec,
                               nfhmm_result *dev_r, void *hip_stream) {
   return nfhmm_fit_batch_device(ctx, 1, dev_p, prec, dev_r, hip_stream);
+}
+
+nfhmm_status nfhmm_fit_device_noalloc(nfhmm_ctx *ctx, const nfhmm_problem *dev_p, nfhmm_precision prec,
+                                      nfhmm_result *dev_r, void *hip_stream) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  Job j;
+  nfhmm_status s = make_job(dev_p, prec, dev_r, false, false, j);
+  if (s != NFHMM_OK) return s;
+  // scratch: the table image, then the job's arena
+  const size_t arena_off = (size_t)rup((int64_t)sizeof(OneJobTable), 256);
+  const size_t need = arena_off + j.L.total;
+  if (need > kNoAllocScratchBytes)
+    return fail(NFHMM_E_NOMEM, "the job needs %zu bytes of working memory; nfhmm_fit_device_noalloc has %zu",
+                need, kNoAllocScratchBytes);
+  HIP_OK(hipSetDevice(ctx->device));
+  char *base = scratch_of(ctx->device);
+  if (!base) return fail(NFHMM_E_DEVICE, "no scratch address for device %d", ctx->device);
+  hipStream_t st = hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream;
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
+  j.arena = base + arena_off;
+  j.start_round = 0;
+  fill_desc(j, j.prob.gamma);
+  const JobDesc &D = j.desc;
+  // the work lists of this one job, as the batched engine would build them
+  OneJobTable img;
+  static_assert(kNumLists <= kOneJobLists, "table image too small");
+  std::memset(&img, 0, sizeof img);
+  img.desc = D;
+  const int stride = update_stride(std::max(32, j.d.Mp), std::max(1, j.d.S * j.d.N));
+  const bool small = spec_blocks(D, false) < kSmallBatchBlocks;
+  WorkList wl[kNumLists];
+  for (int k = 0; k < kNumLists; ++k) {
+    img.start[k][0] = 0;
+    img.start[k][1] = blocks_of((ListKind)k, D, j.d.bf16, update_waves(stride), small);
+    wl[k].jobs = reinterpret_cast<const JobDesc *>(base);
+    wl[k].start = reinterpret_cast<const int *>(base + offsetof(OneJobTable, start)) + 2 * k;
+    wl[k].njobs = 1;
+    wl[k].total = img.start[k][1];
+  }
+  const int nmax = std::max(1, j.d.N);
+  HIP_OK(launch_put_table(img, base, st));   // also clears the status word
+  HIP_OK(launch_pack(D, st));
+  if (D.alpha_init) {
+    HIP_OK(launch_update(wl[kUpd], kUpdFromAlpha, 0, stride, st));
+  } else {
+    HIP_OK(launch_fill_w_ones(D, st));
+    HIP_OK(launch_spectrum(wl[kSpecF], false, small, st));
+    HIP_OK(launch_spectrum(wl[kSpecH], true, small, st));
+    HIP_OK(launch_counts(wl[kCntF], false, st));
+    HIP_OK(launch_counts(wl[kCntH], true, st));
+    HIP_OK(launch_update(wl[kUpd], kUpdUniform, 0, stride, st));
+  }
+  // each iteration on the one stream: the chains, then the contractions, then Eq. 6
+  for (int r = 0; r < j.d.iters; ++r) {
+    HIP_OK(launch_chain_fb(wl[kFBR], wl[kFB], nmax, st));
+    HIP_OK(launch_posterior(wl[kPost], wl[kChain], nmax, st));
+    HIP_OK(launch_spectrum(wl[kSpecF], false, small, st));
+    HIP_OK(launch_spectrum(wl[kSpecH], true, small, st));
+    HIP_OK(launch_counts(wl[kCntF], false, st));
+    HIP_OK(launch_counts(wl[kCntH], true, st));
+    HIP_OK(launch_update(wl[kUpd], kUpdMessages, r, stride, st));
+  }
+  HIP_OK(launch_finish(wl[kFrames], wl[kRecon], wl[kIters], st));
+  HIP_OK(hipMemcpyAsync(ctx->status_host, D.status, 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  const int flag = *ctx->status_host;
+  if (flag & kBadV) return fail(NFHMM_E_INVALID, "V has a negative or non-finite entry");
+  if (flag & kBadW) return fail(NFHMM_E_INVALID, "a dictionary element is not normalised");
+  if (flag & kNonFinite) return fail(NFHMM_E_NONFINITE, "the evidence lower bound became non-finite");
+  return NFHMM_OK;
 }
 
 nfhmm_status nfhmm_submit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precision prec, nfhmm_result *r,

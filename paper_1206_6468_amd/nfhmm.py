@@ -37,7 +37,7 @@ _PREC = {"fp32": FP32, "bf16": BF16, FP32: FP32, BF16: BF16}
 SYMBOLS = [
     "nfhmm_create", "nfhmm_destroy", "nfhmm_last_error", "nfhmm_footprint_bytes",
     "nfhmm_validate", "nfhmm_admission_plan", "nfhmm_fit", "nfhmm_fit_batch",
-    "nfhmm_fit_batch_device", "nfhmm_fit_device", "nfhmm_submit", "nfhmm_poll",
+    "nfhmm_fit_batch_device", "nfhmm_fit_device", "nfhmm_fit_device_noalloc", "nfhmm_submit", "nfhmm_poll",
     "nfhmm_wait", "nfhmm_cancel", "nfhmm_chain_posterior", "nfhmm_special_functions",
     "nfhmm_profile_enable", "nfhmm_profile_read", "nfhmm_profile_select", "nfhmm_set_lanes",
     "nfhmm_stft_frames", "nfhmm_stft", "nfhmm_istft", "nfhmm_stft_device", "nfhmm_istft_device",
@@ -83,6 +83,8 @@ _lib.nfhmm_fit_batch_device.argtypes = [C.c_void_p, C.c_int, _P(nfhmm_problem), 
 _lib.nfhmm_fit_batch_device.restype = C.c_int
 _lib.nfhmm_fit_device.argtypes = [C.c_void_p, _P(nfhmm_problem), C.c_int, _P(nfhmm_result), C.c_void_p]
 _lib.nfhmm_fit_device.restype = C.c_int
+_lib.nfhmm_fit_device_noalloc.argtypes = [C.c_void_p, _P(nfhmm_problem), C.c_int, _P(nfhmm_result), C.c_void_p]
+_lib.nfhmm_fit_device_noalloc.restype = C.c_int
 _lib.nfhmm_submit.argtypes = [C.c_void_p, _P(nfhmm_problem), C.c_int, _P(nfhmm_result),
                               _P(C.c_uint64)]
 _lib.nfhmm_submit.restype = C.c_int
@@ -268,6 +270,14 @@ def fit_batch_device(ctx: Context, jobs, precision="fp32", stream=None):
 
 def fit_device(ctx: Context, job, precision="fp32", stream=None):
     fit_batch_device(ctx, [job], precision, stream)
+
+
+def fit_device_noalloc(ctx: Context, job, precision="fp32", stream=None):
+    """nfhmm_fit_device_noalloc on one DeviceJob: the library's fixed working area,
+    nothing allocated."""
+    prob, res = job.structs()
+    h = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(_lib.nfhmm_fit_device_noalloc(ctx.handle, C.byref(prob), _PREC[precision], C.byref(res), h), ctx.handle)
 
 
 class Submitted:
