@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA = 157.3e12     # MI355X dense FP32 matrix, FLOP/s
 PEAK_BF16_MFMA = 2.5e15       # MI355X dense BF16 matrix, FLOP/s
 PEAK_HBM = 8.0e12             # B/s
+PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector, FLOP/s
 
 
 def _traffic_for(kernel, workload, record="hbm_traffic.json"):
@@ -43,6 +44,16 @@ def _traffic_for(kernel, workload, record="hbm_traffic.json"):
     if e.get("workload") != workload:
         return None
     return e.get("bytes_per_launch")
+
+
+def bf16_bytes_per_frame_iteration(S, N, K, F, T):
+    """Algorithmic HBM bytes per frame-iteration of the BF16-contraction form: the
+    least that must cross each iteration's boundary -- V read once (4 F), the
+    carried alpha-hat read and written in float32 (8 M), the chain rows (evidence
+    and marginals, 8 S N) and one bfloat16 copy of the dictionary read once per
+    iteration and shared by the T frames (2 F M / T)."""
+    M = S * N * K
+    return 4.0 * F + 8.0 * M + 8.0 * S * N + 2.0 * F * M / T
 
 
 def make_jobs(cfg, n, iters=None):
@@ -231,6 +242,36 @@ def stft_bench(L, ctx, jobs=32, sources=2, frames=1000, nfft=1024, hop=256, reps
     }
 
 
+def em_bench(L, ctx, iters=20, reps=3):
+    """EM learning of one source's N-HMM (Section 2.1) at the separation's source
+    shapes (N=40 states of K=10 elements, F=513, T=1000), inputs resident on the
+    device, `iters` iterations per call, timed over `reps` calls.  Algorithmic work
+    per frame-iteration: the three (F x K) by (K x N)-per-state products of an
+    iteration -- P = theta beta in the E-step (double), and the theta and beta
+    updates' sums (float) -- 6 N K F flops, against the FP32 vector peak."""
+    import torch
+
+    from gen import make_nhmm_problem
+    p = make_nhmm_problem(1, 0, iters=iters)
+    job = L.DeviceNhmm(p)
+    L.learn_nhmm_device(ctx, job)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        L.learn_nhmm_device(ctx, job)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    N, K, F, T = p["N"], p["K"], p["F"], p["T"]
+    v = T * iters / dt
+    fl = 6.0 * N * K * F
+    tr = job.loglik.cpu().numpy()
+    return {"workload": f"N{N}-K{K}-F{F}-T{T}", "iterations": iters, "ms_per_call": dt * 1e3,
+            "em_iterations_per_s": iters / dt, "frame_iterations_per_s": v,
+            "roofline": {"bound": "alu", "achieved": v * fl / 1e12, "peak": PEAK_FP32_VALU / 1e12,
+                         "unit": "TFLOP/s", "frac": v * fl / PEAK_FP32_VALU, "flops_per_frame_iteration": fl},
+            "loglik_first_last": [float(tr[0]), float(tr[-1])]}
+
+
 def measured_peaks():
     """What library code reaches on this GPU, beside the nominal peaks: a plain
     FP32 GEMM through torch (the vendor BLAS) at 8192^3 and on the shape of one
@@ -378,38 +419,46 @@ def main():
     jobs = [L.DeviceJob(p) for p in probs]
     torch.cuda.synchronize()
 
-    # the timed steps time only the roofline kernel (k_counts) with events, so that
-    # the step time is barely perturbed; the per-kernel breakdown comes from a
-    # second, fully profiled pass of the same steps
-    dt, prof_c = time_batch(L, ctx, jobs, "fp32", args.steps, args.warmup, profile=True, kinds=("counts",))
+    # A fully profiled pass (every launch bracketed by events) gives the per-kernel
+    # breakdown and names the kernel with the largest summed time; the timed steps
+    # then bracket only the two contractions, so that the step time is barely
+    # perturbed, and the contract's roofline is that of the dominant one.
+    dt_all, prof = time_batch(L, ctx, jobs, "fp32", args.steps, args.warmup, profile=True)
+    dom = max(prof, key=lambda k: prof[k][1])
+    dt, prof_c = time_batch(L, ctx, jobs, "fp32", args.steps, 1, profile=True, kinds=("spectrum", "counts"))
     J = len(jobs)
     value = J * T * iters / dt
-    dt_all, prof = time_batch(L, ctx, jobs, "fp32", args.steps, 0, profile=True)
 
-    # roofline of the dominant contraction kernel.  Each launch covers a group of
-    # the jobs; achieved = algorithmic flops of all timed launches / their summed
-    # device time (= flops per launch / average launch duration).
+    # achieved = algorithmic flops per launch (2 F M T per job and iteration, times
+    # the jobs of the launch) / average launch duration over the timed steps
     flops_per_job_iter = {"spectrum": 2.0 * F * M * T, "counts": 2.0 * F * M * T}
-    dom = max(prof, key=lambda k: prof[k][1])
     rows = {}
     for k, (n, ms) in prof.items():
         rows[k] = {"launches": n, "avg_ms": ms / max(n, 1), "total_ms": ms}
         if k in flops_per_job_iter:
             rows[k]["achieved_tflops"] = flops_per_job_iter[k] * J * iters * args.steps / (ms * 1e-3) / 1e12
-    gemm = "counts"
-    n_g, ms_g = prof_c[gemm]
-    flops_launch = flops_per_job_iter[gemm] * J * iters * args.steps / max(n_g, 1)
-    ach = flops_launch / (ms_g / max(n_g, 1) * 1e-3)
     workload = f"S{S}-N{N}-K{K}-F{F}-T{T}-x{J}"   # the paper-typical job, J of them in one batch
-    roofline = {"bound": "mfma", "kernel": f"k_{gemm}", "achieved": ach / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": _traffic_for(f"k_{gemm}", workload),
-                "largest_summed_time": f"k_{dom}", "kernels": rows,
-                "kernels_note": "from a second, fully profiled pass of the same steps "
-                                f"({dt_all * 1e3:.2f} ms per step with every launch timed); the jobs run in two "
-                                "stream lanes of 16, whose launches overlap, so each launch shares the chip",
-                "algorithmic_flops_per_launch": flops_launch}
 
-    extra = {}
+    def gemm_roof(kname):
+        n_g, ms_g = prof_c[kname]
+        fl = flops_per_job_iter[kname] * J * iters * args.steps / max(n_g, 1)
+        ach = fl / (ms_g / max(n_g, 1) * 1e-3)
+        return {"bound": "mfma", "kernel": f"k_{kname}", "achieved": ach / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_MFMA, "traffic": _traffic_for(f"k_{kname}", workload),
+                "algorithmic_flops_per_launch": fl, "avg_launch_ms": ms_g / max(n_g, 1)}
+    gemm = dom if dom in flops_per_job_iter else "spectrum"
+    roofline = dict(gemm_roof(gemm), largest_summed_time=f"k_{dom}", kernels=rows,
+                    kernels_note="from a separate, fully profiled pass of the same steps "
+                                 f"({dt_all * 1e3:.2f} ms per step with every launch timed); the jobs run in two "
+                                 "stream lanes of 16, whose launches overlap, so each launch shares the chip")
+    other = "counts" if gemm == "spectrum" else "spectrum"
+    # the whole loop against the FP32 MFMA peak: both contractions' 4 F M flops per
+    # frame-iteration at the measured frame-iterations/s
+    loop = {"achieved": value * 4.0 * F * M / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
+            "frac": value * 4.0 * F * M / PEAK_FP32_MFMA, "flops_per_frame_iteration": 4.0 * F * M,
+            "note": "frame-iterations/s x the two contractions' flops per frame-iteration (2 F M each)"}
+
+    extra = {"roofline_" + other: gemm_roof(other), "roofline_loop": loop}
     # the same steps on one stream lane: every launch then has the chip to itself,
     # so this is the contraction's own rate (the two-lane schedule above overlaps
     # one lane's launches with the other's)
@@ -425,10 +474,36 @@ def main():
                                       "unit": "TFLOP/s", "frac": a1 / PEAK_FP32_MFMA,
                                       "algorithmic_flops_per_launch": fl1}
     if not args.no_extra:
-        dtb, profb = time_batch(L, ctx, jobs, "bf16", args.steps, 1, profile=True, kinds=("counts",))
-        tb = flops_per_job_iter["counts"] * J * iters * args.steps / (profb["counts"][1] * 1e-3)
-        extra["bf16"] = {"value": J * T * iters / dtb, "ms_per_step": dtb * 1e3,
-                         "k_counts_tflops": tb / 1e12, "k_counts_frac_of_bf16_peak": tb / PEAK_BF16_MFMA}
+        # BF16 contraction operands: HBM-bound by its algorithmic bytes per
+        # frame-iteration (V read, alpha-hat's w / c round trip in bf16 / f32, the
+        # chain rows, the dictionary's bf16 copies once per iteration)
+        dtb_all, profb = time_batch(L, ctx, jobs, "bf16", args.steps, 1, profile=True)
+        dtb, profb_c = time_batch(L, ctx, jobs, "bf16", args.steps, 0, profile=True, kinds=("counts",))
+        vb = J * T * iters / dtb
+        bytes_fi = bf16_bytes_per_frame_iteration(S, N, K, F, T)
+        tb = flops_per_job_iter["counts"] * J * iters * args.steps / (profb_c["counts"][1] * 1e-3)
+        extra["bf16"] = {"value": vb, "ms_per_step": dtb * 1e3,
+                         "roofline_loop": {"bound": "hbm", "achieved": vb * bytes_fi / 1e9, "peak": PEAK_HBM / 1e9,
+                                           "unit": "GB/s", "frac": vb * bytes_fi / PEAK_HBM,
+                                           "algorithmic_bytes_per_frame_iteration": bytes_fi},
+                         "k_counts_tflops": tb / 1e12, "k_counts_frac_of_bf16_peak": tb / PEAK_BF16_MFMA,
+                         "kernels_ms_per_launch": {k: v[1] / max(v[0], 1) for k, v in profb.items()},
+                         "dominant": max(profb, key=lambda k: profb[k][1])}
+        # three sources (S=3, N=40, K=10, F=513, T=1000): the cost is linear in S
+        log("three-source jobs")
+        p3s = make_jobs(2, J)
+        j3s = [L.DeviceJob(p) for p in p3s]
+        del p3s
+        dts3, prof3 = time_batch(L, ctx, j3s, "fp32", max(2, args.steps // 2), 1, profile=True,
+                                 kinds=("spectrum", "counts"))
+        M3 = 3 * N * K
+        v3 = J * T * iters / dts3
+        extra["three_sources_fp32"] = {
+            "workload": f"S3-N{N}-K{K}-F{F}-T{T}-x{J}", "value": v3, "ms_per_step": dts3 * 1e3,
+            "roofline_loop": {"achieved": v3 * 4.0 * F * M3 / 1e12, "peak": PEAK_FP32_MFMA / 1e12,
+                              "unit": "TFLOP/s", "frac": v3 * 4.0 * F * M3 / PEAK_FP32_MFMA},
+            "time_ratio_vs_two_sources": dts3 / dt, "work_ratio_vs_two_sources": 1.5}
+        del j3s
         dt1, _ = time_batch(L, ctx, jobs[:1], "fp32", max(2, args.steps), 1)
         extra["single_job_fp32"] = {"value": T * iters / dt1, "ms_per_fit": dt1 * 1e3}
         # batch sizes around the headline one (same per-job workload)
@@ -473,6 +548,8 @@ def main():
                                          "note": "nfhmm_fit_batch on host arrays (V, W in; alpha, posteriors, "
                                                  "separated spectrograms, bounds out), best of 2"}
         del hp
+        log("EM learning of one source's N-HMM")
+        extra["nhmm_em"] = em_bench(L, ctx)
         log("time-frequency front and back end")
         extra["stft"] = stft_bench(L, ctx)
         log("library GEMM and copy on this GPU")

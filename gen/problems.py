@@ -159,3 +159,26 @@ def make_tiny(S=2, N=3, K=2, F=7, T=9, seed=0, *, trans="dense", diag=0.7,
     out.update(cfg=-1, job=int(seed), S=S, N=N, K=K, F=F, T=T, M=S * N * K,
                iters=int(iters), gamma=1.0)
     return out
+
+
+def make_nhmm_problem(cfg_id: int, job_id: int = 0, **over) -> dict:
+    """Learning one source's N-HMM (Section 2.1): the spectrogram of that source
+    alone, drawn from the generative process with the source-model shapes of a
+    named workload (one source), and a start for the parameters -- dictionaries
+    drawn afresh from Dirichlet(1), uniform per-frame weights, transitions with 1/2
+    on the diagonal and the rest uniform, uniform initial states.  ``over``
+    overrides dims or sets ``iters``."""
+    cfg = dict(CONFIGS[int(cfg_id)])
+    cfg.update(S=1, T=cfg["T"] or 1000)
+    cfg.update(over)
+    rng = np.random.default_rng(np.random.SeedSequence([SEED_BASE, 77, int(cfg_id), int(job_id)]))
+    N, K, F, T = (int(cfg[k]) for k in ("N", "K", "F", "T"))
+    src = _sample(rng, 1, N, K, F, T, dict_conc=cfg["dict_conc"], trans=cfg["trans"], diag=cfg["diag"],
+                  weights=cfg["weights"], loud=cfg["loud"], quanta=cfg["quanta"])
+    W0 = _normalise_f32(rng.gamma(1.0, size=(N, K, F)) + 1e-3, axis=-1)
+    theta0 = np.full((T, N, K), 1.0 / K, dtype=np.float32)
+    A0 = np.full((N, N), 0.5 / max(N - 1, 1))
+    A0[np.arange(N), np.arange(N)] = 0.5 if N > 1 else 1.0
+    return dict(V=src["V"], W=W0, theta=theta0, A=_normalise_f32(A0, axis=-1),
+                pi=np.full(N, 1.0 / N, dtype=np.float32), N=N, K=K, F=F, T=T,
+                iters=int(cfg.get("iters", 20)), W_true=src["W"][0], A_true=src["A"][0], states=src["states"][0])

@@ -191,6 +191,55 @@ NFHMM_API nfhmm_status nfhmm_fit_device(nfhmm_ctx *ctx, const nfhmm_problem *dev
 NFHMM_API nfhmm_status nfhmm_fit_device_noalloc(nfhmm_ctx *ctx, const nfhmm_problem *dev_p,
                                                 nfhmm_precision prec, nfhmm_result *dev_r, void *hip_stream);
 
+/* ------------------------------------------------------------------ learning a source model */
+
+/* EM learning of one source's N-HMM (Section 2.1): the source model the separation
+ * takes as input, learned from a spectrogram of that source alone (Section 5 learns
+ * one per speaker).  States D_t follow a Markov chain (A, pi); each of the quanta
+ * of frame t draws an element z from theta_t(D_t) and a frequency from
+ * beta(D_t, z).  Section 2.1 states that EM finds the maximum-likelihood
+ * dictionaries and transitions, with theta_t as per-frame nuisance parameters, and
+ * gives no steps; one iteration here is, from the parameters it starts with:
+ *   E-step  P_t(f | d) = sum_z theta_t(d, z) beta(d, z, f); the frame log-likelihood
+ *           sum_f V_tf ln P_t(f | d) (the multinomial constant dropped; in double);
+ *           the chain's marginals gamma_t(d) and pairwise marginals xi_t(i, j)
+ *   M-step  beta'(d, z, f) ~ beta(d, z, f) sum_t gamma_t(d) theta_t(d, z) V_tf / P_t(f | d)
+ *           (normalised over f); theta'_t(d, z) ~ theta_t(d, z) sum_f beta(d, z, f)
+ *           V_tf / P_t(f | d) (over z); A' ~ sum_t xi_t (rows); pi' = gamma_0.
+ *           A row that receives no expected counts keeps its previous values.
+ * Layouts as the separation's: V [T][F]; W [N][K][F] (each row of F values sums to
+ * 1); theta [T][N][K] (each row of K values sums to 1); A [N][N] row-stochastic,
+ * A[i][j] = P(D_t = j | D_{t-1} = i); pi [N].  Limits: 1 <= N <= 64, 1 <= K <= 32,
+ * iters >= 1.  The log-likelihood ln P(V) is non-decreasing over the iterations. */
+typedef struct {
+  int32_t N, K;
+  int64_t F, T;
+  const float *V;       /* [T][F]    counts >= 0, finite                                      */
+  const float *W;       /* [N][K][F] starting dictionaries, rows >= 0 summing to 1 within 1e-4 */
+  const float *theta;   /* [T][N][K] starting weights, entries > 0, rows summing to 1 within 1e-4 */
+  const float *A;       /* [N][N]    starting transitions, rows summing to 1 within 1e-4      */
+  const float *pi;      /* [N]       starting initial-state probabilities                     */
+  int32_t iters;
+} nfhmm_nhmm_problem;
+
+typedef struct {
+  float *W, *theta, *A, *pi;   /* the learned parameters (same layouts); any may be NULL     */
+  double *loglik;              /* [iters] ln P(V) of the parameters each iteration started
+                                  from (multinomial constant dropped), or NULL              */
+} nfhmm_nhmm_result;
+
+/* Blocking EM on host arrays.  The inputs are checked as the layouts above state,
+ * plus: every state's dictionary is non-zero in every bin where V > 0 (else that
+ * state's likelihood is 0 at that frame and the update is undefined) ->
+ * NFHMM_E_INVALID.  Inputs are copied; outputs are written on return. */
+NFHMM_API nfhmm_status nfhmm_learn_nhmm(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_result *r);
+
+/* The same on device pointers (inputs and outputs; the structs in host memory),
+ * ordered on hip_stream (NULL: the context's stream).  Only the sizes are checked.
+ * Blocks until the work is done. */
+NFHMM_API nfhmm_status nfhmm_learn_nhmm_device(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *dev_p,
+                                               nfhmm_nhmm_result *dev_r, void *hip_stream);
+
 /* ------------------------------------------------------------------ serving */
 
 /* Queue one job (host memory; validated and copied before return).  Jobs are

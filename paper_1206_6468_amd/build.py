@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnfhmm.so")
-SOURCES = ["nfhmm_kernels.hip", "stft_kernels.hip", "nfhmm_runtime.hip"]
+SOURCES = ["nfhmm_kernels.hip", "stft_kernels.hip", "nhmm_em_kernels.hip", "nfhmm_runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",

@@ -20,6 +20,7 @@
 #include "jobdesc.h"
 #include "launch.h"
 #include "special.h"
+#include "wave.h"
 
 namespace nfhmm {
 
@@ -47,76 +48,6 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
 // float -> bfloat16, round to nearest even (the gfx950 conversion instruction)
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// Wavefront reductions with DPP lane moves: within quads, half-rows and rows of
-// 16, then across rows with the row broadcasts; the total lands in lane 63 and
-// is read back to every lane.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ float dpp_mov(float old, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWS, 0xf, false));
-}
-__device__ __forceinline__ float lane63(float v) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
-// Global-memory pointers (address space 1), so that loads and stores are
-// global_* instructions, which count only against vmcnt.  A kernel copies the
-// descriptor fields it needs into such locals before its first store: loaded
-// then, they are scalar loads kept in SGPRs; read after a store, the compiler
-// must reload them per lane (the store might have changed the descriptor).
-typedef float vf2 __attribute__((ext_vector_type(2)));
-typedef float vf4 __attribute__((ext_vector_type(4)));
-typedef unsigned int vu2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(1))) float gfloat;
-typedef __attribute__((address_space(1))) vf2 gfloat2;
-typedef __attribute__((address_space(1))) vf4 gfloat4;
-typedef __attribute__((address_space(1))) vu2 guint2;
-typedef __attribute__((address_space(1))) uint16_t gu16;
-__device__ __forceinline__ gfloat *gptr(float *p) { return (gfloat *)p; }
-__device__ __forceinline__ const gfloat *gptr(const float *p) { return (const gfloat *)p; }
-__device__ __forceinline__ gfloat2 *gptr(float2 *p) { return (gfloat2 *)p; }
-__device__ __forceinline__ const gfloat2 *gptr(const float2 *p) { return (const gfloat2 *)p; }
-__device__ __forceinline__ gu16 *gptr(uint16_t *p) { return (gu16 *)p; }
-__device__ __forceinline__ const gu16 *gptr(const uint16_t *p) { return (const gu16 *)p; }
-
-__device__ __forceinline__ float wave_sum(float x) {
-  x += dpp_mov<0xb1, 0xf>(0.0f, x);      // quad_perm [1,0,3,2]
-  x += dpp_mov<0x4e, 0xf>(0.0f, x);      // quad_perm [2,3,0,1]
-  x += dpp_mov<0x141, 0xf>(0.0f, x);     // row_half_mirror
-  x += dpp_mov<0x140, 0xf>(0.0f, x);     // row_mirror
-  x += dpp_mov<0x142, 0xa>(0.0f, x);     // row_bcast:15 into rows 1, 3
-  x += dpp_mov<0x143, 0xc>(0.0f, x);     // row_bcast:31 into rows 2, 3
-  return lane63(x);
-}
-__device__ __forceinline__ float wave_max(float x) {
-  const float ninf = -INFINITY;
-  x = fmaxf(x, dpp_mov<0xb1, 0xf>(ninf, x));
-  x = fmaxf(x, dpp_mov<0x4e, 0xf>(ninf, x));
-  x = fmaxf(x, dpp_mov<0x141, 0xf>(ninf, x));
-  x = fmaxf(x, dpp_mov<0x140, 0xf>(ninf, x));
-  x = fmaxf(x, dpp_mov<0x142, 0xa>(ninf, x));
-  x = fmaxf(x, dpp_mov<0x143, 0xc>(ninf, x));
-  return lane63(x);
-}
-__device__ __forceinline__ Comp comp_dpp_step(Comp c, Comp d) { return comp_merge(c, d); }
-template <int CTRL, int ROWS>
-__device__ __forceinline__ Comp comp_mov(Comp c) {
-  Comp d;
-  d.hi = dpp_mov<CTRL, ROWS>(0.0f, c.hi);
-  d.lo = dpp_mov<CTRL, ROWS>(0.0f, c.lo);
-  return d;
-}
-__device__ __forceinline__ Comp wave_comp(Comp c) {
-  c = comp_merge(c, comp_mov<0xb1, 0xf>(c));
-  c = comp_merge(c, comp_mov<0x4e, 0xf>(c));
-  c = comp_merge(c, comp_mov<0x141, 0xf>(c));
-  c = comp_merge(c, comp_mov<0x140, 0xf>(c));
-  c = comp_merge(c, comp_mov<0x142, 0xa>(c));
-  c = comp_merge(c, comp_mov<0x143, 0xc>(c));
-  Comp r;
-  r.hi = lane63(c.hi);
-  r.lo = lane63(c.lo);
-  return r;
-}
 
 // ------------------------------------------------------------------ packing
 // V_in [T][F] -> V [T][Fp]; checks V finite and >= 0.
@@ -1310,7 +1241,10 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
 
   // ---- Eq. 6; element k belongs to state g = k / K (kept incrementally).  Loads
   //      past the end read the last element (in bounds) and are not used.
-  Comp asum = comp_zero();
+  // alpha_0 and the bound's sum of lnG(alpha_k): per-lane sums in double (exact for
+  // these few terms), then a butterfly over the lanes, which leaves the same value
+  // in every lane.  Sub-chunks of 64 elements past Mp are skipped (a uniform test).
+  double asum = 0.0;
   {
     const int step_g = 64 / K, step_r = 64 % K;
     int g = lane / K, r = lane - (lane / K) * K;
@@ -1319,25 +1253,28 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
       float cv[kUpdU];
 #pragma unroll
       for (int u = 0; u < kUpdU; ++u) {
+        if (base + 64 * u >= Mp) break;
         const int k = min(base + 64 * u + lane, M - 1);
         cv[u] = from_alpha ? alpha_init[(size_t)t * M + k] : c[row + k];
       }
 #pragma unroll
       for (int u = 0; u < kUpdU; ++u) {
+        if (base + 64 * u >= Mp) break;
         const int k = base + 64 * u + lane;
         float a = from_alpha ? cv[u] : cv[u] + gamma * sD[min(g, S * N - 1)] + 1.0f;
         a = k < M ? a : 0.0f;
-        comp_add(asum, a);
+        asum += (double)a;
         if (store_alpha && k < M) alpha[row + k] = a;
-        if (k < Mp) sE[k] = a;
+        if (k < Mp) sE[k] = a;   // Mp is a multiple of 32: the last sub-chunk may be half full
         g += step_g;
         r += step_r;
         if (r >= K) { r -= K; ++g; }
       }
     }
   }
-  asum = wave_comp(asum);
-  const float a0 = asum.hi + asum.lo;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o);
+  const float a0 = (float)asum;
   const Shift8 z0 = shift8(a0);
   const float rest0 = psi_rest(z0);
   const float inv_xs0 = 1.0f / z0.xs;
@@ -1346,7 +1283,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
   // ---- w = exp(psi(alpha) - psi(alpha_0)) = (xs / xs0) exp(rest - rest0);
   //      sE keeps psi(alpha_k) for Eq. 8; sum_k lnG(alpha_k) for the bound;
   //      tail bins: Lambda[l][t] = sum_k beta[l][k] w_k for the next contraction
-  Comp lg = comp_zero();
+  double lg = 0.0;
   float tacc[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int base = 0; base < Mp; base += 64 * kUpdU) {
     float tw[kMaxTail][kUpdU];
@@ -1355,6 +1292,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
       if (jt < Ft) {
 #pragma unroll
         for (int u = 0; u < kUpdU; ++u) {
+          if (base + 64 * u >= Mp) break;
           const size_t o = (size_t)(Fm + jt) * Mp + min(base + 64 * u + lane, M - 1);
           tw[jt][u] = kBF16 ? bf2f(Wfm_h[o]) : Wfm[o];
         }
@@ -1362,6 +1300,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
     }
 #pragma unroll
     for (int u = 0; u < kUpdU; ++u) {
+      if (base + 64 * u >= Mp) break;
       const int k = base + 64 * u + lane;
       const bool in = k < M;
       const Shift8 z = shift8(in ? sE[k] : 1.0f);
@@ -1369,7 +1308,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
       const float lxs = fast_ln(z.xs);
       const float ps = lxs + rest;
       float w = in ? (z.xs * inv_xs0) * fast_exp(rest - rest0) : 0.0f;
-      if (msg && in) comp_add(lg, lgamma_from(z, lxs));
+      if (msg && in) lg += (double)lgamma_from(z, lxs);
       if (k < Mp) {
         sE[k] = in ? ps : 0.0f;
         if constexpr (kBF16) {
@@ -1423,7 +1362,11 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
   //   sum_k lnG(alpha_k) - lnG(alpha_0) + sum V ln Lambda - sum c ln w
   //   + sum_s (ln Z_s part - sum_n d (gamma phi))
   if (msg) {
-    Comp tot = wave_comp(lg);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o);
+    Comp tot;
+    tot.hi = (float)lg;
+    tot.lo = (float)(lg - (double)tot.hi);
     tot = comp_merge(tot, wave_comp(pv));
     comp_add(tot, -lgamma_from(z0, fast_ln(z0.xs)));
     tot = comp_merge(tot, chain);

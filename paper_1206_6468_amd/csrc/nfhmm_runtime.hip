@@ -30,6 +30,7 @@
 #include "host_copy.h"
 #include "jobdesc.h"
 #include "launch.h"
+#include "nhmm_em.h"
 #include "table_ring.h"
 
 using namespace nfhmm;
@@ -1658,6 +1659,172 @@ nfhmm_status nfhmm_istft(nfhmm_ctx *ctx, int32_t nfft, int32_t hop, int32_t B, i
   HIP_OK(e);
   HIP_OK(es);
   return NFHMM_OK;
+}
+
+// ------------------------------------------------------------------ EM learning of a source model
+}  // extern "C"
+
+namespace {
+
+nfhmm_status em_check(const nfhmm_nhmm_problem *p, const nfhmm_nhmm_result *r, bool values, std::string *msg) {
+  auto bad = [&](const char *m) { *msg = m; return NFHMM_E_INVALID; };
+  if (!p || !r) return bad("problem or result is NULL");
+  if (p->N < 1 || p->N > NFHMM_MAX_STATES) return bad("N out of range [1, 64]");
+  if (p->K < 1 || p->K > kEmMaxK) return bad("K out of range [1, 32]");
+  if (p->F < 1 || p->F > (1 << 20) || p->T < 1 || p->T > (1 << 22)) return bad("F or T out of range");
+  if (p->iters < 1 || p->iters > (1 << 20)) return bad("iters out of range [1, 2^20]");
+  if ((int64_t)p->T * p->N * std::max<int64_t>(p->K, 64) >= (int64_t)1 << 31 ||
+      (int64_t)p->N * p->K * p->F * ((p->T + kEmChunk - 1) / kEmChunk) >= (int64_t)1 << 31)
+    return bad("T * N * K or the M-step's partial sums too large");
+  if (!p->V || !p->W || !p->theta || !p->A || !p->pi) return bad("V, W, theta, A and pi are required");
+  if (!values) return NFHMM_OK;
+  const int64_t N = p->N, K = p->K, F = p->F, T = p->T;
+  char buf[256];
+  if (!all_finite_nonneg(p->V, T * F)) return bad("V has a negative or non-finite entry");
+  std::vector<unsigned char> counted(F, 0);
+  for (int64_t i = 0; i < T * F; ++i) counted[i % F] |= (unsigned char)(p->V[i] > 0.0f);
+  for (int64_t d = 0; d < N; ++d) {
+    std::vector<unsigned char> cover(F, 0);
+    for (int64_t z = 0; z < K; ++z) {
+      const float *row = p->W + (d * K + z) * F;
+      double sum = 0.0;
+      for (int64_t f = 0; f < F; ++f) {
+        if (bad_value(row[f])) return bad("W has a negative or non-finite entry");
+        sum += row[f];
+        cover[f] |= (unsigned char)(row[f] > 0.0f);
+      }
+      if (std::fabs(sum - 1.0) > 1e-4) {
+        snprintf(buf, sizeof buf, "dictionary row (%lld, %lld) sums to %.7g, not 1", (long long)d, (long long)z, sum);
+        *msg = buf;
+        return NFHMM_E_INVALID;
+      }
+    }
+    for (int64_t f = 0; f < F; ++f)
+      if (counted[f] && !cover[f]) {
+        snprintf(buf, sizeof buf, "state %lld's dictionary is 0 in bin %lld, which has counts", (long long)d,
+                 (long long)f);
+        *msg = buf;
+        return NFHMM_E_INVALID;
+      }
+  }
+  for (int64_t i = 0; i < T * N; ++i) {
+    double sum = 0.0;
+    for (int64_t z = 0; z < K; ++z) {
+      const float x = p->theta[i * K + z];
+      if (!(x > 0.0f) || !std::isfinite(x)) return bad("theta has an entry that is not finite and > 0");
+      sum += x;
+    }
+    if (std::fabs(sum - 1.0) > 1e-4) return bad("a row of theta does not sum to 1");
+  }
+  double ps = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    if (bad_value(p->pi[i])) return bad("pi has a negative or non-finite entry");
+    ps += p->pi[i];
+    double rs = 0.0;
+    for (int64_t j = 0; j < N; ++j) {
+      if (bad_value(p->A[i * N + j])) return bad("A has a negative or non-finite entry");
+      rs += p->A[i * N + j];
+    }
+    if (std::fabs(rs - 1.0) > 1e-4) return bad("a row of A does not sum to 1");
+  }
+  if (std::fabs(ps - 1.0) > 1e-4) return bad("pi does not sum to 1");
+  return NFHMM_OK;
+}
+
+// One EM run: host or device arrays in and out, the work on st.
+nfhmm_status em_run(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_result *r, bool host, hipStream_t st) {
+  const size_t N = p->N, K = p->K, F = p->F, T = p->T, it = p->iters;
+  const size_t nchunk = (T + kEmChunk - 1) / kEmChunk;
+  size_t off = 0;
+  auto take = [&](size_t b) { size_t o = off; off += (b + 255) / 256 * 256; return o; };
+  // the caller's float32 arrays (host: copies in the arena), then the working ones
+  const size_t o_V = host ? take(T * F * 4) : ~size_t(0);
+  const size_t o_W32 = take(N * K * F * 4), o_th32 = take(T * N * K * 4), o_A32 = take(N * N * 4),
+               o_pi32 = take(N * 4);
+  size_t o_b[2], o_th[2], o_lA[2], o_lpi[2];
+  for (int i = 0; i < 2; ++i) {
+    o_b[i] = take(N * K * F * 8);
+    o_th[i] = take(T * N * K * 8);
+    o_lA[i] = take(N * N * 4);
+    o_lpi[i] = take(N * 4);
+  }
+  const size_t o_ll = take(T * N * 8), o_off = take(T * 8), o_x = take(T * 64 * 4), o_la = take(T * 64 * 4);
+  const size_t o_lgam = take(T * N * 4), o_gmax = take(N * 4);
+  const size_t o_bpart = take(nchunk * N * K * F * 8), o_trace = take(it * 8);
+  Job j;   // only its arena is used: allocated and cached like a fit's
+  j.L.total = off;
+  nfhmm_status s = arena_alloc(ctx, j, true);
+  if (s != NFHMM_OK) return s;
+  char *a = j.arena;
+  auto F32 = [&](size_t o) { return reinterpret_cast<float *>(a + o); };
+  auto F64 = [&](size_t o) { return reinterpret_cast<double *>(a + o); };
+  const hipMemcpyKind in = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  hipError_t e = hipSuccess;
+  auto cp = [&](void *dst, const void *src, size_t b, hipMemcpyKind k) {
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, src, b, k, st);
+  };
+  const float *V = host ? F32(o_V) : p->V;
+  if (host) cp(F32(o_V), p->V, T * F * 4, in);
+  cp(F32(o_W32), p->W, N * K * F * 4, in);
+  cp(F32(o_th32), p->theta, T * N * K * 4, in);
+  cp(F32(o_A32), p->A, N * N * 4, in);
+  cp(F32(o_pi32), p->pi, N * 4, in);
+  if (e == hipSuccess)
+    e = launch_em_import((int)N, (int)K, (int)F, (int)T, F32(o_W32), F32(o_th32), F32(o_A32), F32(o_pi32), F64(o_b[0]),
+                         F64(o_th[0]), F32(o_lA[0]), F32(o_lpi[0]), st);
+  for (size_t i = 0; i < it && e == hipSuccess; ++i) {
+    const int c = (int)(i & 1), n = c ^ 1;
+    EmDesc E{};
+    E.N = (int)N; E.K = (int)K; E.F = (int)F; E.T = (int)T; E.nchunk = (int)nchunk;
+    E.V = V;
+    E.beta = F64(o_b[c]); E.theta = F64(o_th[c]); E.lnA = F32(o_lA[c]); E.lnpi = F32(o_lpi[c]);
+    E.beta_new = F64(o_b[n]); E.theta_new = F64(o_th[n]); E.lnA_new = F32(o_lA[n]); E.lnpi_new = F32(o_lpi[n]);
+    E.ll = F64(o_ll); E.off = F64(o_off); E.x = F32(o_x); E.la = F32(o_la);
+    E.lgam = F32(o_lgam); E.gmax = F32(o_gmax);
+    E.bpart = F64(o_bpart); E.trace = F64(o_trace);
+    e = launch_em_frames(E, st);
+    if (e == hipSuccess) e = launch_em_chain(E, (int)i, st);
+    if (e == hipSuccess) e = launch_em_beta(E, st);
+  }
+  // the learned parameters, as float32, into the staging arrays, then out
+  const int fin = (int)(it & 1);
+  if (e == hipSuccess)
+    e = launch_em_export((int)N, (int)K, (int)F, (int)T, F64(o_b[fin]), F64(o_th[fin]), F32(o_lA[fin]),
+                         F32(o_lpi[fin]), F32(o_W32), F32(o_th32), F32(o_A32), F32(o_pi32), st);
+  const hipMemcpyKind out = host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+  if (r->W) cp(r->W, F32(o_W32), N * K * F * 4, out);
+  if (r->theta) cp(r->theta, F32(o_th32), T * N * K * 4, out);
+  if (r->A) cp(r->A, F32(o_A32), N * N * 4, out);
+  if (r->pi) cp(r->pi, F32(o_pi32), N * 4, out);
+  if (r->loglik) cp(r->loglik, a + o_trace, it * 8, out);
+  const hipError_t es = hipStreamSynchronize(st);
+  arena_release(ctx, j, true);
+  HIP_OK(e);
+  HIP_OK(es);
+  return NFHMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nfhmm_status nfhmm_learn_nhmm(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_result *r) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  std::string m;
+  if (em_check(p, r, true, &m) != NFHMM_OK) return fail(NFHMM_E_INVALID, "%s", m.c_str());
+  HIP_OK(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
+  return em_run(ctx, p, r, true, ctx->stream);
+}
+
+nfhmm_status nfhmm_learn_nhmm_device(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *dev_p, nfhmm_nhmm_result *dev_r,
+                                     void *hip_stream) {
+  if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  std::string m;
+  if (em_check(dev_p, dev_r, false, &m) != NFHMM_OK) return fail(NFHMM_E_INVALID, "%s", m.c_str());
+  HIP_OK(hipSetDevice(ctx->device));
+  std::lock_guard<std::mutex> eng(ctx->engine_mu);
+  return em_run(ctx, dev_p, dev_r, false, hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream);
 }
 
 nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float *logev, const float *A,

@@ -1,0 +1,381 @@
+// HIP kernels of EM learning of one source's N-HMM (Section 2.1 of the paper:
+// states D_t follow a Markov chain; each quantum of frame t draws an element Z
+// from theta_t(D_t) and a frequency from beta(D_t, Z)).  The paper states that EM
+// finds the maximum-likelihood dictionaries and transitions, with the per-frame
+// weights as nuisance parameters; the steps below are derived from that model.
+//
+// One iteration, from parameters (beta, theta, A, pi):
+//   k_em_frame   per (frame t, state d): P_t(f | d) = sum_z theta_t(d, z) beta(d, z, f),
+//                the frame log-likelihood ll[t][d] = sum_f V_tf ln P_t(f | d) (the
+//                multinomial constant dropped), and the theta update
+//                theta'_t(d, z) ~ theta_t(d, z) sum_f beta(d, z, f) V_tf / P_t(f | d),
+//                which needs no chain posterior (gamma_t(d) is a common factor)
+//   k_em_prep    the chain's log evidence ll - max_d ll per frame
+//   k_em_chain   the forward-backward in log space: ln gamma_t(d), ln P(V), and the
+//                pairwise marginals xi_t(i, j) summed over t in log space, which give
+//                A' ~ sum_t xi_t (rows normalised) and pi' = gamma_0
+//   k_em_beta    partial sums over frame chunks of
+//                sum_t gamma_t(d) theta_t(d, z) V_tf / P_t(f | d)
+//   k_em_beta_reduce  beta'(d, z, f) ~ beta(d, z, f) times that sum, normalised over f
+// A row that receives no expected counts keeps its previous values.  Every sum runs
+// in a fixed order, so a result does not depend on scheduling.  beta and theta are
+// double between iterations, A and pi float32 logarithms (nhmm_em.h says why).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "launch.h"
+#include "nhmm_em.h"
+#include "special.h"
+#include "wave.h"
+
+namespace nfhmm {
+
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;   // the butterfly leaves the same value in every lane
+}
+
+// One block of 256 threads per (frame t, state d); KR >= K elements in registers.
+template <int KR>
+__global__ __launch_bounds__(256) void k_em_frame(EmDesc E) {
+  const int b = blockIdx.x;
+  const int t = b / E.N, d = b - (b / E.N) * E.N;
+  const int K = E.K, F = E.F, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double th[KR];
+  __shared__ double red[4][KR];
+  __shared__ double redl[4];
+  const size_t row = ((size_t)t * E.N + d) * K;
+  if (tid < K) th[tid] = E.theta[row + tid];
+  __syncthreads();
+  const double *bd = E.beta + (size_t)d * K * F;
+  const float *v = E.V + (size_t)t * F;
+  double nt[KR];
+#pragma unroll
+  for (int z = 0; z < KR; ++z) nt[z] = 0.0;
+  double ll = 0.0;
+  for (int f = tid; f < F; f += 256) {
+    const float vv = v[f];
+    if (!(vv > 0.0f)) continue;   // V = 0: no term in ll, no counts to share
+    double bz[KR];
+    double P = 0.0;
+#pragma unroll
+    for (int z = 0; z < KR; ++z) {
+      bz[z] = z < K ? bd[(size_t)z * F + f] : 0.0;
+      P = fma(z < K ? th[z] : 0.0, bz[z], P);
+    }
+    ll += (double)vv * log(P);
+    const double R = (double)vv / P;
+#pragma unroll
+    for (int z = 0; z < KR; ++z) nt[z] = fma(bz[z], R, nt[z]);
+  }
+  ll = wave_sum_d(ll);
+  if (lane == 0) redl[wave] = ll;
+#pragma unroll
+  for (int z = 0; z < KR; ++z) {
+    if (z < K) {
+      const double s = wave_sum_d(nt[z]);
+      if (lane == 0) red[wave][z] = s;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    E.ll[(size_t)t * E.N + d] = ((redl[0] + redl[1]) + redl[2]) + redl[3];
+    double tot = 0.0;
+    for (int z = 0; z < K; ++z) {
+      const double s = th[z] * (((red[0][z] + red[1][z]) + red[2][z]) + red[3][z]);
+      red[0][z] = s;
+      tot += s;
+    }
+    for (int z = 0; z < K; ++z) E.theta_new[row + z] = tot > 0.0 ? red[0][z] / tot : th[z];
+  }
+}
+
+// The chain's log evidence of frame t (one wavefront, lane = state): the frame's
+// log-likelihoods relative to their largest, which off[t] keeps (in double) for
+// ln P(V).
+__global__ __launch_bounds__(64) void k_em_prep(EmDesc E) {
+  const int t = blockIdx.x, lane = threadIdx.x;
+  const bool live = lane < E.N;
+  const double x = live ? E.ll[(size_t)t * E.N + lane] : -INFINITY;
+  double m = x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  const bool fin = m > -INFINITY;
+  E.x[(size_t)t * 64 + lane] = (live && fin) ? (float)(x - m) : -INFINITY;
+  if (lane == 0) E.off[t] = m;
+}
+
+// log-sum-exp over the live lanes of a wavefront (-inf if all are -inf)
+__device__ __forceinline__ float lse_lanes(float x, bool live) {
+  const float mx = wave_max(live ? x : -INFINITY);
+  if (!(mx > -INFINITY)) return mx;
+  return mx + __logf(wave_sum(live ? __expf(x - mx) : 0.0f));
+}
+
+// The forward-backward of the source chain in log space, one wavefront, lane r =
+// state r, messages normalised per frame (no value is flushed: the smallest
+// probabilities the iterations need are far below the float32 range).
+//   forward   la_t(n) = x_t(n) + lse_m(la_{t-1}(m) + ln A(m, n)), la_0 = ln pi + x_0;
+//             ln Z = the sum of the frames' normalisers
+//   backward  lb_{t-1}(i) = lse_j(ln A(i, j) + x_t(j) + lb_t(j)), lb_{T-1} = 0;
+//             gamma_{t-1}(i) from la + lb, and with q_t(i, j) = the transition
+//             posterior given D_{t-1} = i, ln xi_t(i, j) = ln gamma_{t-1}(i) + ln q_t(i, j),
+//             summed over t per (i, j) as a running maximum and a scaled sum.
+// Lane r holds column r of ln A for the forward and row r for the backward (row r
+// of the new ln A is its own accumulators).
+template <int NR>
+__global__ __launch_bounds__(64) void k_em_chain(EmDesc E, int it) {
+  const int r = threadIdx.x, N = E.N, T = E.T;
+  const bool live = r < N;
+  __shared__ float buf[64];
+  float la;
+  double z = 0.0;
+  {
+    float col[NR];
+#pragma unroll
+    for (int m = 0; m < NR; ++m) col[m] = (live && m < N) ? E.lnA[(size_t)m * N + r] : -INFINITY;
+    const float l0 = live ? E.lnpi[r] + E.x[r] : -INFINITY;
+    float c = lse_lanes(l0, live);
+    la = (live && c > -INFINITY) ? l0 - c : -INFINITY;
+    E.la[r] = la;
+    z += (double)c;
+    for (int t = 1; t < T; ++t) {
+      buf[r] = la;
+      __syncthreads();
+      float mx = -INFINITY;
+#pragma unroll
+      for (int m = 0; m < NR; ++m) mx = fmaxf(mx, buf[m] + col[m]);
+      float s = 0.0f;
+      if (mx > -INFINITY) {
+#pragma unroll
+        for (int m = 0; m < NR; ++m) s += __expf(buf[m] + col[m] - mx);
+      }
+      __syncthreads();
+      const float l = (live && mx > -INFINITY) ? E.x[(size_t)t * 64 + r] + mx + __logf(s) : -INFINITY;
+      c = lse_lanes(l, live);
+      la = (live && c > -INFINITY) ? l - c : -INFINITY;
+      E.la[(size_t)t * 64 + r] = la;
+      z += (double)c;
+    }
+  }
+  // ln P(V) = sum_t off_t + ln Z of the relative evidence
+  double off = 0.0;
+  for (int t = r; t < T; t += 64) off += E.off[t];
+  off = wave_sum_d(off);
+  if (r == 0) E.trace[it] = off + z;
+  // backward, gamma and the transition counts
+  float row[NR], M[NR], S[NR];
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    row[j] = (live && j < N) ? E.lnA[(size_t)r * N + j] : -INFINITY;
+    M[j] = -INFINITY;
+    S[j] = 0.0f;
+  }
+  float lb = live ? 0.0f : -INFINITY;
+  float lgam;
+  {
+    const float g = la + lb;
+    const float cg = lse_lanes(g, live);   // every lane: the reduction reads lane 63
+    lgam = (live && cg > -INFINITY) ? g - cg : -INFINITY;
+    if (live) E.lgam[(size_t)(T - 1) * N + r] = lgam;
+  }
+  float gmx = lgam;
+  for (int t = T - 1; t >= 1; --t) {
+    buf[r] = live ? E.x[(size_t)t * 64 + r] + lb : -INFINITY;
+    __syncthreads();
+    float mx = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < NR; ++j) mx = fmaxf(mx, row[j] + buf[j]);
+    float s = 0.0f;
+    if (mx > -INFINITY) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) s += __expf(row[j] + buf[j] - mx);
+    }
+    const float sI = (live && mx > -INFINITY) ? mx + __logf(s) : -INFINITY;   // lb_{t-1}(r), unnormalised
+    const float lap = live ? E.la[(size_t)(t - 1) * 64 + r] : -INFINITY;
+    const float g = lap + sI;
+    const float cg = lse_lanes(g, live);
+    lgam = (live && cg > -INFINITY) ? g - cg : -INFINITY;
+    if (live) E.lgam[(size_t)(t - 1) * N + r] = lgam;
+    gmx = fmaxf(gmx, lgam);
+    if (lgam >= kEmLogTiny) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        const float v = lgam + row[j] + buf[j] - sI;   // ln xi_t(r, j)
+        if (v >= kEmLogTiny) {
+          const float d = v - M[j];
+          const float e = __expf(-fabsf(d));
+          S[j] = d > 0.0f ? fmaf(S[j], e, 1.0f) : S[j] + e;
+          M[j] = fmaxf(M[j], v);
+        }
+      }
+    }
+    __syncthreads();
+    const float cb = lse_lanes(sI, live);
+    lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
+  }
+  // pi' = gamma_0; row r of A' from its accumulators (kept if it received nothing)
+  if (live) {
+    E.lnpi_new[r] = lgam >= kEmLogTiny ? lgam : -INFINITY;
+    E.gmax[r] = gmx;
+  }
+  float lr[NR];
+  float rmx = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < NR; ++j) {
+    lr[j] = (S[j] > 0.0f) ? M[j] + __logf(S[j]) : -INFINITY;
+    if (lr[j] < kEmLogTiny) lr[j] = -INFINITY;   // an expected count that underflows a double
+    rmx = fmaxf(rmx, lr[j]);
+  }
+  float rs = 0.0f;
+  if (rmx > -INFINITY) {
+#pragma unroll
+    for (int j = 0; j < NR; ++j) rs += __expf(lr[j] - rmx);
+  }
+  const float lrs = rmx + __logf(rs);
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+    if (live && j < N) E.lnA_new[(size_t)r * N + j] = rmx > -INFINITY ? lr[j] - lrs : row[j];
+}
+
+// Partial sums of the beta update over one chunk of frames: lane = bin f of a
+// 64-bin tile, block (tile, state d, chunk).  theta_t(d, .) and gamma_t(d) are the
+// same for every lane.  KR >= K elements in registers.
+template <int KR>
+__global__ __launch_bounds__(64) void k_em_beta(EmDesc E) {
+  const int f = blockIdx.x * 64 + threadIdx.x, d = blockIdx.y, c = blockIdx.z;
+  const int K = E.K, F = E.F, N = E.N;
+  const bool in = f < F;
+  const float gmx = E.gmax[d];
+  double bz[KR], acc[KR];
+#pragma unroll
+  for (int z = 0; z < KR; ++z) {
+    bz[z] = (in && z < K) ? E.beta[((size_t)d * K + z) * F + f] : 0.0;
+    acc[z] = 0.0;
+  }
+  const int t0 = c * kEmChunk, t1 = min(E.T, t0 + kEmChunk);
+  for (int t = t0; t < t1; ++t) {
+    const float vv = in ? E.V[(size_t)t * F + f] : 0.0f;
+    const double *th = E.theta + ((size_t)t * N + d) * K;
+    double tz[KR];
+    double P = 0.0;
+#pragma unroll
+    for (int z = 0; z < KR; ++z) {
+      tz[z] = z < K ? th[z] : 0.0;
+      P = fma(tz[z], bz[z], P);
+    }
+    // gamma_t(d) relative to the state's largest: the row is normalised over f,
+    // so the per-state scale cancels, and frames far below the largest still count
+    const float lg = E.lgam[(size_t)t * N + d];
+    const double g = lg >= kEmLogTiny ? exp((double)(lg - gmx)) : 0.0;
+    const double gr = (vv > 0.0f && g > 0.0) ? g * ((double)vv / P) : 0.0;
+#pragma unroll
+    for (int z = 0; z < KR; ++z) acc[z] = fma(tz[z], gr, acc[z]);
+  }
+  if (in) {
+    double *out = E.bpart + ((size_t)c * N + d) * K * F;
+    for (int z = 0; z < K; ++z) out[(size_t)z * F + f] = acc[z];
+  }
+}
+
+// beta'(d, z, .) for one row (d, z): the chunks' partial sums in order, times
+// beta(d, z, f), normalised over f (the row is kept if it received nothing).
+__global__ __launch_bounds__(256) void k_em_beta_reduce(EmDesc E) {
+  const int rw = blockIdx.x, F = E.F, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const size_t NKF = (size_t)E.N * E.K * F;
+  __shared__ double red[4];
+  __shared__ double total;
+  const double *brow = E.beta + (size_t)rw * F;
+  double *nrow = E.beta_new + (size_t)rw * F;
+  double s = 0.0;
+  for (int f = tid; f < F; f += 256) {
+    double acc = 0.0;
+    for (int c = 0; c < E.nchunk; ++c) acc += E.bpart[(size_t)c * NKF + (size_t)rw * F + f];
+    const double x = brow[f] * acc;
+    nrow[f] = x;
+    s += x;
+  }
+  s = wave_sum_d(s);
+  if (lane == 0) red[wave] = s;
+  __syncthreads();
+  if (tid == 0) total = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  const double tot = total;
+  for (int f = tid; f < F; f += 256) nrow[f] = tot > 0.0 ? nrow[f] / tot : brow[f];
+}
+
+// float32 parameters <-> working parameters (grid-stride over the largest array)
+__global__ void k_em_import(int N, int K, int F, int T, const float *W, const float *theta, const float *A,
+                            const float *pi, double *beta, double *th, float *lnA, float *lnpi) {
+  const size_t nb = (size_t)N * K * F, nt = (size_t)T * N * K, na = (size_t)N * N;
+  const size_t n = nb > nt ? nb : nt;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    if (i < nb) beta[i] = (double)W[i];
+    if (i < nt) th[i] = (double)theta[i];
+    if (i < na) lnA[i] = A[i] > 0.0f ? logf(A[i]) : -INFINITY;
+    if (i < (size_t)N) lnpi[i] = pi[i] > 0.0f ? logf(pi[i]) : -INFINITY;
+  }
+}
+
+__global__ void k_em_export(int N, int K, int F, int T, const double *beta, const double *th, const float *lnA,
+                            const float *lnpi, float *W, float *theta, float *A, float *pi) {
+  const size_t nb = (size_t)N * K * F, nt = (size_t)T * N * K, na = (size_t)N * N;
+  const size_t n = nb > nt ? nb : nt;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    if (W && i < nb) W[i] = (float)beta[i];
+    if (theta && i < nt) theta[i] = (float)th[i];
+    if (A && i < na) A[i] = expf(lnA[i]);
+    if (pi && i < (size_t)N) pi[i] = expf(lnpi[i]);
+  }
+}
+
+hipError_t launch_em_frames(const EmDesc &E, hipStream_t st) {
+  if (E.K <= 4) k_em_frame<4><<<E.T * E.N, 256, 0, st>>>(E);
+  else if (E.K <= 8) k_em_frame<8><<<E.T * E.N, 256, 0, st>>>(E);
+  else if (E.K <= 16) k_em_frame<16><<<E.T * E.N, 256, 0, st>>>(E);
+  else k_em_frame<kEmMaxK><<<E.T * E.N, 256, 0, st>>>(E);
+  k_em_prep<<<E.T, 64, 0, st>>>(E);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_chain(const EmDesc &E, int it, hipStream_t st) {
+  const int nr = (E.N + 15) & ~15;
+  switch (nr) {
+    case 16: k_em_chain<16><<<1, 64, 0, st>>>(E, it); break;
+    case 32: k_em_chain<32><<<1, 64, 0, st>>>(E, it); break;
+    case 48: k_em_chain<48><<<1, 64, 0, st>>>(E, it); break;
+    case 64: k_em_chain<64><<<1, 64, 0, st>>>(E, it); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_em_beta(const EmDesc &E, hipStream_t st) {
+  const dim3 g((E.F + 63) / 64, E.N, E.nchunk);
+  if (E.K <= 4) k_em_beta<4><<<g, 64, 0, st>>>(E);
+  else if (E.K <= 8) k_em_beta<8><<<g, 64, 0, st>>>(E);
+  else if (E.K <= 16) k_em_beta<16><<<g, 64, 0, st>>>(E);
+  else k_em_beta<kEmMaxK><<<g, 64, 0, st>>>(E);
+  k_em_beta_reduce<<<E.N * E.K, 256, 0, st>>>(E);
+  return hipGetLastError();
+}
+
+static int em_grid(size_t n) { return (int)(n / 256 + 1 < 2048 ? n / 256 + 1 : 2048); }
+
+hipError_t launch_em_import(int N, int K, int F, int T, const float *W, const float *theta, const float *A,
+                            const float *pi, double *beta, double *th, float *lnA, float *lnpi, hipStream_t st) {
+  const size_t n = std::max((size_t)N * K * F, (size_t)T * N * K);
+  k_em_import<<<em_grid(n), 256, 0, st>>>(N, K, F, T, W, theta, A, pi, beta, th, lnA, lnpi);
+  return hipGetLastError();
+}
+
+hipError_t launch_em_export(int N, int K, int F, int T, const double *beta, const double *th, const float *lnA,
+                            const float *lnpi, float *W, float *theta, float *A, float *pi, hipStream_t st) {
+  const size_t n = std::max((size_t)N * K * F, (size_t)T * N * K);
+  k_em_export<<<em_grid(n), 256, 0, st>>>(N, K, F, T, beta, th, lnA, lnpi, W, theta, A, pi);
+  return hipGetLastError();
+}
+
+}  // namespace nfhmm

@@ -41,6 +41,7 @@ SYMBOLS = [
     "nfhmm_wait", "nfhmm_cancel", "nfhmm_chain_posterior", "nfhmm_special_functions",
     "nfhmm_profile_enable", "nfhmm_profile_read", "nfhmm_profile_select", "nfhmm_set_lanes",
     "nfhmm_stft_frames", "nfhmm_stft", "nfhmm_istft", "nfhmm_stft_device", "nfhmm_istft_device",
+    "nfhmm_learn_nhmm", "nfhmm_learn_nhmm_device",
 ]
 K_SPECTRUM, K_COUNTS, K_CHAINS, K_UPDATE, K_POSTERIOR = 0, 1, 2, 3, 4
 KERNEL_KINDS = {"spectrum": K_SPECTRUM, "counts": K_COUNTS, "chains": K_CHAINS, "update": K_UPDATE,
@@ -57,6 +58,17 @@ class nfhmm_problem(C.Structure):
 class nfhmm_result(C.Structure):
     _fields_ = [("alpha", C.c_void_p), ("post", C.c_void_p), ("sep", C.c_void_p),
                 ("elbo", C.c_void_p)]
+
+
+class nfhmm_nhmm_problem(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("F", C.c_int64), ("T", C.c_int64),
+                ("V", C.c_void_p), ("W", C.c_void_p), ("theta", C.c_void_p), ("A", C.c_void_p),
+                ("pi", C.c_void_p), ("iters", C.c_int32)]
+
+
+class nfhmm_nhmm_result(C.Structure):
+    _fields_ = [("W", C.c_void_p), ("theta", C.c_void_p), ("A", C.c_void_p), ("pi", C.c_void_p),
+                ("loglik", C.c_void_p)]
 
 
 _P = C.POINTER
@@ -121,6 +133,10 @@ _lib.nfhmm_profile_enable.argtypes = [C.c_void_p, C.c_int]
 _lib.nfhmm_profile_enable.restype = C.c_int
 _lib.nfhmm_profile_read.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C.c_double)]
 _lib.nfhmm_profile_read.restype = C.c_int
+_lib.nfhmm_learn_nhmm.argtypes = [C.c_void_p, _P(nfhmm_nhmm_problem), _P(nfhmm_nhmm_result)]
+_lib.nfhmm_learn_nhmm.restype = C.c_int
+_lib.nfhmm_learn_nhmm_device.argtypes = [C.c_void_p, _P(nfhmm_nhmm_problem), _P(nfhmm_nhmm_result), C.c_void_p]
+_lib.nfhmm_learn_nhmm_device.restype = C.c_int
 
 
 class NfhmmError(RuntimeError):
@@ -425,3 +441,49 @@ def profile_read(ctx: Context, kind):
     n, ms = C.c_int64(), C.c_double()
     _check(_lib.nfhmm_profile_read(ctx.handle, KERNEL_KINDS.get(kind, kind), C.byref(n), C.byref(ms)), ctx.handle)
     return int(n.value), float(ms.value)
+
+
+def learn_nhmm(ctx: Context, prob, iters=None):
+    """nfhmm_learn_nhmm on host arrays.  prob: V [T][F], W [N][K][F], theta [T][N][K],
+    A [N][N], pi [N] (the starting parameters) and iters; returns dict(W, theta, A, pi,
+    loglik)."""
+    V, W, th, A, pi = (_f32(prob[k]) for k in ("V", "W", "theta", "A", "pi"))
+    T, F = V.shape
+    N, K = W.shape[0], W.shape[1]
+    it = int(prob["iters"] if iters is None else iters)
+    out = dict(W=np.empty_like(W), theta=np.empty_like(th), A=np.empty_like(A), pi=np.empty_like(pi),
+               loglik=np.empty(it, np.float64))
+    p = nfhmm_nhmm_problem(N, K, F, T, _ptr(V), _ptr(W), _ptr(th), _ptr(A), _ptr(pi), it)
+    r = nfhmm_nhmm_result(*(_ptr(out[k]) for k in ("W", "theta", "A", "pi", "loglik")))
+    _check(_lib.nfhmm_learn_nhmm(ctx.handle, C.byref(p), C.byref(r)), ctx.handle)
+    return out
+
+
+class DeviceNhmm:
+    """Device-resident inputs and outputs of one EM problem (torch tensors on the GPU)."""
+
+    def __init__(self, prob, iters=None, device="cuda"):
+        import torch
+        dev = torch.device(device)
+        f = lambda k: torch.as_tensor(_f32(prob[k]), device=dev)  # noqa: E731
+        self.V, self.W, self.theta, self.A, self.pi = (f(k) for k in ("V", "W", "theta", "A", "pi"))
+        self.T, self.F = self.V.shape
+        self.N, self.K = self.W.shape[0], self.W.shape[1]
+        self.iters = int(prob["iters"] if iters is None else iters)
+        self.W_out, self.theta_out = torch.empty_like(self.W), torch.empty_like(self.theta)
+        self.A_out, self.pi_out = torch.empty_like(self.A), torch.empty_like(self.pi)
+        self.loglik = torch.empty((self.iters,), dtype=torch.float64, device=dev)
+
+    def structs(self):
+        p = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+        prob = nfhmm_nhmm_problem(self.N, self.K, self.F, self.T, p(self.V), p(self.W), p(self.theta), p(self.A),
+                                  p(self.pi), self.iters)
+        res = nfhmm_nhmm_result(p(self.W_out), p(self.theta_out), p(self.A_out), p(self.pi_out), p(self.loglik))
+        return prob, res
+
+
+def learn_nhmm_device(ctx: Context, job: DeviceNhmm, stream=None):
+    """nfhmm_learn_nhmm_device on DeviceNhmm tensors."""
+    prob, res = job.structs()
+    h = None if stream is None else C.c_void_p(stream.cuda_stream)
+    _check(_lib.nfhmm_learn_nhmm_device(ctx.handle, C.byref(prob), C.byref(res), h), ctx.handle)

@@ -31,7 +31,7 @@ from collections import defaultdict
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-KERNEL_SOURCES = ("nfhmm_kernels.hip", "special.h", "jobdesc.h", "launch.h")
+KERNEL_SOURCES = ("nfhmm_kernels.hip", "special.h", "wave.h", "jobdesc.h", "launch.h")
 
 
 def kernel_source_hash(files=KERNEL_SOURCES) -> str:

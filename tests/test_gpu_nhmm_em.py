@@ -1,0 +1,128 @@
+"""EM learning of one source's N-HMM on the GPU (nfhmm_learn_nhmm through the C
+ABI) against the FP64 reference of oracle/nhmm_em_oracle.py (the steps derived
+from the model of Section 2.1; the reference is pinned in tests/test_nhmm_em_pins.py).
+
+Both start from the same float32 parameters and run the same number of
+iterations; every learned parameter and the log-likelihood trace are compared
+element by element.  The GPU keeps beta and theta in double between iterations
+and runs the chain in float32 log space (A and pi as logarithms), treating as zero
+what underflows a double, as the reference does; the differences are the chain's
+float32 rounding carried through the updates.  Tolerances: dictionaries
+|d beta| <= 1e-5 of their row's largest entry, theta |d| <= 1e-6, A |d| <= 2e-5,
+pi |d| <= 1e-5, ln P(V) 1e-9 relative (measured at the paper's shapes: 6.4e-7,
+9e-9, 2.2e-6, 0, 9e-11).
+"""
+import numpy as np
+import pytest
+
+from gen import make_nhmm_problem
+from oracle import nhmm_em_oracle as EM
+
+pytestmark = pytest.mark.gpu
+
+TOL = dict(W=1e-5, theta=1e-6, A=2e-5, pi=1e-5, loglik=1e-9)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1206_6468_amd import nfhmm
+    return nfhmm
+
+
+@pytest.fixture(scope="module")
+def ctx(L):
+    c = L.Context(0)
+    yield c
+    c.close()
+
+
+def _oracle(prob, iters):
+    f64 = lambda k: np.asarray(prob[k], np.float64)  # noqa: E731
+    V, beta, theta, A, pi = (f64(k) for k in ("V", "W", "theta", "A", "pi"))
+    trace = []
+    for _ in range(iters):
+        beta, theta, A, pi, lnZ = EM.em_step(V, beta, theta, A, pi)
+        trace.append(lnZ)
+    return dict(W=beta, theta=theta, A=A, pi=pi, loglik=np.array(trace))
+
+
+def _errs(g, r):
+    rowmax = np.max(r["W"], axis=-1, keepdims=True)
+    return dict(W=float(np.max(np.abs(g["W"] - r["W"]) / rowmax)),
+                theta=float(np.max(np.abs(g["theta"] - r["theta"]))),
+                A=float(np.max(np.abs(g["A"] - r["A"]))),
+                pi=float(np.max(np.abs(g["pi"] - r["pi"]))),
+                loglik=float(np.max(np.abs(g["loglik"] - r["loglik"]) / np.abs(r["loglik"]))))
+
+
+def _fmt(e):
+    return "  ".join(f"{k} {v:.2e}" for k, v in e.items())
+
+
+@pytest.mark.parametrize("name,over", [
+    ("small", dict(N=4, K=3, F=24, T=40, iters=8)),
+    ("ragged", dict(N=7, K=5, F=70, T=131, iters=5)),
+    ("one-state", dict(N=1, K=6, F=33, T=50, iters=5)),
+    ("K-max", dict(N=3, K=32, F=65, T=66, iters=4)),
+])
+def test_em_matches_oracle(L, ctx, name, over):
+    p = make_nhmm_problem(0, 1, **over)
+    g = L.learn_nhmm(ctx, p)
+    r = _oracle(p, p["iters"])
+    e = _errs(g, r)
+    print(f"\n{name} x{p['iters']}: {_fmt(e)}")
+    for k, tol in TOL.items():
+        assert e[k] <= tol, (k, e[k])
+
+
+def test_em_paper_shape(L, ctx):
+    """One speaker's model at the separation's shapes: N = 40 states of K = 10
+    elements, F = 513 bins, T = 1000 frames; three iterations."""
+    p = make_nhmm_problem(1, 0, iters=3)
+    g = L.learn_nhmm(ctx, p)
+    r = _oracle(p, 3)
+    e = _errs(g, r)
+    print(f"\npaper shape x3: {_fmt(e)}")
+    for k, tol in TOL.items():
+        assert e[k] <= tol, (k, e[k])
+
+
+def test_em_likelihood_never_decreases(L, ctx):
+    p = make_nhmm_problem(1, 1, N=20, K=8, T=400, iters=25)
+    g = L.learn_nhmm(ctx, p)
+    tr = g["loglik"]
+    print(f"\nln P(V): {tr[0]:.6e} -> {tr[-1]:.6e}")
+    assert np.all(np.isfinite(tr))
+    assert np.all(np.diff(tr) >= -1e-9 * np.abs(tr[1:]))
+    assert tr[-1] > tr[0]
+    np.testing.assert_allclose(g["W"].sum(-1), 1.0, atol=2e-6)
+    np.testing.assert_allclose(g["theta"].sum(-1), 1.0, atol=2e-6)
+    np.testing.assert_allclose(g["A"].sum(-1), 1.0, atol=2e-6)
+
+
+def test_em_device_path_equals_host_path(L, ctx):
+    import torch
+    p = make_nhmm_problem(0, 2, N=6, K=4, F=50, T=90, iters=4)
+    h = L.learn_nhmm(ctx, p)
+    j = L.DeviceNhmm(p)
+    L.learn_nhmm_device(ctx, j)
+    torch.cuda.synchronize()
+    for k, t in (("W", j.W_out), ("theta", j.theta_out), ("A", j.A_out), ("pi", j.pi_out), ("loglik", j.loglik)):
+        assert np.array_equal(h[k], t.cpu().numpy()), k
+
+
+def test_em_rejects_invalid_starts(L, ctx):
+    p = make_nhmm_problem(0, 3, N=3, K=2, F=16, T=20, iters=2)
+    bad_theta = dict(p, theta=p["theta"].copy())
+    bad_theta["theta"][4, 1] = [1.0, 0.0]
+    W = p["W"].astype(np.float64).copy()
+    W[1, :, 5] = 0.0
+    W /= W.sum(-1, keepdims=True)
+    V = p["V"].copy()
+    V[:, 5] = np.maximum(V[:, 5], 1.0)
+    bad_cover = dict(p, W=W.astype(np.float32), V=V)
+    for bad, needle in ((bad_theta, "theta"), (bad_cover, "bin 5")):
+        with pytest.raises(L.NfhmmError) as e:
+            L.learn_nhmm(ctx, bad)
+        assert e.value.status == L.E_INVALID and needle in str(e.value)
+    assert np.all(np.isfinite(L.learn_nhmm(ctx, p)["loglik"]))
