@@ -27,10 +27,10 @@ PEAK_HBM = 8.0e12             # B/s
 PEAK_FP32_VALU = 157.3e12     # MI355X FP32 vector, FLOP/s
 
 
-def _traffic_for(kernel, workload, record="hbm_traffic.json"):
-    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
-    a plain copy) from a committed counter record, if it was taken on the
-    current sources of the kernels it covers and on this workload; else None."""
+def _traffic_record(record):
+    """A committed counter record (rocprofv3 FETCH_SIZE + WRITE_SIZE per kernel,
+    scaled by a plain copy), if it was taken on the current sources of the kernels
+    it covers; else None."""
     from paper_1206_6468_amd.rocprof_summary import KERNEL_SOURCES, kernel_source_hash
     path = os.path.join(ROOT, "profiles", record)
     try:
@@ -40,10 +40,19 @@ def _traffic_for(kernel, workload, record="hbm_traffic.json"):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash(tuple(d.get("kernel_sources", KERNEL_SOURCES))):
         return None
-    e = d.get("kernels", {}).get(kernel, {})
-    if e.get("workload") != workload:
+    return d
+
+
+def _traffic_for(kernel, workload, record="hbm_traffic.json"):
+    """Measured HBM bytes per launch of `kernel` (its FP32 instantiation when the
+    record names template arguments) on this workload, from a current record; else None."""
+    d = _traffic_record(record)
+    if d is None:
         return None
-    return e.get("bytes_per_launch")
+    for name, e in d.get("kernels", {}).items():
+        if (name == kernel or name.startswith(kernel + "<false")) and e.get("workload") == workload:
+            return e.get("bytes_per_launch")
+    return None
 
 
 def bf16_bytes_per_frame_iteration(S, N, K, F, T):
@@ -54,6 +63,21 @@ def bf16_bytes_per_frame_iteration(S, N, K, F, T):
     iteration and shared by the T frames (2 F M / T)."""
     M = S * N * K
     return 4.0 * F + 8.0 * M + 8.0 * S * N + 2.0 * F * M / T
+
+
+def bf16_measured_bytes(J, T, iters, record="hbm_traffic_bf16.json"):
+    """HBM bytes per frame-iteration that the BF16 form's iteration kernels move by
+    counter, from a current record of one fit of the same batch (bench.py --bf16-only
+    --steps 1 --warmup 0: every dispatch of these kernels belongs to its `iters`
+    iterations, plus the default start's one launch of each contraction); else None."""
+    d = _traffic_record(record)
+    if d is None:
+        return None
+    per_iter = ("k_spectrum", "k_counts", "k_counts_bf16", "k_update", "k_fb_round", "k_fb_fixup", "k_posterior",
+                "k_chain_exact")
+    tot = sum(e["bytes_per_launch"] * e["dispatches"] for name, e in d.get("kernels", {}).items()
+              if name.split("<")[0] in per_iter)
+    return tot / (iters * J * T)
 
 
 def make_jobs(cfg, n, iters=None):
@@ -131,6 +155,16 @@ def serving(L, probs, budget_bytes, max_slots, load=0.8, seed=4):
         t_sat = time.perf_counter() - t0
         rate = load * n_jobs / t_sat
 
+        # the same, bringing back only the posteriors and the separations (not
+        # alpha-hat, 40 % of the bytes): how much of the saturated time is the
+        # host<->device copies
+        log("serving: saturated, posteriors and separations only")
+        t0 = time.perf_counter()
+        subs = [L.submit(ctx, p, "bf16", outputs=("post", "sep", "elbo")) for p in probs]
+        for sb in subs:
+            L.wait(ctx, sb)
+        t_sep = time.perf_counter() - t0
+
         log(f"serving: Poisson arrivals at {rate:.1f} jobs/s")
         rng = np.random.default_rng(seed)
         arrivals = np.cumsum(rng.exponential(1.0 / rate, n_jobs))
@@ -175,6 +209,11 @@ def serving(L, probs, budget_bytes, max_slots, load=0.8, seed=4):
         "saturated": {"seconds": t_sat, "jobs_per_s": n_jobs / t_sat, "frame_iterations_per_s": work / t_sat,
                       "p50_ms": float(np.percentile(np.array(lat_sat) * 1e3, 50)),
                       "p99_ms": float(np.percentile(np.array(lat_sat) * 1e3, 99))},
+        "saturated_without_alpha": {"seconds": t_sep, "frame_iterations_per_s": work / t_sep,
+                                    "note": "the same jobs bringing back d-hat, V* and the bound only"},
+        "copied_gb": {"in": sum(p["V"].nbytes + p["W"].nbytes + p["A"].nbytes + p["pi"].nbytes for p in probs) / 1e9,
+                      "out": sum(p["T"] * p["S"] * p["N"] * p["K"] * 4 + p["S"] * p["T"] * (p["N"] + p["F"]) * 4
+                                 for p in probs) / 1e9},
         "poisson": {"load": load, "rate_jobs_per_s": rate, "seconds": t_end - t_start,
                     "frame_iterations_per_s": work / (t_end - t_start),
                     "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
@@ -383,6 +422,9 @@ def main():
     ap.add_argument("--stft-only", action="store_true",
                     help="only time the time-frequency front and back end (STFT of 32 mixtures of "
                          "1000 frames, inverse of 2 sources each) and print its figures")
+    ap.add_argument("--bf16-only", action="store_true",
+                    help="only time the BF16-contraction form of the batch (for a profiler run of its "
+                         "kernels) and print its figures")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs on a single MI355X and has no "
@@ -407,6 +449,18 @@ def main():
     if args.stft_only:
         ctx = L.Context(0)
         print(json.dumps(stft_bench(L, ctx, reps=max(args.steps, 1))), flush=True)
+        ctx.close()
+        return
+    if args.bf16_only:
+        probs = make_jobs(1, args.jobs)
+        ctx = L.Context(0)
+        jobs = [L.DeviceJob(p) for p in probs]
+        dtb, profb = time_batch(L, ctx, jobs, "bf16", args.steps, args.warmup, profile=True)
+        p0 = probs[0]
+        print(json.dumps({"workload": f"S{p0['S']}-N{p0['N']}-K{p0['K']}-F{p0['F']}-T{p0['T']}-x{len(jobs)}",
+                          "precision": "bf16", "ms_per_step": dtb * 1e3,
+                          "value": len(jobs) * p0["T"] * p0["iters"] / dtb,
+                          "kernels_ms_per_launch": {k: v[1] / max(v[0], 1) for k, v in profb.items()}}), flush=True)
         ctx.close()
         return
     # host-side inputs first, before anything touches the GPU
@@ -487,6 +541,7 @@ def main():
                                            "unit": "GB/s", "frac": vb * bytes_fi / PEAK_HBM,
                                            "algorithmic_bytes_per_frame_iteration": bytes_fi},
                          "k_counts_tflops": tb / 1e12, "k_counts_frac_of_bf16_peak": tb / PEAK_BF16_MFMA,
+                         "measured_bytes_per_frame_iteration": bf16_measured_bytes(J, T, iters),
                          "kernels_ms_per_launch": {k: v[1] / max(v[0], 1) for k, v in profb.items()},
                          "dominant": max(profb, key=lambda k: profb[k][1])}
         # three sources (S=3, N=40, K=10, F=513, T=1000): the cost is linear in S

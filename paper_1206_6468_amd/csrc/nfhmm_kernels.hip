@@ -1308,7 +1308,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
       const float lxs = fast_ln(z.xs);
       const float ps = lxs + rest;
       float w = in ? (z.xs * inv_xs0) * fast_exp(rest - rest0) : 0.0f;
-      if (msg && in) lg += (double)lgamma_from(z, lxs);
+      if (msg && in) lg += (double)lgamma_from_ge1(z, lxs);   // alpha >= 1 (Eq. 6)
       if (k < Mp) {
         sE[k] = in ? ps : 0.0f;
         if constexpr (kBF16) {
@@ -1368,7 +1368,7 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
     tot.hi = (float)lg;
     tot.lo = (float)(lg - (double)tot.hi);
     tot = comp_merge(tot, wave_comp(pv));
-    comp_add(tot, -lgamma_from(z0, fast_ln(z0.xs)));
+    comp_add(tot, -lgamma_from_ge1(z0, fast_ln(z0.xs)));
     tot = comp_merge(tot, chain);
     comp_add(tot, vtail.x);
     comp_add(tot, vtail.y);

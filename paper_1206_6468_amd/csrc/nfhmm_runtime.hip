@@ -384,7 +384,10 @@ enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFBR, kFB, kPost, kChain, kUpd, kF
 struct Table {
   WorkList lists[kNumLists];
   int nmax = 1, mpmax = 32, upd_stride = 32;
-  bool spec_small = false;   // 64 x 64 spectrum tiles (the batch would not fill the chip)
+  // spectrum block tiles: FP32 always 64 x 64 (four blocks per CU; measured 1 %
+  // faster than 128 x 64 for the paper-typical batch); BF16 128 x 64, or 64 x 64
+  // when the batch would not fill the chip
+  bool spec_small = false;
   char *dev = nullptr, *host = nullptr;
   size_t cap = 0;
 };
@@ -415,7 +418,7 @@ int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb, bool spec_sm
   const int spec = spec_blocks(D, spec_small);
   const int cnt = ((D.Mp + kCntBM - 1) / kCntBM) * ((D.T + kCntBN - 1) / kCntBN);
   switch (k) {
-    case kSpecF: return bf16 ? 0 : spec;
+    case kSpecF: return bf16 ? 0 : spec_blocks(D, true);
     case kSpecH: return bf16 ? spec : 0;
     case kCntF: return bf16 ? 0 : cnt;
     case kCntH: return bf16 ? cnt : 0;
@@ -826,7 +829,7 @@ nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStr
     TableLease lease;
     nfhmm_status s = get_table(ctx, uni, st, &t, lease);
     if (s != NFHMM_OK) return s;
-    HIP_OK(launch_spectrum(t->lists[kSpecF], false, t->spec_small, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecF], false, true, st));
     HIP_OK(launch_spectrum(t->lists[kSpecH], true, t->spec_small, st));
     HIP_OK(launch_counts(t->lists[kCntF], false, st));
     HIP_OK(launch_counts(t->lists[kCntH], true, st));
@@ -894,7 +897,7 @@ nfhmm_status engine_iterate(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, int 
   HIP_OK(hipEventRecord(ev_join, fb));
   {
     Timed tm(ctx, NFHMM_K_SPECTRUM, st);
-    HIP_OK(launch_spectrum(t->lists[kSpecF], false, t->spec_small, st));
+    HIP_OK(launch_spectrum(t->lists[kSpecF], false, true, st));
     HIP_OK(launch_spectrum(t->lists[kSpecH], true, t->spec_small, st));
   }
   {
@@ -1421,7 +1424,7 @@ nfhmm_status nfhmm_fit_device_noalloc(nfhmm_ctx *ctx, const nfhmm_problem *dev_p
     HIP_OK(launch_update(wl[kUpd], kUpdFromAlpha, 0, stride, st));
   } else {
     HIP_OK(launch_fill_w_ones(D, st));
-    HIP_OK(launch_spectrum(wl[kSpecF], false, small, st));
+    HIP_OK(launch_spectrum(wl[kSpecF], false, true, st));
     HIP_OK(launch_spectrum(wl[kSpecH], true, small, st));
     HIP_OK(launch_counts(wl[kCntF], false, st));
     HIP_OK(launch_counts(wl[kCntH], true, st));
@@ -1431,7 +1434,7 @@ nfhmm_status nfhmm_fit_device_noalloc(nfhmm_ctx *ctx, const nfhmm_problem *dev_p
   for (int r = 0; r < j.d.iters; ++r) {
     HIP_OK(launch_chain_fb(wl[kFBR], wl[kFB], nmax, st));
     HIP_OK(launch_posterior(wl[kPost], wl[kChain], nmax, st));
-    HIP_OK(launch_spectrum(wl[kSpecF], false, small, st));
+    HIP_OK(launch_spectrum(wl[kSpecF], false, true, st));
     HIP_OK(launch_spectrum(wl[kSpecH], true, small, st));
     HIP_OK(launch_counts(wl[kCntF], false, st));
     HIP_OK(launch_counts(wl[kCntH], true, st));

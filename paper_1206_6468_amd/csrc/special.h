@@ -116,6 +116,18 @@ NFHMM_HD float lgamma_from(const Shift8 &s, float lxs) {
   return (s.xs - 0.5f) * lxs - s.xs + half_log_2pi + series - lp;
 }
 
+// ln Gamma(x) given lxs = ln xs, for x >= 1: the shift product p is then 1 or at
+// least 1 * 2 * 3 * 4, never below the normal range, so ln p needs no guard
+NFHMM_HD float lgamma_from_ge1(const Shift8 &s, float lxs) {
+  const float r = fast_rcp(s.xs);
+  const float r2 = r * r;
+  const float series =
+      r * (1.0f / 12.0f - r2 * (1.0f / 360.0f - r2 * (1.0f / 1260.0f - r2 * (1.0f / 1680.0f - r2 * (1.0f / 1188.0f)))));
+  const float half_log_2pi = 0.91893853320467274f;
+  const float lp = s.p == 1.0f ? 0.0f : fast_ln(s.p);
+  return (s.xs - 0.5f) * lxs - s.xs + half_log_2pi + series - lp;
+}
+
 // psi(x) for x > 0
 NFHMM_HD float digammaf(float x) {
   const Shift8 s = shift8(x);

@@ -196,14 +196,19 @@ def _problem_struct(prob, keep):
                          float(prob.get("gamma", 1.0)), int(prob["iters"]), _ptr(ai))
 
 
-def _alloc_outputs(prob, keep):
+OUTPUTS = ("alpha", "post", "sep", "elbo")
+
+
+def _alloc_outputs(prob, keep, outputs=OUTPUTS):
+    """Output arrays of one problem; those not named in `outputs` are skipped (NULL)."""
     S, N, K, F, T = (int(prob[k]) for k in ("S", "N", "K", "F", "T"))
     it = int(prob["iters"])
-    out = dict(alpha=np.empty((T, S * N * K), np.float32), post=np.empty((S, T, N), np.float32),
-               sep=np.empty((S, T, F), np.float32), elbo=np.empty(max(it, 0), np.float64))
+    shapes = dict(alpha=((T, S * N * K), np.float32), post=((S, T, N), np.float32),
+                  sep=((S, T, F), np.float32), elbo=((max(it, 0),), np.float64))
+    out = {k: np.empty(*shapes[k]) for k in OUTPUTS if k in outputs}
     keep.append(out)
-    return out, nfhmm_result(_ptr(out["alpha"]), _ptr(out["post"]), _ptr(out["sep"]),
-                             _ptr(out["elbo"]) if it > 0 else None)
+    return out, nfhmm_result(_ptr(out.get("alpha")), _ptr(out.get("post")), _ptr(out.get("sep")),
+                             _ptr(out.get("elbo")) if it > 0 else None)
 
 
 def footprint_bytes(prob, precision="fp32") -> int:
@@ -305,10 +310,11 @@ class Submitted:
         self._keep = keep
 
 
-def submit(ctx: Context, prob, precision="bf16") -> Submitted:
+def submit(ctx: Context, prob, precision="bf16", outputs=OUTPUTS) -> Submitted:
+    """nfhmm_submit; `outputs` names the results to bring back (the others are NULL)."""
     keep = []
     ps = _problem_struct(prob, keep)
-    out, r = _alloc_outputs(prob, keep)
+    out, r = _alloc_outputs(prob, keep, outputs)
     jid = C.c_uint64()
     _check(_lib.nfhmm_submit(ctx.handle, C.byref(ps), _PREC[precision], C.byref(r), C.byref(jid)), ctx.handle)
     return Submitted(int(jid.value), out, keep)

@@ -62,6 +62,24 @@ def test_serving_results_equal_alone(L, precision):
         ctx.close()
 
 
+def test_serving_with_outputs_skipped(L):
+    """Outputs left NULL are neither computed into nor copied back; the others equal
+    those of the same job with every output requested."""
+    probs = _mix()[:4]
+    ctx = L.Context(0)
+    try:
+        full = [L.wait(ctx, L.submit(ctx, p, "bf16"))[0] for p in probs]
+        for want in (("post", "sep", "elbo"), ("alpha",), ("sep",), ()):
+            subs = [L.submit(ctx, p, "bf16", outputs=want) for p in probs]
+            for s, f in zip(subs, full):
+                out, _ = L.wait(ctx, s)
+                assert set(out) == set(want)
+                for k in want:
+                    assert np.array_equal(out[k], f[k]), (want, k)
+    finally:
+        ctx.close()
+
+
 def test_serving_poll_and_cancel(L):
     ctx = L.Context(0, max_slots=2)
     try:
