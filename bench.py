@@ -193,9 +193,28 @@ def serving(L, probs, budget_bytes, max_slots, load=0.8, seed=4):
     finally:
         ctx.close()
 
-    log("serving: sequential FP32 baseline (one job at a time)")
+    # the same mix as one blocking BF16 batch: with host arrays (the copies of
+    # serving, but no admission, rounds or overlap), then with the inputs resident
+    # (the device-side rate of this mix, which serving's rounds approach when the
+    # copies are free)
+    log("serving: the same jobs as one blocking BF16 batch, host arrays / resident inputs")
+    import torch
     ctx = L.Context(0)
     try:
+        L.fit_batch(ctx, [dict(p, iters=2) for p in probs[:4]], "bf16")
+        t0 = time.perf_counter()
+        L.fit_batch(ctx, probs, "bf16")
+        t_bh = time.perf_counter() - t0
+        djobs = [L.DeviceJob(p) for p in probs]
+        L.fit_batch_device(ctx, djobs, "bf16")          # warm: arenas and tables for these shapes
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L.fit_batch_device(ctx, djobs, "bf16")
+        torch.cuda.synchronize()
+        t_bd = time.perf_counter() - t0
+        del djobs
+
+        log("serving: sequential FP32 baseline (one job at a time)")
         L.fit(ctx, dict(probs[0], iters=2), "fp32")
         t0 = time.perf_counter()
         for p in probs:
@@ -218,6 +237,10 @@ def serving(L, probs, budget_bytes, max_slots, load=0.8, seed=4):
                     "frame_iterations_per_s": work / (t_end - t_start),
                     "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
                     "mean_ms": float(lat_ms.mean()), "max_submit_lag_ms": float(max(lags) * 1e3)},
+        "blocking_bf16_host_arrays": {"seconds": t_bh, "frame_iterations_per_s": work / t_bh,
+                                      "saturated_serving_over_this": t_bh / t_sat},
+        "blocking_bf16_resident": {"seconds": t_bd, "frame_iterations_per_s": work / t_bd,
+                                   "saturated_serving_over_this": t_bd / t_sat},
         "sequential_fp32": {"seconds": t_seq, "frame_iterations_per_s": work / t_seq,
                             "mean_job_ms": t_seq / n_jobs * 1e3},
         "note": "latency = scheduled arrival -> outputs in host memory (includes host<->device copies)",

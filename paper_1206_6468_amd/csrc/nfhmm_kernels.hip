@@ -50,9 +50,12 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------------ packing
+// Each packing step is a block body taking its block index, so that it runs as
+// a per-job kernel (the allocation-free single-job path) or over a work list
+// that covers every job starting together (one launch per step).
+
 // V_in [T][F] -> V [T][Fp]; checks V finite and >= 0.
-__global__ void k_pack_v(JobDesc J) {
-  const int t = blockIdx.x;
+__device__ __forceinline__ void pack_v_row(const JobDesc &J, int t) {
   int bad = 0;
   for (int l = threadIdx.x; l < J.Fp; l += blockDim.x) {
     float v = 0.0f;
@@ -66,8 +69,7 @@ __global__ void k_pack_v(JobDesc J) {
 }
 
 // W_in [M][F] -> Wmf [Mp][Fp] (+ bf16); checks rows finite, >= 0, summing to 1.
-__global__ void k_pack_wmf(JobDesc J) {
-  const int k = blockIdx.x;
+__device__ __forceinline__ void pack_wmf_row(const JobDesc &J, int k) {
   __shared__ float red[256];
   float s = 0.0f;
   int bad = 0;
@@ -92,9 +94,9 @@ __global__ void k_pack_wmf(JobDesc J) {
 }
 
 // Wmf [Mp][Fp] -> Wfm [Fp][Mp] (+ bf16), 32x32 tiles through LDS.
-__global__ void k_transpose_w(JobDesc J) {
+__device__ __forceinline__ void transpose_tile(const JobDesc &J, int bx, int by) {
   __shared__ float tile[32][33];
-  const int k0 = blockIdx.x * 32, l0 = blockIdx.y * 32;
+  const int k0 = bx * 32, l0 = by * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 256 threads: 8 rows per pass
   for (int r = ty; r < 32; r += 8) tile[r][tx] = J.Wmf[(size_t)(k0 + r) * J.Fp + l0 + tx];
   __syncthreads();
@@ -105,10 +107,11 @@ __global__ void k_transpose_w(JobDesc J) {
   }
 }
 
-// w = 1 on the M real elements (z-hat proportional to beta), 0 on the padding.
-__global__ void k_fill_w_ones(JobDesc J) {
+// w = 1 on the M real elements (z-hat proportional to beta), 0 on the padding:
+// part b of nb of the job's T x Mp values.
+__device__ __forceinline__ void fill_w_ones_part(const JobDesc &J, int b, int nb) {
   const size_t n = (size_t)J.T * J.Mp;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+  for (size_t i = (size_t)b * blockDim.x + threadIdx.x; i < n; i += (size_t)nb * blockDim.x) {
     const float v = ((int)(i % J.Mp) < J.M) ? 1.0f : 0.0f;
     if (J.bf16) J.wh[i] = f2bf(v); else J.w[i] = v;
   }
@@ -116,8 +119,8 @@ __global__ void k_fill_w_ones(JobDesc J) {
 
 // Tail bins for the default start (w = 1): Lambda[l][t] = sum_k beta[l][k], R = V / Lambda.
 // One 64-lane block per frame.
-__global__ void k_tail_ones(JobDesc J) {
-  const int t = blockIdx.x, lane = threadIdx.x;
+__device__ __forceinline__ void tail_ones_frame(const JobDesc &J, int t) {
+  const int lane = threadIdx.x;
   for (int jt = 0; jt < J.Ft; ++jt) {
     const int l = J.Fm + jt;
     float acc = 0.0f;
@@ -131,6 +134,44 @@ __global__ void k_tail_ones(JobDesc J) {
       else J.R[(size_t)t * J.Fp + l] = rr;
     }
   }
+}
+
+__global__ void k_pack_v(JobDesc J) { pack_v_row(J, blockIdx.x); }
+__global__ void k_pack_wmf(JobDesc J) { pack_wmf_row(J, blockIdx.x); }
+__global__ void k_transpose_w(JobDesc J) { transpose_tile(J, blockIdx.x, blockIdx.y); }
+__global__ void k_fill_w_ones(JobDesc J) { fill_w_ones_part(J, blockIdx.x, gridDim.x); }
+__global__ void k_tail_ones(JobDesc J) { tail_ones_frame(J, blockIdx.x); }
+
+// Batched forms over a work list.  Per job, k_begin_pack has T blocks packing V,
+// then Mp packing the dictionary, then (default start only) kBeginFillBlocks
+// setting w = 1; k_begin_transpose one block per 32 x 32 tile; k_begin_tail one
+// 64-lane block per frame (default start with tail bins only).
+__global__ void k_status_clear(WorkList wl) {
+  for (int i = threadIdx.x; i < wl.njobs; i += blockDim.x) *wl.jobs[i].status = 0;
+}
+
+__global__ __launch_bounds__(256) void k_begin_pack(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int local = b - wl.start[jb];
+  if (local < J.T) pack_v_row(J, local);
+  else if (local < J.T + J.Mp) pack_wmf_row(J, local - J.T);
+  else fill_w_ones_part(J, local - J.T - J.Mp, kBeginFillBlocks);
+}
+
+__global__ __launch_bounds__(256) void k_begin_transpose(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int local = b - wl.start[jb], nx = J.Mp / 32;
+  transpose_tile(J, local % nx, local / nx);
+}
+
+__global__ __launch_bounds__(64) void k_begin_tail(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  tail_ones_frame(wl.jobs[jb], b - wl.start[jb]);
 }
 
 // ------------------------------------------------------------------ MFMA tiles
@@ -1158,49 +1199,54 @@ __global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
 // chain pass, and the Lambda rows of the tail bins.  alpha itself is stored only
 // when it is an output (the job's last iteration, or a start with no iterations):
 // it is c + gamma B'd + 1 and nothing else reads it.
+//
+// Two forms of the element passes.  The streamed form (any size) walks the row
+// in chunks of 64 x kUpdU elements.  The resident form (rows of at most 1024
+// elements and at most one tail bin: every paper-sized job) issues every load of
+// the frame -- its row of c (or of alpha_init), the tail bin's dictionary row,
+// that bin's count, the frame's d-hat and bound partials -- before anything else,
+// keeps alpha in registers (four float4 per lane, elements 256 j + 4 lane + e),
+// and stores nothing before its last load has been consumed: global loads and
+// stores share one counter on gfx9, so a load issued after a store would also
+// wait for that store.  The two forms sum the tail bins' Lambda in different
+// orders, so a job takes the same form for all its updates (a resumed fit then
+// repeats the uninterrupted one bit for bit).
 __device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
 
-constexpr int kUpdU = 4;   // elements per lane whose loads are issued together
+constexpr int kUpdU = 4;   // elements per lane whose loads are issued together (streamed form)
 constexpr int kMaxTail = 4;   // tail bins handled here (F mod 64 <= 4)
+constexpr int kUpdResident = 1024;   // largest Mp of the resident form
 
-template <bool kBF16>
-__device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, float *sE, int mode, int round) {
-  const int S = J.S, N = J.N, K = J.K, M = J.M, Mp = J.Mp, T = J.T, Fp = J.Fp;
-  const int Fm = J.Fm, Ft = J.Ft, nsl = J.nsl;
-  const int it = round - J.start_round, iters = J.iters;
-  const float gamma = J.gamma;
-  const gfloat *c = gptr(J.c), *alpha_init = gptr(J.alpha_init), *post_in = gptr(J.post);
-  const gfloat *phi_in = gptr(J.phi), *sh_in = gptr(J.sh), *Vin = gptr(J.V);
-  const gfloat *Wfm = gptr(J.Wfm);
-  const gu16 *Wfm_h = gptr(J.Wfm_h);
-  const gfloat2 *lnz = gptr(J.lnz), *clw = gptr(J.clw);
-  gfloat2 *vll = gptr(J.vll), *elbo = gptr(J.elbo);
-  gfloat *alpha = gptr(J.alpha), *wout = gptr(J.w), *Rout = gptr(J.R), *post = gptr(J.post);
-  gfloat *phi = gptr(J.phi), *ev = gptr(J.ev), *sh = gptr(J.sh);
-  gu16 *wh = gptr(J.wh), *Rh = gptr(J.Rh);
+// What the update needs besides the element rows: the contraction-side partials
+// of the bound, the chain's part, and d-hat of every source at frame t in sD.
+struct UpdPre {
+  vf2 vtail;   // tail part of sum V ln Lambda (previous call)
+  Comp pv;     // contraction-side parts of the bound
+  Comp chain;  // ln Z parts and -sum_n d (gamma phi)
+};
 
-  float *sD = sE + Mp;
-  const size_t row = (size_t)t * Mp;
-  const bool msg = mode == kUpdMessages;
-  const bool store_alpha = msg ? (it == iters - 1) : (iters == 0);
+__device__ __forceinline__ UpdPre update_prelude(const JobDesc &J, int t, int lane, float *sD, bool msg) {
+  const int S = J.S, N = J.N, Mp = J.Mp, T = J.T, Ft = J.Ft, nsl = J.nsl;
+  const gfloat *post_in = gptr(J.post), *phi_in = gptr(J.phi), *sh_in = gptr(J.sh);
+  const gfloat2 *lnz = gptr(J.lnz), *clw = gptr(J.clw), *vll = gptr(J.vll);
+  gfloat *post = gptr(J.post);
   const bool live = lane < N;
-
-  // ---- loads that do not depend on anything computed here, issued first
-  vf2 vtail = vf2{0.0f, 0.0f};   // tail part of sum V ln Lambda (previous call)
-  Comp pv = comp_zero();                    // contraction-side parts of the bound
-  Comp chain = comp_zero();
+  UpdPre u;
+  u.vtail = vf2{0.0f, 0.0f};
+  u.pv = comp_zero();
+  u.chain = comp_zero();
   if (msg) {
-    if (Ft > 0) vtail = vll[(size_t)nsl * T + t];
+    if (Ft > 0) u.vtail = vll[(size_t)nsl * T + t];
     const int nkt = (Mp + kCntBM - 1) / kCntBM;
     for (int r = lane; r < nsl; r += 64) {
       const vf2 v = vll[(size_t)r * T + t];
       Comp d; d.hi = v.x; d.lo = v.y;
-      pv = comp_merge(pv, d);
+      u.pv = comp_merge(u.pv, d);
     }
     for (int r = lane; r < nkt; r += 64) {
       const vf2 v = clw[(size_t)r * T + t];
       Comp d; d.hi = v.x; d.lo = v.y;
-      pv = comp_merge(pv, d);
+      u.pv = comp_merge(u.pv, d);
     }
     const int nl = live ? lane : 0;
     float dv[kMaxSources], pf[kMaxSources], shv[kMaxSources];
@@ -1220,15 +1266,15 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
           sD[s * N + lane] = dv[s];
           comp_add(cc, -dv[s] * pf[s]);
         }
-        comp_add(chain, shv[s]);
+        comp_add(u.chain, shv[s]);
       }
     }
-    chain = comp_merge(chain, wave_comp(cc));
+    u.chain = comp_merge(u.chain, wave_comp(cc));
     if (t == 0) {
       for (int s = 0; s < S; ++s) {
         const vf2 z = lnz[s];
-        comp_add(chain, z.x);
-        comp_add(chain, z.y);
+        comp_add(u.chain, z.x);
+        comp_add(u.chain, z.y);
       }
     }
   } else {
@@ -1238,105 +1284,57 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
     }
   }
   lds_order();
+  return u;
+}
 
-  // ---- Eq. 6; element k belongs to state g = k / K (kept incrementally).  Loads
-  //      past the end read the last element (in bounds) and are not used.
-  // alpha_0 and the bound's sum of lnG(alpha_k): per-lane sums in double (exact for
-  // these few terms), then a butterfly over the lanes, which leaves the same value
-  // in every lane.  Sub-chunks of 64 elements past Mp are skipped (a uniform test).
-  double asum = 0.0;
-  {
-    const int step_g = 64 / K, step_r = 64 % K;
-    int g = lane / K, r = lane - (lane / K) * K;
-    const bool from_alpha = mode == kUpdFromAlpha;
-    for (int base = 0; base < Mp; base += 64 * kUpdU) {
-      float cv[kUpdU];
-#pragma unroll
-      for (int u = 0; u < kUpdU; ++u) {
-        if (base + 64 * u >= Mp) break;
-        const int k = min(base + 64 * u + lane, M - 1);
-        cv[u] = from_alpha ? alpha_init[(size_t)t * M + k] : c[row + k];
-      }
-#pragma unroll
-      for (int u = 0; u < kUpdU; ++u) {
-        if (base + 64 * u >= Mp) break;
-        const int k = base + 64 * u + lane;
-        float a = from_alpha ? cv[u] : cv[u] + gamma * sD[min(g, S * N - 1)] + 1.0f;
-        a = k < M ? a : 0.0f;
-        asum += (double)a;
-        if (store_alpha && k < M) alpha[row + k] = a;
-        if (k < Mp) sE[k] = a;   // Mp is a multiple of 32: the last sub-chunk may be half full
-        g += step_g;
-        r += step_r;
-        if (r >= K) { r -= K; ++g; }
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) asum += __shfl_xor(asum, o);
-  const float a0 = (float)asum;
-  const Shift8 z0 = shift8(a0);
-  const float rest0 = psi_rest(z0);
-  const float inv_xs0 = 1.0f / z0.xs;
-  lds_order();
+// One element of the second pass: psi(alpha) into sE (for Eq. 8), w, and the
+// bound's lnG(alpha).  alpha >= 1 (Eq. 6) for every element in a c-based mode.
+struct ElemOut {
+  float w, ps;
+};
+__device__ __forceinline__ ElemOut update_elem(float a, bool in, float inv_xs0, float rest0, bool want_lg, double &lg) {
+  // straight-line code, results selected at the end: a branch around the
+  // exponential or lnG would split the element's computation and keep its
+  // temporaries live across the branch
+  const Shift8 z = shift8(in ? a : 1.0f);
+  const float rest = psi_rest(z);
+  const float lxs = fast_ln(z.xs);
+  const float w = (z.xs * inv_xs0) * fast_exp(rest - rest0);
+  const float l = lgamma_from_ge1(z, lxs);
+  ElemOut o;
+  o.ps = in ? lxs + rest : 0.0f;
+  o.w = in ? w : 0.0f;
+  lg += (want_lg && in) ? (double)l : 0.0;
+  return o;
+}
 
-  // ---- w = exp(psi(alpha) - psi(alpha_0)) = (xs / xs0) exp(rest - rest0);
-  //      sE keeps psi(alpha_k) for Eq. 8; sum_k lnG(alpha_k) for the bound;
-  //      tail bins: Lambda[l][t] = sum_k beta[l][k] w_k for the next contraction
-  double lg = 0.0;
-  float tacc[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
-  for (int base = 0; base < Mp; base += 64 * kUpdU) {
-    float tw[kMaxTail][kUpdU];
-#pragma unroll
-    for (int jt = 0; jt < kMaxTail; ++jt) {
-      if (jt < Ft) {
-#pragma unroll
-        for (int u = 0; u < kUpdU; ++u) {
-          if (base + 64 * u >= Mp) break;
-          const size_t o = (size_t)(Fm + jt) * Mp + min(base + 64 * u + lane, M - 1);
-          tw[jt][u] = kBF16 ? bf2f(Wfm_h[o]) : Wfm[o];
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kUpdU; ++u) {
-      if (base + 64 * u >= Mp) break;
-      const int k = base + 64 * u + lane;
-      const bool in = k < M;
-      const Shift8 z = shift8(in ? sE[k] : 1.0f);
-      const float rest = psi_rest(z);
-      const float lxs = fast_ln(z.xs);
-      const float ps = lxs + rest;
-      float w = in ? (z.xs * inv_xs0) * fast_exp(rest - rest0) : 0.0f;
-      if (msg && in) lg += (double)lgamma_from_ge1(z, lxs);   // alpha >= 1 (Eq. 6)
-      if (k < Mp) {
-        sE[k] = in ? ps : 0.0f;
-        if constexpr (kBF16) {
-          const uint16_t h = f2bf(w);
-          wh[row + k] = h;
-          w = bf2f(h);
-        } else {
-          wout[row + k] = w;
-        }
-      }
-#pragma unroll
-      for (int jt = 0; jt < kMaxTail; ++jt)
-        if (jt < Ft) tacc[jt] = fmaf(tw[jt][u], w, tacc[jt]);
-    }
-  }
-  lds_order();
+// The tail bins' R and V ln Lambda, Eq. 8 up to a per-frame constant, and the
+// frame's bound contribution.
+template <bool kBF16>
+__device__ __forceinline__ void update_finish(const JobDesc &J, int t, int lane, const float *sE, bool msg, int it,
+                                              const float (&tacc)[kMaxTail], const float (&vt)[kMaxTail], double lg,
+                                              const Shift8 &z0, const UpdPre &u) {
+  const int S = J.S, N = J.N, K = J.K, T = J.T, Fp = J.Fp, Fm = J.Fm, Ft = J.Ft, nsl = J.nsl;
+  const float gamma = J.gamma;
+  gfloat2 *vll = gptr(J.vll), *elbo = gptr(J.elbo);
+  gfloat *Rout = gptr(J.R), *phi = gptr(J.phi), *ev = gptr(J.ev), *sh = gptr(J.sh);
+  gu16 *Rh = gptr(J.Rh);
+  const bool live = lane < N;
 
   // ---- tail bins of the next contraction: R = V / Lambda, and their V ln Lambda
   Comp vl = comp_zero();
-  for (int jt = 0; jt < Ft; ++jt) {
-    const float lam = wave_sum(tacc[jt]);
-    const int l = Fm + jt;
-    const float v = Vin[(size_t)t * Fp + l];
-    const float rr = v > 0.0f ? v / lam : 0.0f;
-    if (v > 0.0f) comp_add(vl, v * ln_pos(lam));
-    if (lane == 0) {
-      if constexpr (kBF16) Rh[(size_t)t * Fp + l] = f2bf(rr);
-      else Rout[(size_t)t * Fp + l] = rr;
+#pragma unroll
+  for (int jt = 0; jt < kMaxTail; ++jt) {
+    if (jt < Ft) {
+      const float lam = wave_sum(tacc[jt]);
+      const int l = Fm + jt;
+      const float v = vt[jt];
+      const float rr = v > 0.0f ? v / lam : 0.0f;
+      if (v > 0.0f) comp_add(vl, v * ln_pos(lam));
+      if (lane == 0) {
+        if constexpr (kBF16) Rh[(size_t)t * Fp + l] = f2bf(rr);
+        else Rout[(size_t)t * Fp + l] = rr;
+      }
     }
   }
 
@@ -1367,17 +1365,315 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
     Comp tot;
     tot.hi = (float)lg;
     tot.lo = (float)(lg - (double)tot.hi);
-    tot = comp_merge(tot, wave_comp(pv));
+    tot = comp_merge(tot, wave_comp(u.pv));
     comp_add(tot, -lgamma_from_ge1(z0, fast_ln(z0.xs)));
-    tot = comp_merge(tot, chain);
-    comp_add(tot, vtail.x);
-    comp_add(tot, vtail.y);
+    tot = comp_merge(tot, u.chain);
+    comp_add(tot, u.vtail.x);
+    comp_add(tot, u.vtail.y);
     if (lane == 0) elbo[(size_t)it * T + t] = vf2{tot.hi, tot.lo};
   }
   if (lane == 0 && Ft > 0) vll[(size_t)nsl * T + t] = vf2{vl.hi, vl.lo};
 }
 
-__global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round, int stride) {
+__device__ __forceinline__ double wave_sum_f64(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Streamed form: any Mp, any mode.
+template <bool kBF16>
+__device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, float *sE, int mode, int round) {
+  const int S = J.S, N = J.N, K = J.K, M = J.M, Mp = J.Mp, T = J.T, Fp = J.Fp;
+  const int Fm = J.Fm, Ft = J.Ft;
+  const int it = round - J.start_round, iters = J.iters;
+  const float gamma = J.gamma;
+  const gfloat *c = gptr(J.c), *alpha_init = gptr(J.alpha_init), *Vin = gptr(J.V);
+  const gfloat *Wfm = gptr(J.Wfm);
+  const gu16 *Wfm_h = gptr(J.Wfm_h);
+  gfloat *alpha = gptr(J.alpha), *wout = gptr(J.w);
+  gu16 *wh = gptr(J.wh);
+
+  float *sD = sE + Mp;
+  const size_t row = (size_t)t * Mp;
+  const bool msg = mode == kUpdMessages;
+  const bool store_alpha = msg ? (it == iters - 1) : (iters == 0);
+  const UpdPre u = update_prelude(J, t, lane, sD, msg);
+
+  // ---- Eq. 6; element k belongs to state g = k / K (kept incrementally).  Loads
+  //      past the end read the last element (in bounds) and are not used.
+  // alpha_0: per-lane sums in double, then a butterfly over the lanes, which
+  // leaves the same value in every lane.  Every term is a float >= 1 and the sum
+  // stays far below 2^53 ulps of the smallest, so the double sum is exact and
+  // does not depend on the order.  Sub-chunks of 64 elements past Mp are skipped
+  // (a uniform test).
+  double asum = 0.0;
+  {
+    const int step_g = 64 / K, step_r = 64 % K;
+    int g = lane / K, r = lane - (lane / K) * K;
+    const bool from_alpha = mode == kUpdFromAlpha;
+    for (int base = 0; base < Mp; base += 64 * kUpdU) {
+      float cv[kUpdU];
+#pragma unroll
+      for (int u = 0; u < kUpdU; ++u) {
+        if (base + 64 * u >= Mp) break;
+        const int k = min(base + 64 * u + lane, M - 1);
+        cv[u] = from_alpha ? alpha_init[(size_t)t * M + k] : c[row + k];
+      }
+#pragma unroll
+      for (int u = 0; u < kUpdU; ++u) {
+        if (base + 64 * u >= Mp) break;
+        const int k = base + 64 * u + lane;
+        float a = from_alpha ? cv[u] : cv[u] + gamma * sD[min(g, S * N - 1)] + 1.0f;
+        a = k < M ? a : 0.0f;
+        asum += (double)a;
+        if (store_alpha && k < M) alpha[row + k] = a;
+        if (k < Mp) sE[k] = a;   // Mp is a multiple of 32: the last sub-chunk may be half full
+        g += step_g;
+        r += step_r;
+        if (r >= K) { r -= K; ++g; }
+      }
+    }
+  }
+  asum = wave_sum_f64(asum);
+  const float a0 = (float)asum;
+  const Shift8 z0 = shift8(a0);
+  const float rest0 = psi_rest(z0);
+  const float inv_xs0 = 1.0f / z0.xs;
+  lds_order();
+
+  // ---- w = exp(psi(alpha) - psi(alpha_0)) = (xs / xs0) exp(rest - rest0);
+  //      sE keeps psi(alpha_k) for Eq. 8; sum_k lnG(alpha_k) for the bound;
+  //      tail bins: Lambda[l][t] = sum_k beta[l][k] w_k for the next contraction
+  double lg = 0.0;
+  float tacc[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int base = 0; base < Mp; base += 64 * kUpdU) {
+    float tw[kMaxTail][kUpdU];
+#pragma unroll
+    for (int jt = 0; jt < kMaxTail; ++jt) {
+      if (jt < Ft) {
+#pragma unroll
+        for (int u = 0; u < kUpdU; ++u) {
+          if (base + 64 * u >= Mp) break;
+          const size_t o = (size_t)(Fm + jt) * Mp + min(base + 64 * u + lane, M - 1);
+          tw[jt][u] = kBF16 ? bf2f(Wfm_h[o]) : Wfm[o];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUpdU; ++u) {
+      if (base + 64 * u >= Mp) break;
+      const int k = base + 64 * u + lane;
+      const bool in = k < M;
+      ElemOut e = update_elem(in ? sE[k] : 1.0f, in, inv_xs0, rest0, msg, lg);
+      if (k < Mp) {
+        sE[k] = e.ps;
+        if constexpr (kBF16) {
+          const uint16_t h = f2bf(e.w);
+          wh[row + k] = h;
+          e.w = bf2f(h);
+        } else {
+          wout[row + k] = e.w;
+        }
+      }
+#pragma unroll
+      for (int jt = 0; jt < kMaxTail; ++jt)
+        if (jt < Ft) tacc[jt] = fmaf(tw[jt][u], e.w, tacc[jt]);
+    }
+  }
+  lds_order();
+  float vt[kMaxTail];
+#pragma unroll
+  for (int jt = 0; jt < kMaxTail; ++jt) vt[jt] = jt < Ft ? Vin[(size_t)t * Fp + Fm + jt] : 0.0f;
+  update_finish<kBF16>(J, t, lane, sE, msg, it, tacc, vt, lg, z0, u);
+}
+
+// Resident form: Mp <= kUpdResident, Ft <= 1, any mode.
+// Every load is issued unconditionally or under a lane mask, with no use inside
+// the masked region, so that the compiler places no wait before the last one.
+template <bool kBF16>
+__device__ __forceinline__ void update_frame_resident(const JobDesc &J, int t, int lane, float *sE, int mode,
+                                                      int round) {
+  const int S = J.S, N = J.N, K = J.K, M = J.M, Mp = J.Mp, T = J.T, Fp = J.Fp, Fm = J.Fm, Ft = J.Ft;
+  const int nsl = J.nsl;
+  const int it = round - J.start_round, iters = J.iters;
+  const float gamma = J.gamma;
+  const gfloat *c = gptr(J.c), *Vin = gptr(J.V), *Wfm = gptr(J.Wfm), *alpha_init = gptr(J.alpha_init);
+  const gfloat *post_in = gptr(J.post), *phi_in = gptr(J.phi), *sh_in = gptr(J.sh);
+  const gfloat2 *lnz = gptr(J.lnz), *clw = gptr(J.clw), *vll = gptr(J.vll);
+  const gu16 *Wfm_h = gptr(J.Wfm_h);
+  gfloat *alpha = gptr(J.alpha), *wout = gptr(J.w), *post = gptr(J.post);
+  gu16 *wh = gptr(J.wh);
+  float *sD = sE + Mp;
+  const size_t row = (size_t)t * Mp;
+  const bool msg = mode == kUpdMessages, from_alpha = mode == kUpdFromAlpha;
+  const bool store_alpha = msg ? (it == iters - 1) : (iters == 0);
+  const bool live = lane < N;
+  const int k0 = 4 * lane;
+
+  // ---- every load first: the row of c and the tail bin's row of beta (chunks
+  //      past Mp read the row's last chunk and are masked out below), the tail
+  //      bin's count, and the frame's d-hat, chain terms and bound partials
+  vf4 cv[4];
+  vf4 twf[4];
+  vu2 twh[4];
+  const size_t trow = (size_t)(Ft > 0 ? Fm : 0) * Mp;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int kk = min(256 * j + k0, Mp - 4);
+    if (from_alpha) {   // [T][M] rows: not 16-byte aligned in general
+#pragma unroll
+      for (int e = 0; e < 4; ++e) cv[j][e] = alpha_init[(size_t)t * M + min(256 * j + k0 + e, M - 1)];
+    } else {
+      cv[j] = *(const gfloat4 *)(c + row + kk);
+    }
+    if constexpr (kBF16) twh[j] = *(const guint2 *)(Wfm_h + trow + kk);
+    else twf[j] = *(const gfloat4 *)(Wfm + trow + kk);
+  }
+  const float vt0 = Vin[(size_t)t * Fp + (Ft > 0 ? Fm : 0)];
+  // (source, state) pair i = s N + n in lane i % 64 of slot i / 64; two slots
+  // cover S N <= 128 and are loaded here, any others in a loop below
+  const int SN = S * N;
+  float dq[2] = {0.0f, 0.0f}, fq[2] = {0.0f, 0.0f}, shl = 0.0f;
+  vf2 vtail = vf2{0.0f, 0.0f}, pv_sl = vf2{0.0f, 0.0f}, pv_kt = vf2{0.0f, 0.0f}, z_s = vf2{0.0f, 0.0f};
+  const int nkt = (Mp + kCntBM - 1) / kCntBM;   // <= 64 here
+  if (msg) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = min(lane + 64 * q, SN - 1), s = i / N, n = i - s * N;
+      dq[q] = post_in[((size_t)s * T + t) * N + n];
+      fq[q] = phi_in[((size_t)s * T + t) * 64 + n];
+    }
+    shl = sh_in[(size_t)min(lane, S - 1) * T + t];
+    // clamped, unconditional loads, masked after use-free: a load under a lane
+    // mask whose result needs a copy makes the compiler wait inside the mask
+    vtail = vll[(size_t)(Ft > 0 ? nsl : 0) * T + t];
+    pv_sl = vll[(size_t)min(lane, nsl - 1) * T + t];
+    pv_kt = clw[(size_t)min(lane, nkt - 1) * T + t];
+    z_s = lnz[min(lane, S - 1)];
+  }
+
+  // ---- d-hat into LDS (uniform start: 1/N, which is also the posterior output)
+  Comp chain = comp_zero(), pv = comp_zero();
+  if (msg) {
+    Comp cc = comp_zero();
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (lane + 64 * q < SN) {
+        sD[lane + 64 * q] = dq[q];
+        comp_add(cc, -dq[q] * fq[q]);
+      }
+    }
+    for (int i = lane + 128; i < SN; i += 64) {   // more than 128 (source, state) pairs
+      const int s = i / N, n = i - s * N;
+      const float dv = post_in[((size_t)s * T + t) * N + n];
+      sD[i] = dv;
+      comp_add(cc, -dv * phi_in[((size_t)s * T + t) * 64 + n]);
+    }
+    if (lane < S) comp_add(cc, shl);
+    chain = wave_comp(cc);
+    Comp d;
+    d.hi = lane < nsl ? pv_sl.x : 0.0f; d.lo = lane < nsl ? pv_sl.y : 0.0f; pv = comp_merge(pv, d);
+    d.hi = lane < nkt ? pv_kt.x : 0.0f; d.lo = lane < nkt ? pv_kt.y : 0.0f; pv = comp_merge(pv, d);
+    for (int r = lane + 64; r < nsl; r += 64) {   // only for more than 4096 bins
+      const vf2 v = vll[(size_t)r * T + t];
+      d.hi = v.x; d.lo = v.y;
+      pv = comp_merge(pv, d);
+    }
+    if (t == 0) {
+      for (int s = 0; s < S; ++s) {
+        const float zx = __shfl(z_s.x, s), zy = __shfl(z_s.y, s);
+        comp_add(chain, zx);
+        comp_add(chain, zy);
+      }
+    }
+  } else {
+    for (int i = lane; i < S * N; i += 64) sD[i] = 1.0f / (float)N;
+  }
+  lds_order();
+
+  // ---- Eq. 6 in registers; alpha_0 as the exact double sum
+  const int step_g = 256 / K, step_r = 256 % K;
+  int g0 = k0 / K, r0 = k0 - (k0 / K) * K;   // state and position of element 256 j + k0
+  double asum = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int g = g0, r = r0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int k = 256 * j + k0 + e;
+      float a = from_alpha ? cv[j][e] : cv[j][e] + gamma * sD[min(g, S * N - 1)] + 1.0f;
+      a = k < M ? a : 0.0f;
+      cv[j][e] = a;
+      asum += (double)a;
+      if (++r == K) { r = 0; ++g; }
+    }
+    g0 += step_g;
+    r0 += step_r;
+    if (r0 >= K) { r0 -= K; ++g0; }
+  }
+  asum = wave_sum_f64(asum);
+  const float a0 = (float)asum;
+  const Shift8 z0 = shift8(a0);
+  const float rest0 = psi_rest(z0);
+  const float inv_xs0 = 1.0f / z0.xs;
+
+  // ---- w, psi, lnG, and the stores (no global load follows them)
+  if (!msg) {
+    for (int i = lane; i < S * N; i += 64) post[((size_t)(i / N) * T + t) * N + (i % N)] = 1.0f / (float)N;
+  }
+  double lg = 0.0;
+  float tacc[kMaxTail] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int kj = 256 * j + k0;
+    vf4 tw;
+    if constexpr (kBF16)
+      tw = vf4{__uint_as_float(twh[j].x << 16), __uint_as_float(twh[j].x & 0xffff0000u),
+               __uint_as_float(twh[j].y << 16), __uint_as_float(twh[j].y & 0xffff0000u)};
+    else
+      tw = twf[j];
+    vf4 ps, wv;
+    uint32_t hw[2] = {0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      ElemOut o = update_elem(cv[j][e], kj + e < M, inv_xs0, rest0, msg, lg);
+      if constexpr (kBF16) {
+        const uint16_t h = f2bf(o.w);
+        hw[e >> 1] |= (uint32_t)h << (16 * (e & 1));
+        o.w = bf2f(h);
+      }
+      wv[e] = o.w;
+      ps[e] = o.ps;
+      tacc[0] = fmaf(tw[e], o.w, tacc[0]);
+    }
+    if (kj < Mp) {
+      *(vf4 *)(sE + kj) = ps;
+      if (store_alpha) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (kj + e < M) alpha[row + kj + e] = cv[j][e];
+      }
+      if constexpr (kBF16) *(guint2 *)(wh + row + kj) = vu2{hw[0], hw[1]};
+      else *(gfloat4 *)(wout + row + kj) = wv;
+    }
+    // one chunk of four elements at a time: the sums are pinned here, else the
+    // compiler sinks their additions to the end and holds all sixteen terms
+    __asm__ volatile("" : "+v"(lg), "+v"(tacc[0]));
+  }
+  lds_order();
+  UpdPre u;
+  u.vtail = Ft > 0 ? vtail : vf2{0.0f, 0.0f};
+  u.pv = pv;
+  u.chain = chain;
+  const float vt[kMaxTail] = {vt0, 0.0f, 0.0f, 0.0f};
+  update_finish<kBF16>(J, t, lane, sE, msg, it, tacc, vt, lg, z0, u);
+}
+
+// Five wavefronts per SIMD: the resident form needs 98 registers, which would
+// allow four; held to 96 it spills a few values once per frame.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_update(WorkList wl, int mode,
+                                                                                         int round, int stride) {
   extern __shared__ float smem[];   // per wave: [Mp] alpha, then psi(alpha); then [S N] d-hat
   const int b = blockIdx.x;
   const int jb = find_job(wl.start, wl.njobs, b);
@@ -1388,8 +1684,14 @@ __global__ __launch_bounds__(256) void k_update(WorkList wl, int mode, int round
   const bool bf16 = J.bf16;
   if (t >= J.T) return;
   float *sE = smem + (size_t)wave * stride;
-  if (bf16) update_frame<true>(J, t, lane, sE, mode, round);
-  else update_frame<false>(J, t, lane, sE, mode, round);
+  const bool resident = J.Mp <= kUpdResident && J.Ft <= 1;
+  if (resident) {
+    if (bf16) update_frame_resident<true>(J, t, lane, sE, mode, round);
+    else update_frame_resident<false>(J, t, lane, sE, mode, round);
+  } else {
+    if (bf16) update_frame<true>(J, t, lane, sE, mode, round);
+    else update_frame<false>(J, t, lane, sE, mode, round);
+  }
 }
 
 // ------------------------------------------------------------------ Section 4
@@ -1542,6 +1844,14 @@ hipError_t launch_pack(const JobDesc &J, hipStream_t st) {
 hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st) {
   k_fill_w_ones<<<256, 256, 0, st>>>(J);
   if (J.Ft > 0) k_tail_ones<<<J.T, 64, 0, st>>>(J);
+  return last();
+}
+
+hipError_t launch_begin(const WorkList &pack, const WorkList &trans, const WorkList &tail, hipStream_t st) {
+  if (pack.njobs > 0) k_status_clear<<<1, 256, 0, st>>>(pack);
+  if (pack.total > 0) k_begin_pack<<<pack.total, 256, 0, st>>>(pack);
+  if (trans.total > 0) k_begin_transpose<<<trans.total, 256, 0, st>>>(trans);
+  if (tail.total > 0) k_begin_tail<<<tail.total, 64, 0, st>>>(tail);
   return last();
 }
 

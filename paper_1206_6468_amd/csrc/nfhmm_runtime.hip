@@ -379,7 +379,10 @@ void fill_desc(Job &j, float gamma) {
 // ------------------------------------------------------------------ work-list tables
 // One table describes a set of jobs for every launch of a round: the job
 // descriptors and, per launch kind, the prefix sums of blocks per job.
-enum ListKind { kSpecF, kSpecH, kCntF, kCntH, kFBR, kFB, kPost, kChain, kUpd, kFrames, kRecon, kIters, kNumLists };
+enum ListKind {
+  kSpecF, kSpecH, kCntF, kCntH, kFBR, kFB, kPost, kChain, kUpd, kFrames, kRecon, kIters,
+  kBegin, kTrans, kTail, kNumLists
+};
 
 struct Table {
   WorkList lists[kNumLists];
@@ -430,6 +433,9 @@ int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb, bool spec_sm
     case kFrames: return D.T;
     case kRecon: return D.S * D.nlt * ct;
     case kIters: return D.iters;
+    case kBegin: return D.T + D.Mp + (D.alpha_init ? 0 : kBeginFillBlocks);
+    case kTrans: return (D.Mp / 32) * (D.Fp / 32);
+    case kTail: return (D.alpha_init || D.Ft == 0) ? 0 : D.T;
     default: return 0;
   }
 }
@@ -817,13 +823,16 @@ void deliver_staged(nfhmm_ctx *ctx, Job &j) {
 // Start jobs: pack inputs, then the default start (or the warm start).
 nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st) {
   if (jobs.empty()) return NFHMM_OK;
-  std::vector<Job *> uni, warm;
-  for (Job *j : jobs) {
-    HIP_OK(hipMemsetAsync(j->desc.status, 0, 4, st));
-    HIP_OK(launch_pack(j->desc, st));
-    if (j->desc.alpha_init) warm.push_back(j);
-    else { uni.push_back(j); HIP_OK(launch_fill_w_ones(j->desc, st)); }
+  {
+    // packing of every job in three launches (one per step), not five per job
+    Table *t;
+    TableLease lease;
+    nfhmm_status s = get_table(ctx, jobs, st, &t, lease);
+    if (s != NFHMM_OK) return s;
+    HIP_OK(launch_begin(t->lists[kBegin], t->lists[kTrans], t->lists[kTail], st));
   }
+  std::vector<Job *> uni, warm;
+  for (Job *j : jobs) (j->desc.alpha_init ? warm : uni).push_back(j);
   if (!uni.empty()) {
     Table *t;
     TableLease lease;
