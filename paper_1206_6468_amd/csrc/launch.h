@@ -19,15 +19,18 @@ struct OneJobTable {
 };
 hipError_t launch_put_table(const OneJobTable &img, void *dst, hipStream_t st);
 
-hipError_t launch_pack(const JobDesc &J, hipStream_t st);
-hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st);
 // Every job of a work list starting together: clear the status words, pack V and
-// the dictionary (and set w = 1 for a default start), transpose the dictionary,
-// then the default start's tail bins.  Blocks per job: pack T + Mp (+
-// kBeginFillBlocks for a default start), trans (Mp / 32) (Fp / 32), tail T for a
-// default start with tail bins, else 0.
+// the dictionary (and set w = 1 for a default start), transpose the dictionary.
+// Blocks per job: pack T + Mp (+ kBeginFillBlocks for a default start), trans
+// (Mp / 32) (Fp / 32).
 constexpr int kBeginFillBlocks = 32;
-hipError_t launch_begin(const WorkList &pack, const WorkList &trans, const WorkList &tail, hipStream_t st);
+hipError_t launch_begin(const WorkList &pack, const WorkList &trans, hipStream_t st);
+// R = V / Lambda of a default start, where Lambda = beta 1 is one value per bin:
+// lam has ceil(F / 16) blocks per default-start job, ratio T (0 for warm starts).
+constexpr int kStartLamBinsPerBlock = 16;
+hipError_t launch_start_ratio(const WorkList &lam, const WorkList &ratio, hipStream_t st);
+// dst[i] = the status word of job i of wl (device memory, wl.njobs ints)
+hipError_t launch_status_gather(const WorkList &wl, int *dst, hipStream_t st);
 // small: 64 x 64 block tiles (work lists built with kSpecSmallBM / BN) instead of
 // kSpecBM x kSpecBN
 hipError_t launch_spectrum(const WorkList &wl, bool bf16, bool small, hipStream_t st);

@@ -50,9 +50,9 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------------ packing
-// Each packing step is a block body taking its block index, so that it runs as
-// a per-job kernel (the allocation-free single-job path) or over a work list
-// that covers every job starting together (one launch per step).
+// Each packing step is a block body taking its block index; the kernels below
+// run it over a work list that covers every job starting together (one launch
+// per step; the allocation-free path builds a one-job list).
 
 // V_in [T][F] -> V [T][Fp]; checks V finite and >= 0.
 __device__ __forceinline__ void pack_v_row(const JobDesc &J, int t) {
@@ -117,37 +117,16 @@ __device__ __forceinline__ void fill_w_ones_part(const JobDesc &J, int b, int nb
   }
 }
 
-// Tail bins for the default start (w = 1): Lambda[l][t] = sum_k beta[l][k], R = V / Lambda.
-// One 64-lane block per frame.
-__device__ __forceinline__ void tail_ones_frame(const JobDesc &J, int t) {
-  const int lane = threadIdx.x;
-  for (int jt = 0; jt < J.Ft; ++jt) {
-    const int l = J.Fm + jt;
-    float acc = 0.0f;
-    for (int k = lane; k < J.M; k += 64)
-      acc += J.bf16 ? bf2f(J.Wfm_h[(size_t)l * J.Mp + k]) : J.Wfm[(size_t)l * J.Mp + k];
-    const float lam = wave_sum(acc);
-    if (lane == 0) {
-      const float v = J.V[(size_t)t * J.Fp + l];
-      const float rr = v > 0.0f ? v / lam : 0.0f;
-      if (J.bf16) J.Rh[(size_t)t * J.Fp + l] = f2bf(rr);
-      else J.R[(size_t)t * J.Fp + l] = rr;
-    }
-  }
-}
-
-__global__ void k_pack_v(JobDesc J) { pack_v_row(J, blockIdx.x); }
-__global__ void k_pack_wmf(JobDesc J) { pack_wmf_row(J, blockIdx.x); }
-__global__ void k_transpose_w(JobDesc J) { transpose_tile(J, blockIdx.x, blockIdx.y); }
-__global__ void k_fill_w_ones(JobDesc J) { fill_w_ones_part(J, blockIdx.x, gridDim.x); }
-__global__ void k_tail_ones(JobDesc J) { tail_ones_frame(J, blockIdx.x); }
-
 // Batched forms over a work list.  Per job, k_begin_pack has T blocks packing V,
 // then Mp packing the dictionary, then (default start only) kBeginFillBlocks
-// setting w = 1; k_begin_transpose one block per 32 x 32 tile; k_begin_tail one
-// 64-lane block per frame (default start with tail bins only).
+// setting w = 1; k_begin_transpose one block per 32 x 32 tile.
 __global__ void k_status_clear(WorkList wl) {
   for (int i = threadIdx.x; i < wl.njobs; i += blockDim.x) *wl.jobs[i].status = 0;
+}
+
+// dst[i] = status word of job i of the list
+__global__ void k_status_gather(WorkList wl, int *dst) {
+  for (int i = threadIdx.x; i < wl.njobs; i += blockDim.x) dst[i] = *wl.jobs[i].status;
 }
 
 __global__ __launch_bounds__(256) void k_begin_pack(WorkList wl) {
@@ -168,10 +147,42 @@ __global__ __launch_bounds__(256) void k_begin_transpose(WorkList wl) {
   transpose_tile(J, local % nx, local / nx);
 }
 
-__global__ __launch_bounds__(64) void k_begin_tail(WorkList wl) {
+// The default start (w = 1, Section 3.2's first iteration from a flat alpha-hat):
+// Lambda = beta 1 is the same in every frame, the row sum of each bin's
+// dictionary values, so the start forms it once per job (k_start_lambda: 16 bins
+// per block, into the job's sep buffer, free until the separation) and then R =
+// V / Lambda per frame (k_start_ratio), as the spectrum kernel's epilogue and
+// the tail-bin path would.
+__global__ __launch_bounds__(256) void k_start_lambda(WorkList wl) {
   const int b = blockIdx.x;
   const int jb = find_job(wl.start, wl.njobs, b);
-  tail_ones_frame(wl.jobs[jb], b - wl.start[jb]);
+  const JobDesc &J = wl.jobs[jb];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l0 = (b - wl.start[jb]) * kStartLamBinsPerBlock + wave * (kStartLamBinsPerBlock / 4);
+  for (int i = 0; i < kStartLamBinsPerBlock / 4; ++i) {
+    const int l = l0 + i;
+    if (l >= J.F) break;   // uniform over the wave
+    float acc = 0.0f;
+    for (int k = lane; k < J.M; k += 64)
+      acc += J.bf16 ? bf2f(J.Wfm_h[(size_t)l * J.Mp + k]) : J.Wfm[(size_t)l * J.Mp + k];
+    const float lam = wave_sum(acc);
+    if (lane == 0) J.sep[l] = lam;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_start_ratio(WorkList wl) {
+  const int b = blockIdx.x;
+  const int jb = find_job(wl.start, wl.njobs, b);
+  const JobDesc &J = wl.jobs[jb];
+  const int t = b - wl.start[jb];
+  // every bin of the padded row: the contraction reads [0, Fm), which for a
+  // ragged F without tail bins runs past F (V = 0 there, so R = 0)
+  for (int l = threadIdx.x; l < J.Fp; l += blockDim.x) {
+    const float v = J.V[(size_t)t * J.Fp + l], lam = l < J.F ? J.sep[l] : 1.0f;
+    const float rr = v > 0.0f ? (l < J.Fm ? v * fast_rcp(lam) : v / lam) : 0.0f;
+    if (J.bf16) J.Rh[(size_t)t * J.Fp + l] = f2bf(rr);
+    else J.R[(size_t)t * J.Fp + l] = rr;
+  }
 }
 
 // ------------------------------------------------------------------ MFMA tiles
@@ -179,8 +190,8 @@ __global__ __launch_bounds__(64) void k_begin_tail(WorkList wl) {
 // = 4 waves in a 2x2 grid, each wave (16*WM) x (16*WN) = WM x WN MFMA 16x16 tiles
 // held in accumulator registers.  Operand k-slices pass through LDS: loaded
 // straight into it for the two contractions of every iteration (below,
-// gemm_nt_f32_dma / gemm_nt_bf16_dma), through registers with padded rows for the
-// once-per-job reconstruction, whose k range is arbitrary.  A larger wave tile
+// gemm_nt_f32_dma / gemm_nt_bf16_dma), and for the once-per-job reconstruction,
+// whose k range is arbitrary, with its ragged stages masked in LDS.  A larger wave tile
 // reuses every fragment read from LDS across more MFMAs.  Within every 16 (f32)
 // or 32 (bf16) wide k-chunk lane (r, q) of a fragment supplies the q-th group of
 // consecutive k; A and B use the same grouping, so every k is summed once.
@@ -196,104 +207,8 @@ __device__ __forceinline__ Frag frag_of(int tid) {
   return f;
 }
 
-constexpr int kBKf = 32, kLdsF = kBKf + 4;          // f32: 32 k per stage, rows padded
+constexpr int kBKf = 32;                            // f32: 32 k per stage
 constexpr int kBKh = 64;                            // bf16: 64 k per stage
-
-// ROWS x 32 floats: thread tid loads rows (tid/8) + 32h, float4 column (tid%8)
-template <int ROWS, bool kMasked>
-__device__ __forceinline__ void gload_f32(const float *__restrict__ src, int ld, int nrows, int row0, int k,
-                                          int kb, int ke, int tid, float4 (&r)[ROWS / 32]) {
-  const int rr = tid >> 3, c = (tid & 7) * 4;
-#pragma unroll
-  for (int h = 0; h < ROWS / 32; ++h) {
-    const int row = row0 + rr + 32 * h, kk = k + c;
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (kMasked) {   // k-range [kb, ke) with kb, ke arbitrary: elementwise mask
-      if (row < nrows && kk + 3 >= kb && kk < ke) {
-        v = *(const float4 *)(src + (size_t)row * ld + kk);
-        if (kk + 0 < kb || kk + 0 >= ke) v.x = 0.f;
-        if (kk + 1 < kb || kk + 1 >= ke) v.y = 0.f;
-        if (kk + 2 < kb || kk + 2 >= ke) v.z = 0.f;
-        if (kk + 3 < kb || kk + 3 >= ke) v.w = 0.f;
-      }
-    } else if (row < nrows && kk < ke) {
-      v = *(const float4 *)(src + (size_t)row * ld + kk);
-    }
-    r[h] = v;
-  }
-}
-
-template <int ROWS>
-__device__ __forceinline__ void sstore_f32(float *lds, int tid, const float4 (&r)[ROWS / 32]) {
-  const int rr = tid >> 3, c = (tid & 7) * 4;
-#pragma unroll
-  for (int h = 0; h < ROWS / 32; ++h) *(float4 *)(lds + (rr + 32 * h) * kLdsF + c) = r[h];
-}
-
-template <int WM, int WN>
-__device__ __forceinline__ void mma_stage_f32(const float *As, const float *Bs, const Frag &f,
-                                              floatx4 (&acc)[WM][WN]) {
-#pragma unroll
-  for (int kk = 0; kk < kBKf; kk += 16) {
-    float4 a[WM], b[WN];
-#pragma unroll
-    for (int i = 0; i < WM; ++i)
-      a[i] = *(const float4 *)(As + (f.wr * 16 * WM + i * 16 + f.lr) * kLdsF + kk + f.lq * 4);
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-      b[j] = *(const float4 *)(Bs + (f.wc * 16 * WN + j * 16 + f.lr) * kLdsF + kk + f.lq * 4);
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-          const float av = p == 0 ? a[i].x : p == 1 ? a[i].y : p == 2 ? a[i].z : a[i].w;
-          const float bv = p == 0 ? b[j].x : p == 1 ? b[j].y : p == 2 ? b[j].z : b[j].w;
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[i][j], 0, 0, 0);
-        }
-  }
-}
-
-// f32 main loop over k in [kb, ke) through registers (the reconstruction: its k
-// range is one job's elements, in any position); kMasked selects the elementwise
-// k mask
-template <int WM, int WN, bool kMasked>
-__device__ void gemm_nt_f32(const float *__restrict__ A, int lda, int arows, int row0, const float *__restrict__ B,
-                            int ldb, int bcols, int col0, int kb, int ke, floatx4 (&acc)[WM][WN]) {
-  constexpr int BM = 32 * WM, BN = 32 * WN;
-  __shared__ float As[2][BM * kLdsF];
-  __shared__ float Bs[2][BN * kLdsF];
-  const int tid = threadIdx.x;
-  const Frag f = frag_of(tid);
-#pragma unroll
-  for (int i = 0; i < WM; ++i)
-#pragma unroll
-    for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int k0 = kMasked ? (kb & ~3) : kb;
-  float4 ra[BM / 32], rb[BN / 32];
-  gload_f32<BM, kMasked>(A, lda, arows, row0, k0, kb, ke, tid, ra);
-  gload_f32<BN, kMasked>(B, ldb, bcols, col0, k0, kb, ke, tid, rb);
-  sstore_f32<BM>(As[0], tid, ra);
-  sstore_f32<BN>(Bs[0], tid, rb);
-  __syncthreads();
-  int buf = 0;
-  for (int k = k0; k < ke; k += kBKf) {
-    const int kn = k + kBKf;
-    const bool more = kn < ke;
-    if (more) {
-      gload_f32<BM, kMasked>(A, lda, arows, row0, kn, kb, ke, tid, ra);
-      gload_f32<BN, kMasked>(B, ldb, bcols, col0, kn, kb, ke, tid, rb);
-    }
-    mma_stage_f32<WM, WN>(As[buf], Bs[buf], f, acc);
-    if (more) {
-      sstore_f32<BM>(As[buf ^ 1], tid, ra);
-      sstore_f32<BN>(Bs[buf ^ 1], tid, rb);
-    }
-    __syncthreads();
-    buf ^= 1;
-  }
-}
 
 // f32 main loop with the operands loaded straight into LDS (global_load_lds,
 // 16 bytes per lane; no staging registers and no LDS store instructions).  A
@@ -385,6 +300,60 @@ __device__ void gemm_nt_f32_dma(const float *__restrict__ A, int lda, int arows,
     mma_stage_f32_dma<WM, WN>(As1, Bs1, f, acc);
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
+  }
+}
+
+// The same for a k range [kb, ke) in any position (the reconstruction: one
+// source's elements): whole stages of 32 from kb rounded down to ke rounded up
+// (within the padded rows), loaded straight into LDS as above; in the first and
+// last stage the B entries outside [kb, ke) are set to zero in LDS, between two
+// barriers, before their MFMAs.
+template <int BN>
+__device__ __forceinline__ void mask_stage_b(float *Bs, int ks, int kb, int ke, int tid) {
+  if (ks >= kb && ks + kBKf <= ke) return;   // uniform over the block
+  for (int idx = tid; idx < BN * kDmaRow; idx += blockDim.x) {
+    const int r = idx / kDmaRow, kl = idx - r * kDmaRow, k = ks + kl;
+    if (k < kb || k >= ke) Bs[r * kDmaRow + (((kl >> 2) ^ (r & 7)) << 2) + (kl & 3)] = 0.0f;
+  }
+  __syncthreads();
+}
+
+template <int WM, int WN>
+__device__ void gemm_nt_f32_dma_kmask(const float *__restrict__ A, int lda, int arows, int row0,
+                                      const float *__restrict__ B, int ldb, int bcols, int col0, int kb, int ke,
+                                      floatx4 (&acc)[WM][WN]) {
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  __shared__ __attribute__((aligned(16))) float As0[BM * kDmaRow], As1[BM * kDmaRow];
+  __shared__ __attribute__((aligned(16))) float Bs0[BN * kDmaRow], Bs1[BN * kDmaRow];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const Frag f = frag_of(tid);
+#pragma unroll
+  for (int i = 0; i < WM; ++i)
+#pragma unroll
+    for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int k0 = kb & ~(kBKf - 1), k1 = (ke + kBKf - 1) & ~(kBKf - 1);
+  dma_rows<BM>(A, lda, arows, row0, k0, As0, wave, lane);
+  dma_rows<BN>(B, ldb, bcols, col0, k0, Bs0, wave, lane);
+  __syncthreads();
+  mask_stage_b<BN>(Bs0, k0, kb, ke, tid);
+  for (int k = k0; k < k1; k += 2 * kBKf) {
+    if (k + kBKf < k1) {
+      dma_rows<BM>(A, lda, arows, row0, k + kBKf, As1, wave, lane);
+      dma_rows<BN>(B, ldb, bcols, col0, k + kBKf, Bs1, wave, lane);
+    }
+    mma_stage_f32_dma<WM, WN>(As0, Bs0, f, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    if (k + kBKf >= k1) break;
+    mask_stage_b<BN>(Bs1, k + kBKf, kb, ke, tid);
+    if (k + 2 * kBKf < k1) {
+      dma_rows<BM>(A, lda, arows, row0, k + 2 * kBKf, As0, wave, lane);
+      dma_rows<BN>(B, ldb, bcols, col0, k + 2 * kBKf, Bs0, wave, lane);
+    }
+    mma_stage_f32_dma<WM, WN>(As1, Bs1, f, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();
+    if (k + 2 * kBKf < k1) mask_stage_b<BN>(Bs0, k + 2 * kBKf, kb, ke, tid);
   }
 }
 
@@ -1198,7 +1167,7 @@ __global__ __launch_bounds__(64) void k_chain_exact(WorkList wl) {
 // (Eq. 8, up to a per-frame constant) with its shifted exponential for the next
 // chain pass, and the Lambda rows of the tail bins.  alpha itself is stored only
 // when it is an output (the job's last iteration, or a start with no iterations):
-// it is c + gamma B'd + 1 and nothing else reads it.
+// it is c + gamma B'd + 1 and nothing else reads it but the reconstruction.
 //
 // Two forms of the element passes.  The streamed form (any size) walks the row
 // in chunks of 64 x kUpdU elements.  The resident form (rows of at most 1024
@@ -1427,7 +1396,6 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
         float a = from_alpha ? cv[u] : cv[u] + gamma * sD[min(g, S * N - 1)] + 1.0f;
         a = k < M ? a : 0.0f;
         asum += (double)a;
-        if (store_alpha && k < M) alpha[row + k] = a;
         if (k < Mp) sE[k] = a;   // Mp is a multiple of 32: the last sub-chunk may be half full
         g += step_g;
         r += step_r;
@@ -1465,7 +1433,9 @@ __device__ __forceinline__ void update_frame(const JobDesc &J, int t, int lane, 
       if (base + 64 * u >= Mp) break;
       const int k = base + 64 * u + lane;
       const bool in = k < M;
-      ElemOut e = update_elem(in ? sE[k] : 1.0f, in, inv_xs0, rest0, msg, lg);
+      const float a = in ? sE[k] : 1.0f;
+      ElemOut e = update_elem(a, in, inv_xs0, rest0, msg, lg);
+      if (store_alpha && in) alpha[row + k] = a;
       if (k < Mp) {
         sE[k] = e.ps;
         if constexpr (kBF16) {
@@ -1695,27 +1665,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 }
 
 // ------------------------------------------------------------------ Section 4
-// E[theta_t] = alpha_t / alpha_t0 into the c buffer (one block per frame).
-__global__ __launch_bounds__(256) void k_theta(WorkList wl) {
-  __shared__ Comp red[4];
-  const int b = blockIdx.x;
-  const int jb = find_job(wl.start, wl.njobs, b);
-  const JobDesc &J = wl.jobs[jb];
-  const int t = b - wl.start[jb];
-  const size_t row = (size_t)t * J.Mp;
-  Comp s = comp_zero();
-  for (int k = threadIdx.x; k < J.M; k += 256) comp_add(s, J.alpha[row + k]);
-  s = wave_comp(s);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-  __syncthreads();
-  Comp a = red[0];
-  for (int w2 = 1; w2 < 4; ++w2) a = comp_merge(a, red[w2]);
-  const float inv = 1.0f / (a.hi + a.lo);
-  for (int k = threadIdx.x; k < J.Mp; k += 256) J.c[row + k] = k < J.M ? J.alpha[row + k] * inv : 0.0f;
-}
-
-// Vhat^(s) = beta_s E[theta]_s, rows l, columns t, k over source s's elements.
-// Work: per job S * nlt * ceil(T/64) tiles.
+// Vhat^(s) = beta_s E[theta]_s with E[theta_t] = alpha_t / alpha_t0 (Section 4),
+// computed as alpha_t0 Vhat^(s): the product with alpha-hat itself.  The common
+// factor alpha_t0 of a frame's column cancels in the ratio mask, the only use of
+// Vhat.  Rows l, columns t, k over source s's elements.  Work: per job S * nlt *
+// ceil(T/64) tiles.
 __global__ __launch_bounds__(256) void k_reconstruct(WorkList wl) {
   const int b = xcd_remap(blockIdx.x, wl.total);
   const int jb = find_job(wl.start, wl.njobs, b);
@@ -1729,7 +1683,7 @@ __global__ __launch_bounds__(256) void k_reconstruct(WorkList wl) {
   const int row0 = rt * 64, col0 = ct * 64;
   const int kb = s * J.NK, ke = kb + J.NK;
   floatx4 acc[2][2];
-  gemm_nt_f32<2, 2, true>(J.Wfm, J.Mp, J.Fp, row0, J.c, J.Mp, J.T, col0, kb, ke, acc);
+  gemm_nt_f32_dma_kmask<2, 2>(J.Wfm, J.Mp, J.Fp, row0, J.alpha, J.Mp, J.T, col0, kb, ke, acc);
   const Frag f = frag_of(threadIdx.x);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -1834,24 +1788,21 @@ hipError_t launch_put_table(const OneJobTable &img, void *dst, hipStream_t st) {
   return last();
 }
 
-hipError_t launch_pack(const JobDesc &J, hipStream_t st) {
-  k_pack_v<<<J.T, 256, 0, st>>>(J);
-  k_pack_wmf<<<J.Mp, 256, 0, st>>>(J);
-  k_transpose_w<<<dim3(J.Mp / 32, J.Fp / 32), 256, 0, st>>>(J);
+hipError_t launch_status_gather(const WorkList &wl, int *dst, hipStream_t st) {
+  if (wl.njobs > 0) k_status_gather<<<1, 256, 0, st>>>(wl, dst);
   return last();
 }
 
-hipError_t launch_fill_w_ones(const JobDesc &J, hipStream_t st) {
-  k_fill_w_ones<<<256, 256, 0, st>>>(J);
-  if (J.Ft > 0) k_tail_ones<<<J.T, 64, 0, st>>>(J);
-  return last();
-}
-
-hipError_t launch_begin(const WorkList &pack, const WorkList &trans, const WorkList &tail, hipStream_t st) {
+hipError_t launch_begin(const WorkList &pack, const WorkList &trans, hipStream_t st) {
   if (pack.njobs > 0) k_status_clear<<<1, 256, 0, st>>>(pack);
   if (pack.total > 0) k_begin_pack<<<pack.total, 256, 0, st>>>(pack);
   if (trans.total > 0) k_begin_transpose<<<trans.total, 256, 0, st>>>(trans);
-  if (tail.total > 0) k_begin_tail<<<tail.total, 64, 0, st>>>(tail);
+  return last();
+}
+
+hipError_t launch_start_ratio(const WorkList &lam, const WorkList &ratio, hipStream_t st) {
+  if (lam.total > 0) k_start_lambda<<<lam.total, 256, 0, st>>>(lam);
+  if (ratio.total > 0) k_start_ratio<<<ratio.total, 256, 0, st>>>(ratio);
   return last();
 }
 
@@ -1921,7 +1872,6 @@ hipError_t launch_update(const WorkList &wl, int mode, int round, int stride, hi
 }
 
 hipError_t launch_finish(const WorkList &frames, const WorkList &tiles, const WorkList &iters, hipStream_t st) {
-  if (frames.total > 0) k_theta<<<frames.total, 256, 0, st>>>(frames);
   if (tiles.total > 0) k_reconstruct<<<tiles.total, 256, 0, st>>>(tiles);
   if (frames.total > 0) k_mask_export<<<frames.total, 256, 0, st>>>(frames);
   if (iters.total > 0) k_elbo_reduce<<<iters.total, 256, 0, st>>>(iters);

@@ -381,7 +381,7 @@ void fill_desc(Job &j, float gamma) {
 // descriptors and, per launch kind, the prefix sums of blocks per job.
 enum ListKind {
   kSpecF, kSpecH, kCntF, kCntH, kFBR, kFB, kPost, kChain, kUpd, kFrames, kRecon, kIters,
-  kBegin, kTrans, kTail, kNumLists
+  kBegin, kTrans, kLam, kRatio, kNumLists
 };
 
 struct Table {
@@ -435,7 +435,8 @@ int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb, bool spec_sm
     case kIters: return D.iters;
     case kBegin: return D.T + D.Mp + (D.alpha_init ? 0 : kBeginFillBlocks);
     case kTrans: return (D.Mp / 32) * (D.Fp / 32);
-    case kTail: return (D.alpha_init || D.Ft == 0) ? 0 : D.T;
+    case kLam: return D.alpha_init ? 0 : (D.F + kStartLamBinsPerBlock - 1) / kStartLamBinsPerBlock;
+    case kRatio: return D.alpha_init ? 0 : D.T;
     default: return 0;
   }
 }
@@ -509,6 +510,10 @@ struct nfhmm_ctx {
   std::vector<hipEvent_t> event_pool;
   // pinned word for the no-alloc fit's status read-back (allocated at create)
   int *status_host = nullptr;
+  // status words of a blocking batch, gathered on the device and read back in
+  // one copy (instead of one synchronous copy per job)
+  int *status_dev = nullptr, *status_pin = nullptr;
+  int status_cap = 0;
 };
 
 namespace {
@@ -824,12 +829,14 @@ void deliver_staged(nfhmm_ctx *ctx, Job &j) {
 nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStream_t st) {
   if (jobs.empty()) return NFHMM_OK;
   {
-    // packing of every job in three launches (one per step), not five per job
+    // packing of every job in three launches (one per step), not five per job,
+    // then R of the default starts
     Table *t;
     TableLease lease;
     nfhmm_status s = get_table(ctx, jobs, st, &t, lease);
     if (s != NFHMM_OK) return s;
-    HIP_OK(launch_begin(t->lists[kBegin], t->lists[kTrans], t->lists[kTail], st));
+    HIP_OK(launch_begin(t->lists[kBegin], t->lists[kTrans], st));
+    HIP_OK(launch_start_ratio(t->lists[kLam], t->lists[kRatio], st));
   }
   std::vector<Job *> uni, warm;
   for (Job *j : jobs) (j->desc.alpha_init ? warm : uni).push_back(j);
@@ -838,8 +845,6 @@ nfhmm_status engine_begin(nfhmm_ctx *ctx, const std::vector<Job *> &jobs, hipStr
     TableLease lease;
     nfhmm_status s = get_table(ctx, uni, st, &t, lease);
     if (s != NFHMM_OK) return s;
-    HIP_OK(launch_spectrum(t->lists[kSpecF], false, true, st));
-    HIP_OK(launch_spectrum(t->lists[kSpecH], true, t->spec_small, st));
     HIP_OK(launch_counts(t->lists[kCntF], false, st));
     HIP_OK(launch_counts(t->lists[kCntH], true, st));
     HIP_OK(launch_update(t->lists[kUpd], kUpdUniform, 0, t->upd_stride, st));
@@ -973,6 +978,26 @@ nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t 
     HIP_OK(hipEventRecord(ctx->lanes[g].done, ctx->lanes[g].main));
     HIP_OK(hipStreamWaitEvent(st, ctx->lanes[g].done, 0));
   }
+  // every job's status word into one pinned array, read after the one
+  // synchronisation below
+  const int n = (int)jobs.size();
+  if (n > ctx->status_cap) {
+    if (ctx->status_dev) (void)hipFree(ctx->status_dev);
+    if (ctx->status_pin) (void)hipHostFree(ctx->status_pin);
+    ctx->status_dev = ctx->status_pin = nullptr;
+    ctx->status_cap = 0;
+    const int cap = (n + 255) / 256 * 256;
+    HIP_OK(hipMalloc((void **)&ctx->status_dev, (size_t)cap * 4));
+    HIP_OK(hipHostMalloc((void **)&ctx->status_pin, (size_t)cap * 4, hipHostMallocDefault));
+    ctx->status_cap = cap;
+  }
+  {
+    Table *t;
+    TableLease lease;
+    if ((s = get_table(ctx, jobs, st, &t, lease)) != NFHMM_OK) return s;
+    HIP_OK(launch_status_gather(t->lists[kBegin], ctx->status_dev, st));
+    HIP_OK(hipMemcpyAsync(ctx->status_pin, ctx->status_dev, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+  }
   // host outputs through the pinned ring, then the copy pool into the caller's
   // arrays; every region taken here is given back before returning
   nfhmm_status ds = NFHMM_OK;
@@ -991,9 +1016,9 @@ nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t 
   if (ds != NFHMM_OK) return ds;
   HIP_OK(se);
   nfhmm_status first = NFHMM_OK;
-  for (Job *j : jobs) {
-    int flag = 0;
-    HIP_OK(hipMemcpy(&flag, j->desc.status, 4, hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) {
+    Job *j = jobs[i];
+    const int flag = ctx->status_pin[i];
     if (flag & (kBadV | kBadW)) {
       j->status = NFHMM_E_INVALID;
       j->error = (flag & kBadV) ? "V has a negative or non-finite entry" : "a dictionary element is not normalised";
@@ -1271,6 +1296,8 @@ void nfhmm_destroy(nfhmm_ctx *ctx) {
     if (t.host) (void)hipHostFree(t.host);
   }
   if (ctx->status_host) (void)hipHostFree(ctx->status_host);
+  if (ctx->status_dev) (void)hipFree(ctx->status_dev);
+  if (ctx->status_pin) (void)hipHostFree(ctx->status_pin);
   (void)hipEventDestroy(ctx->ev_fork);
   (void)hipEventDestroy(ctx->ev_join);
   for (auto &ln : ctx->lanes) {
@@ -1428,13 +1455,11 @@ nfhmm_status nfhmm_fit_device_noalloc(nfhmm_ctx *ctx, const nfhmm_problem *dev_p
   }
   const int nmax = std::max(1, j.d.N);
   HIP_OK(launch_put_table(img, base, st));   // also clears the status word
-  HIP_OK(launch_pack(D, st));
+  HIP_OK(launch_begin(wl[kBegin], wl[kTrans], st));
   if (D.alpha_init) {
     HIP_OK(launch_update(wl[kUpd], kUpdFromAlpha, 0, stride, st));
   } else {
-    HIP_OK(launch_fill_w_ones(D, st));
-    HIP_OK(launch_spectrum(wl[kSpecF], false, true, st));
-    HIP_OK(launch_spectrum(wl[kSpecH], true, small, st));
+    HIP_OK(launch_start_ratio(wl[kLam], wl[kRatio], st));
     HIP_OK(launch_counts(wl[kCntF], false, st));
     HIP_OK(launch_counts(wl[kCntH], true, st));
     HIP_OK(launch_update(wl[kUpd], kUpdUniform, 0, stride, st));
