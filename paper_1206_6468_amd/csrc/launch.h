@@ -21,8 +21,8 @@ hipError_t launch_put_table(const OneJobTable &img, void *dst, hipStream_t st);
 
 // Every job of a work list starting together: clear the status words, pack V and
 // the dictionary (and set w = 1 for a default start), transpose the dictionary.
-// Blocks per job: pack T + Mp (+ kBeginFillBlocks for a default start), trans
-// (Mp / 32) (Fp / 32).
+// Blocks per job: pack ceil(T / 4) + Mp / 4 (+ kBeginFillBlocks for a default
+// start), trans (Mp / 32) (Fp / 32).
 constexpr int kBeginFillBlocks = 32;
 hipError_t launch_begin(const WorkList &pack, const WorkList &trans, hipStream_t st);
 // R = V / Lambda of a default start, where Lambda = beta 1 is one value per bin:

@@ -54,43 +54,38 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // run it over a work list that covers every job starting together (one launch
 // per step; the allocation-free path builds a one-job list).
 
-// V_in [T][F] -> V [T][Fp]; checks V finite and >= 0.
-__device__ __forceinline__ void pack_v_row(const JobDesc &J, int t) {
-  int bad = 0;
-  for (int l = threadIdx.x; l < J.Fp; l += blockDim.x) {
+// V_in [T][F] -> V [T][Fp]; checks V finite and >= 0.  One wavefront per row.
+__device__ __forceinline__ void pack_v_row(const JobDesc &J, int t, int lane) {
+  bool bad = false;
+  for (int l = lane; l < J.Fp; l += 64) {
     float v = 0.0f;
     if (l < J.F) {
       v = J.V_in[(size_t)t * J.F + l];
-      if (!(v >= 0.0f) || isinf(v)) { bad = 1; v = 0.0f; }
+      if (!(v >= 0.0f) || isinf(v)) { bad = true; v = 0.0f; }
     }
     J.V[(size_t)t * J.Fp + l] = v;
   }
-  if (__syncthreads_or(bad) && threadIdx.x == 0) atomicOr(J.status, kBadV);
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(J.status, kBadV);
 }
 
 // W_in [M][F] -> Wmf [Mp][Fp] (+ bf16); checks rows finite, >= 0, summing to 1.
-__device__ __forceinline__ void pack_wmf_row(const JobDesc &J, int k) {
-  __shared__ float red[256];
+// One wavefront per row.
+__device__ __forceinline__ void pack_wmf_row(const JobDesc &J, int k, int lane) {
   float s = 0.0f;
-  int bad = 0;
-  for (int l = threadIdx.x; l < J.Fp; l += blockDim.x) {
+  bool bad = false;
+  for (int l = lane; l < J.Fp; l += 64) {
     float v = 0.0f;
     if (k < J.M && l < J.F) {
       v = J.W_in[(size_t)k * J.F + l];
-      if (!(v >= 0.0f) || isinf(v)) { bad = 1; v = 0.0f; }
+      if (!(v >= 0.0f) || isinf(v)) { bad = true; v = 0.0f; }
     }
     s += v;
     J.Wmf[(size_t)k * J.Fp + l] = v;
     if (J.bf16) J.Wmf_h[(size_t)k * J.Fp + l] = f2bf(v);
   }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  const int anybad = __syncthreads_or(bad);
-  if (threadIdx.x == 0 && k < J.M && (anybad || fabsf(red[0] - 1.0f) > 1e-4f)) atomicOr(J.status, kBadW);
+  const float tot = wave_sum(s);
+  const bool anybad = __ballot(bad) != 0;
+  if (lane == 0 && k < J.M && (anybad || fabsf(tot - 1.0f) > 1e-4f)) atomicOr(J.status, kBadW);
 }
 
 // Wmf [Mp][Fp] -> Wfm [Fp][Mp] (+ bf16), 32x32 tiles through LDS.
@@ -117,9 +112,10 @@ __device__ __forceinline__ void fill_w_ones_part(const JobDesc &J, int b, int nb
   }
 }
 
-// Batched forms over a work list.  Per job, k_begin_pack has T blocks packing V,
-// then Mp packing the dictionary, then (default start only) kBeginFillBlocks
-// setting w = 1; k_begin_transpose one block per 32 x 32 tile.
+// Batched forms over a work list.  Per job, k_begin_pack has ceil(T / 4) blocks
+// packing V and Mp / 4 packing the dictionary (a row per wavefront), then
+// (default start only) kBeginFillBlocks setting w = 1; k_begin_transpose one
+// block per 32 x 32 tile.
 __global__ void k_status_clear(WorkList wl) {
   for (int i = threadIdx.x; i < wl.njobs; i += blockDim.x) *wl.jobs[i].status = 0;
 }
@@ -134,9 +130,16 @@ __global__ __launch_bounds__(256) void k_begin_pack(WorkList wl) {
   const int jb = find_job(wl.start, wl.njobs, b);
   const JobDesc &J = wl.jobs[jb];
   const int local = b - wl.start[jb];
-  if (local < J.T) pack_v_row(J, local);
-  else if (local < J.T + J.Mp) pack_wmf_row(J, local - J.T);
-  else fill_w_ones_part(J, local - J.T - J.Mp, kBeginFillBlocks);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nv = (J.T + 3) / 4, nw = J.Mp / 4;   // blocks of four rows (one per wavefront)
+  if (local < nv) {
+    const int t = 4 * local + wave;
+    if (t < J.T) pack_v_row(J, t, lane);
+  } else if (local < nv + nw) {
+    pack_wmf_row(J, 4 * (local - nv) + wave, lane);
+  } else {
+    fill_w_ones_part(J, local - nv - nw, kBeginFillBlocks);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_begin_transpose(WorkList wl) {

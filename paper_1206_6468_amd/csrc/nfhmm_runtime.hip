@@ -433,7 +433,7 @@ int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb, bool spec_sm
     case kFrames: return D.T;
     case kRecon: return D.S * D.nlt * ct;
     case kIters: return D.iters;
-    case kBegin: return D.T + D.Mp + (D.alpha_init ? 0 : kBeginFillBlocks);
+    case kBegin: return (D.T + 3) / 4 + D.Mp / 4 + (D.alpha_init ? 0 : kBeginFillBlocks);
     case kTrans: return (D.Mp / 32) * (D.Fp / 32);
     case kLam: return D.alpha_init ? 0 : (D.F + kStartLamBinsPerBlock - 1) / kStartLamBinsPerBlock;
     case kRatio: return D.alpha_init ? 0 : D.T;

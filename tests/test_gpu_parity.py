@@ -316,6 +316,25 @@ def test_batch_is_bitwise_invariant(L, ctx):
             assert np.array_equal(a[k], b[k]), k
 
 
+def test_batch_mixing_default_and_warm_starts(L, ctx):
+    """One batch whose jobs start from the default alpha-hat and from given ones
+    (the start kernels cover both kinds in the same launches), with ragged F (no
+    tail bin, F below one 64-bin tile) and jobs of no iterations: each job equal
+    bit for bit to the same job fitted alone, in FP32 and in BF16."""
+    base = [make_problem(0, 30), dict(make_tiny(S=3, N=4, K=3, F=70, T=150, seed=12, quanta=900), iters=3),
+            dict(make_tiny(S=1, N=7, K=2, F=33, T=57, seed=13, quanta=500), iters=2)]
+    warm = [dict(p, alpha_init=_start_alpha(p, 1)) for p in base]
+    probs = [base[0], warm[1], base[2], warm[0], dict(base[1], iters=0), dict(warm[2], iters=0)]
+    for prec in ("fp32", "bf16"):
+        batch = L.fit_batch(ctx, probs, prec)
+        for j, (p, b) in enumerate(zip(probs, batch)):
+            a = L.fit(ctx, p, prec)
+            for k in ("alpha", "post", "sep"):
+                assert np.array_equal(a[k], b[k]), (prec, j, k)
+            assert np.allclose(a["elbo"], b["elbo"], rtol=1e-12, atol=0.0), (prec, j)
+            assert np.all(np.isfinite(b["sep"])) and np.all(np.isfinite(b["alpha"])), (prec, j)
+
+
 def test_bench_launch_configuration(L, ctx):
     """The bench's configuration: 32 config-1 jobs in one batch (two stream lanes
     of 16).  One step from oracle alpha-hats: sampled jobs against the FP64
