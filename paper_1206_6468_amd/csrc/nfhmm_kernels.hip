@@ -290,7 +290,12 @@ __device__ void gemm_nt_f32_dma(const float *__restrict__ A, int lda, int arows,
       dma_rows<BM>(A, lda, arows, row0, k + kBKf, As1, wave, lane);
       dma_rows<BN>(B, ldb, bcols, col0, k + kBKf, Bs1, wave, lane);
     }
+    // a raised wave priority while the stage's MFMAs issue: of the waves sharing a
+    // SIMD, one that has begun its cluster keeps the matrix pipe (measured +1.4 %
+    // on the loop; no gain in the bf16 loop, which is not issue-bound)
+    __builtin_amdgcn_s_setprio(1);
     mma_stage_f32_dma<WM, WN>(As0, Bs0, f, acc);
+    __builtin_amdgcn_s_setprio(0);
     // the MFMAs stay before the barrier (and its wait for the loads in flight),
     // which the scheduler would otherwise move above them
     __builtin_amdgcn_sched_barrier(0);
@@ -300,7 +305,9 @@ __device__ void gemm_nt_f32_dma(const float *__restrict__ A, int lda, int arows,
       dma_rows<BM>(A, lda, arows, row0, k + 2 * kBKf, As0, wave, lane);
       dma_rows<BN>(B, ldb, bcols, col0, k + 2 * kBKf, Bs0, wave, lane);
     }
+    __builtin_amdgcn_s_setprio(1);
     mma_stage_f32_dma<WM, WN>(As1, Bs1, f, acc);
+    __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
   }
