@@ -126,12 +126,13 @@ __device__ __forceinline__ void twiddle3(float (&vr)[4], float (&vi)[4], const f
   }
 }
 
-// One radix-4 pass of size ns from (sr, si) to (dr, di), both in LDS.
+// One radix-4 pass of size ns from (sr, si) to (dr, di), both in LDS; the
+// calling thread takes butterflies j0, j0 + stride, ...
 template <int L, int SIGN>
 __device__ __forceinline__ void pass4(const float *sr, const float *si, float *dr, float *di, const float *twr,
-                                      const float *twi, int off, int ns) {
+                                      const float *twi, int off, int ns, int j0, int stride) {
   constexpr int Q = L / 4;
-  for (int j = threadIdx.x; j < Q; j += kStftThreads) {
+  for (int j = j0; j < Q; j += stride) {
     const int k = j & (ns - 1);
     float vr[4], vi[4];
 #pragma unroll
@@ -156,10 +157,10 @@ __device__ __forceinline__ void pass4(const float *sr, const float *si, float *d
 // offset.
 template <int L, int SIGN>
 __device__ __forceinline__ int middle_passes(float *&sr, float *&si, float *&dr, float *&di, const float *twr,
-                                             const float *twi) {
+                                             const float *twi, int j0 = threadIdx.x, int stride = kStftThreads) {
   int off = 0;
   for (int ns = first_twiddled<L>(); ns < L / 4; ns *= 4) {
-    pass4<L, SIGN>(sr, si, dr, di, twr, twi, off, ns);
+    pass4<L, SIGN>(sr, si, dr, di, twr, twi, off, ns, j0, stride);
     off += 3 * ns;
     __syncthreads();
     float *tr = sr, *ti = si;
@@ -291,14 +292,18 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
   // complex inverse transform: with Z[k] = (X[k] + conj X[H-k]) + i e_k (X[k] -
   // conj X[H-k]), e_k = exp(2 pi i k / NFFT), its inverse z gives z[m] =
   // y[2m] + i y[2m+1].  A block takes kIstftPair sources of one mixture, which
-  // share the phase: its loads and sincos, and the squared-window ring.
+  // share the phase (its loads and sincos, folded for both sources by the same
+  // thread) and the squared-window ring; their transforms run side by side, the
+  // block's threads split between them, so every pass keeps all threads busy and
+  // each barrier serves both.
   constexpr int H = NFFT / 2, F = H + 1, Q = H / 4, P = H / 2 + 1;   // P pairs (k, H - k), k <= H/2
   constexpr bool kOdd = ilog2(H) % 2 == 1;
+  constexpr int TPS = kStftThreads / kIstftPair;   // threads per source in the passes
   // the first pass writes 2 or 4 consecutive words per lane
-  __shared__ __align__(16) float re[H];
-  __shared__ __align__(16) float im[H];
-  __shared__ __align__(16) float re2[H];
-  __shared__ __align__(16) float im2[H];
+  __shared__ __align__(16) float re[kIstftPair][H];
+  __shared__ __align__(16) float im[kIstftPair][H];
+  __shared__ __align__(16) float re2[kIstftPair][H];
+  __shared__ __align__(16) float im2[kIstftPair][H];
   __shared__ float twr[H], twi[H], win[NFFT], er[P], ei[P];
   __shared__ float acc[kIstftPair][NFFT], wacc[NFFT];   // rings: slot i mod NFFT holds sample i
   const int groups = (S + kIstftPair - 1) / kIstftPair;
@@ -307,6 +312,7 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
   const int t0 = blockIdx.x * G, t1 = min(T, t0 + G);
   const int lead = (NFFT + hop - 1) / hop - 1;   // frames before t0 that cover samples >= t0 hop
   const int ts = max(0, t0 - lead);
+  const int sl = threadIdx.x / TPS, lt = threadIdx.x - sl * TPS;   // this thread's source in the passes
   twiddles<H, 1>(twr, twi);
   window<NFFT>(win);
   for (int k = threadIdx.x; k < P; k += kStftThreads) sincospif(2.0f * (float)k / (float)NFFT, &ei[k], &er[k]);
@@ -338,85 +344,80 @@ __global__ __launch_bounds__(kStftThreads) void k_istft(const float *__restrict_
   if (ts < t1) load(ts);
   for (int t = ts; t < t1; ++t) {
     __syncthreads();   // the tables and rings are written; the previous frame is folded in
-    // this frame's bins: the phase's sincos once for every source of the block
-    float ca[kPerP], sa[kPerP], cb[kPerP], sb[kPerP], mca[kPerP][kIstftPair], mcb[kPerP][kIstftPair];
+    // this frame's bins, folded for every source: the phase's sincos once
 #pragma unroll
     for (int q = 0; q < kPerP; ++q) {
-      sincosf(pa[q], &sa[q], &ca[q]);
-      sincosf(pb[q], &sb[q], &cb[q]);
+      const int k = threadIdx.x + q * kStftThreads;
+      if (k >= P) break;
+      // the hardware sine and cosine, accurate to about 1e-6 on [-pi, pi]: the phase
+      // is first reduced by whole turns (no change for a phase already in range,
+      // as those of the transform are)
+      float ca, sa, cb, sb;
+      const float ra = pa[q] - 6.28318530717958648f * rintf(pa[q] * 0.159154943091895336f);
+      const float rb = pb[q] - 6.28318530717958648f * rintf(pb[q] * 0.159154943091895336f);
+      __sincosf(ra, &sa, &ca);
+      __sincosf(rb, &sb, &cb);
+      const float c = er[k], d = ei[k];
 #pragma unroll
       for (int s = 0; s < kIstftPair; ++s) {
-        mca[q][s] = ma[q][s];
-        mcb[q][s] = mb[q][s];
-      }
-    }
-    if (t + 1 < t1) load(t + 1);
-    const int64_t base = (int64_t)t * hop;
-#pragma unroll
-    for (int s = 0; s < kIstftPair; ++s) {
-      if (s >= ns) break;
-      if (s > 0) __syncthreads();   // the previous source's last pass has read the buffers
-#pragma unroll
-      for (int q = 0; q < kPerP; ++q) {
-        const int k = threadIdx.x + q * kStftThreads;
-        if (k >= P) break;
         // a = X[k], b = X[H - k]; bins 0 and H of a real signal are real (their
         // imaginary parts are dropped)
-        const float ar = mca[q][s] * ca[q], ai = k == 0 ? 0.0f : mca[q][s] * sa[q];
-        const float br = mcb[q][s] * cb[q], bi = k == 0 ? 0.0f : mcb[q][s] * sb[q];
-        const float c = er[k], d = ei[k];
+        const float ar = ma[q][s] * ca, ai = k == 0 ? 0.0f : ma[q][s] * sa;
+        const float br = mb[q][s] * cb, bi = k == 0 ? 0.0f : mb[q][s] * sb;
         // Z[k] = u + i e v, u = a + conj b, v = a - conj b
         const float ur = ar + br, ui = ai - bi, vr = ar - br, vi = ai + bi;
-        re[sw(k)] = ur - (c * vi + d * vr);
-        im[sw(k)] = ui + (c * vr - d * vi);
+        re[s][sw(k)] = ur - (c * vi + d * vr);
+        im[s][sw(k)] = ui + (c * vr - d * vi);
         if (k > 0 && k < H - k) {
           // Z[H - k] from the same pair: roles of a and b swapped, e_{H-k} = -conj e_k
           const float ur2 = br + ar, ui2 = bi - ai, vr2 = br - ar, vi2 = bi + ai;
-          re[sw(H - k)] = ur2 - (-c * vi2 + d * vr2);
-          im[sw(H - k)] = ui2 + (-c * vr2 - d * vi2);
+          re[s][sw(H - k)] = ur2 - (-c * vi2 + d * vr2);
+          im[s][sw(H - k)] = ui2 + (-c * vr2 - d * vi2);
         }
       }
-      __syncthreads();
-      // first pass (ns = 1, twiddles 1) from (re, im) to (re2, im2)
-      if constexpr (kOdd) {
-        for (int j = threadIdx.x; j < H / 2; j += kStftThreads) {
-          const float xr = re[sw(j)], xi = im[sw(j)], zr = re[sw(j + H / 2)], zi = im[sw(j + H / 2)];
-          reinterpret_cast<float2 *>(re2)[sw(2 * j) >> 1] = make_float2(xr + zr, xr - zr);
-          reinterpret_cast<float2 *>(im2)[sw(2 * j) >> 1] = make_float2(xi + zi, xi - zi);
-        }
-      } else {
-        for (int j = threadIdx.x; j < Q; j += kStftThreads) {
-          float vr[4], vi[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            vr[r] = re[sw(j + r * Q)];
-            vi[r] = im[sw(j + r * Q)];
-          }
-          dft4<1>(vr, vi);
-          reinterpret_cast<float4 *>(re2)[sw(4 * j) >> 2] = make_float4(vr[0], vr[1], vr[2], vr[3]);
-          reinterpret_cast<float4 *>(im2)[sw(4 * j) >> 2] = make_float4(vi[0], vi[1], vi[2], vi[3]);
-        }
+    }
+    if (t + 1 < t1) load(t + 1);
+    __syncthreads();
+    // first pass (ns = 1, twiddles 1) from (re, im) to (re2, im2), source sl
+    if constexpr (kOdd) {
+      for (int j = lt; j < H / 2; j += TPS) {
+        const float xr = re[sl][sw(j)], xi = im[sl][sw(j)], zr = re[sl][sw(j + H / 2)], zi = im[sl][sw(j + H / 2)];
+        reinterpret_cast<float2 *>(re2[sl])[sw(2 * j) >> 1] = make_float2(xr + zr, xr - zr);
+        reinterpret_cast<float2 *>(im2[sl])[sw(2 * j) >> 1] = make_float2(xi + zi, xi - zi);
       }
-      __syncthreads();
-      float *sr = re2, *si = im2, *dr = re, *di = im;
-      const int off = middle_passes<H, 1>(sr, si, dr, di, twr, twi);
-      // last pass: z[m], m = j + r H/4, is samples 2m (real part) and 2m + 1
-      // (imaginary part) of the frame; scaled and windowed into the rings (the
-      // squared window once, with the first source)
-      for (int j = threadIdx.x; j < Q; j += kStftThreads) {
+    } else {
+      for (int j = lt; j < Q; j += TPS) {
         float vr[4], vi[4];
-        last_pass<H, 1>(sr, si, twr, twi, off, j, vr, vi);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = 2 * (j + r * Q);
-          const int q0 = (int)((base + i) & (NFFT - 1)), q1 = (int)((base + i + 1) & (NFFT - 1));
-          const float w0 = win[i], w1 = win[i + 1];
-          acc[s][q0] += vr[r] * (1.0f / (float)NFFT) * w0;
-          acc[s][q1] += vi[r] * (1.0f / (float)NFFT) * w1;
-          if (s == 0) {
-            wacc[q0] += w0 * w0;
-            wacc[q1] += w1 * w1;
-          }
+          vr[r] = re[sl][sw(j + r * Q)];
+          vi[r] = im[sl][sw(j + r * Q)];
+        }
+        dft4<1>(vr, vi);
+        reinterpret_cast<float4 *>(re2[sl])[sw(4 * j) >> 2] = make_float4(vr[0], vr[1], vr[2], vr[3]);
+        reinterpret_cast<float4 *>(im2[sl])[sw(4 * j) >> 2] = make_float4(vi[0], vi[1], vi[2], vi[3]);
+      }
+    }
+    __syncthreads();
+    float *sr = re2[sl], *si = im2[sl], *dr = re[sl], *di = im[sl];
+    const int off = middle_passes<H, 1>(sr, si, dr, di, twr, twi, lt, TPS);
+    // last pass: z[m], m = j + r H/4, is samples 2m (real part) and 2m + 1
+    // (imaginary part) of the frame; scaled and windowed into source sl's ring
+    // (the squared window once, by the first source's threads)
+    const int64_t base = (int64_t)t * hop;
+    for (int j = lt; j < Q; j += TPS) {
+      float vr[4], vi[4];
+      last_pass<H, 1>(sr, si, twr, twi, off, j, vr, vi);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 2 * (j + r * Q);
+        const int q0 = (int)((base + i) & (NFFT - 1)), q1 = (int)((base + i + 1) & (NFFT - 1));
+        const float w0 = win[i], w1 = win[i + 1];
+        acc[sl][q0] += vr[r] * (1.0f / (float)NFFT) * w0;
+        acc[sl][q1] += vi[r] * (1.0f / (float)NFFT) * w1;
+        if (sl == 0) {
+          wacc[q0] += w0 * w0;
+          wacc[q1] += w1 * w1;
         }
       }
     }

@@ -90,6 +90,25 @@ def test_istft_frames_past_the_end_and_uncovered_tail(L, ctx):
             assert np.all(y[:, 11 * hop + nfft:] == 0.0)
 
 
+def test_istft_phase_in_any_turn(L, ctx):
+    # phases shifted by whole turns (as an unwrapped phase would be) resynthesise
+    # the same signal
+    nfft, hop, n = 1024, 256, 30_000
+    rng = np.random.default_rng(5)
+    mag, phase = SO.stft(rng.normal(size=n), nfft, hop)
+    m = mag[None].astype(np.float32)
+    p = phase.astype(np.float32)
+    turns = rng.integers(-40, 41, size=p.shape)
+    p2 = (p.astype(np.float64) + 2.0 * np.pi * turns).astype(np.float32)
+    y1 = L.istft(ctx, m, p, n, nfft, hop)
+    y2 = L.istft(ctx, m, p2, n, nfft, hop)
+    ws = SO.window_weight(n, mag.shape[0], nfft, hop)
+    ok = ws >= 0.1
+    err = np.max(np.abs(y1[:, ok] - y2[:, ok])) / np.max(np.abs(y1[:, ok]))
+    print(f"\nistft, phases off by up to 40 turns: max |dy| / max |y| = {err:.2e}")
+    assert err < 1e-4
+
+
 def test_round_trip_and_sources_sum_to_mixture(L, ctx):
     # analysis, three masks that sum to one, resynthesis with the mixture phase
     nfft, hop, n = 1024, 256, 64_000
