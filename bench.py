@@ -382,6 +382,22 @@ def measured_peaks():
     out["hbm_copy_gbps"] = 2.0 * src.numel() * 4 / (ms * 1e-3) / 1e9   # read + write
     out["hbm_copy_frac"] = out["hbm_copy_gbps"] * 1e9 / PEAK_HBM
     del src, dst
+    # the host link: 256 MiB each way, from pinned and from pageable host memory
+    # (what bounds the copies of serving and of the host-array calls)
+    dev = torch.empty((1 << 26,), device="cuda")
+    for kind, pin in (("pinned", True), ("pageable", False)):
+        host = torch.empty((1 << 26,), pin_memory=pin)
+        host.fill_(1.0)
+        for name, (dst, src) in (("h2d", (dev, host)), ("d2h", (host, dev))):
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            out[f"{name}_{kind}_gbps"] = reps * host.numel() * 4 / (time.perf_counter() - t0) / 1e9
+        del host
+    del dev
     torch.cuda.empty_cache()
     return out
 
@@ -445,6 +461,8 @@ def main():
     ap.add_argument("--stft-only", action="store_true",
                     help="only time the time-frequency front and back end (STFT of 32 mixtures of "
                          "1000 frames, inverse of 2 sources each) and print its figures")
+    ap.add_argument("--em-only", action="store_true",
+                    help="only the EM learning of one source model (one JSON line)")
     ap.add_argument("--bf16-only", action="store_true",
                     help="only time the BF16-contraction form of the batch (for a profiler run of its "
                          "kernels) and print its figures")
@@ -472,6 +490,11 @@ def main():
     if args.stft_only:
         ctx = L.Context(0)
         print(json.dumps(stft_bench(L, ctx, reps=max(args.steps, 1))), flush=True)
+        ctx.close()
+        return
+    if args.em_only:
+        ctx = L.Context(0)
+        print(json.dumps(em_bench(L, ctx)), flush=True)
         ctx.close()
         return
     if args.bf16_only:

@@ -1787,6 +1787,8 @@ nfhmm_status em_run(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_resu
   }
   const size_t o_ll = take(T * N * 8), o_off = take(T * 8), o_x = take(T * 64 * 4), o_la = take(T * 64 * 4);
   const size_t o_lgam = take(T * N * 4), o_gmax = take(N * 4);
+  const size_t o_lbn = take(T * 64 * 4), o_sI = take(T * 64 * 4);
+  const size_t o_xpart = take(nchunk * N * 64 * 8), o_gpart = take(nchunk * N * 4);
   const size_t o_bpart = take(nchunk * N * K * F * 8), o_trace = take(it * 8);
   Job j;   // only its arena is used: allocated and cached like a fit's
   j.L.total = off;
@@ -1818,6 +1820,8 @@ nfhmm_status em_run(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_resu
     E.beta_new = F64(o_b[n]); E.theta_new = F64(o_th[n]); E.lnA_new = F32(o_lA[n]); E.lnpi_new = F32(o_lpi[n]);
     E.ll = F64(o_ll); E.off = F64(o_off); E.x = F32(o_x); E.la = F32(o_la);
     E.lgam = F32(o_lgam); E.gmax = F32(o_gmax);
+    E.lbn = F32(o_lbn); E.sI = F32(o_sI);
+    E.xpart = reinterpret_cast<float2 *>(a + o_xpart); E.gpart = F32(o_gpart);
     E.bpart = F64(o_bpart); E.trace = F64(o_trace);
     e = launch_em_frames(E, st);
     if (e == hipSuccess) e = launch_em_chain(E, (int)i, st);

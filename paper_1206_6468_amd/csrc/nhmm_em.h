@@ -22,7 +22,7 @@
 namespace nfhmm {
 
 constexpr int kEmMaxK = 32;      // elements per state
-constexpr int kEmChunk = 32;     // frames per partial sum of the beta update's sums over t
+constexpr int kEmChunk = 32;     // frames per partial sum of the beta update's and the xi sums over t
 // ln of the smallest normal double: probabilities (marginals, pairwise marginals,
 // transitions, initial probabilities) below it count as zero, as they are in a
 // double-precision evaluation of the same updates -- where a state or a
@@ -44,8 +44,12 @@ struct EmDesc {
   double *off;              // [T]         their largest value per frame
   float *x;                 // [T][64]     ll - off: the chain's log evidence (row per frame)
   float *la;                // [T][64]     log forward messages, normalised per frame
+  float *lbn;               // [T][64]     log backward messages, normalised per frame
+  float *sI;                // [T][64]     the backward messages before that normalisation
   float *lgam;              // [T][N]      ln gamma_t(d), the log state marginals
   float *gmax;              // [N]         max_t ln gamma_t(d)
+  float2 *xpart;            // [nchunk][N][64] per frame chunk: sum of xi_t(i, j) as (max, scaled sum)
+  float *gpart;             // [nchunk][N] per frame chunk: max ln gamma_t(i)
   double *bpart;            // [nchunk][N][K][F] partial sums over frame chunks of the beta update
   double *trace;            // [iters]     ln P(V) of the parameters each iteration started from
 };
@@ -53,7 +57,9 @@ struct EmDesc {
 // E-step per (frame, state) -- frame log-likelihoods and the theta update, which
 // needs no chain posterior -- and the chain's log-evidence rows.
 hipError_t launch_em_frames(const EmDesc &E, hipStream_t st);
-// The chain in log space: gamma, the new ln A and ln pi, and ln P(V) for iteration `it`.
+// The chain in log space (the two sweeps side by side, then gamma and the pairwise
+// marginals over frame chunks): gamma, the new ln A and ln pi, and ln P(V) for
+// iteration `it`.
 hipError_t launch_em_chain(const EmDesc &E, int it, hipStream_t st);
 // The beta update (after the chain).
 hipError_t launch_em_beta(const EmDesc &E, hipStream_t st);

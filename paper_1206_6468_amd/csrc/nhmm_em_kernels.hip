@@ -11,9 +11,15 @@
 //                theta'_t(d, z) ~ theta_t(d, z) sum_f beta(d, z, f) V_tf / P_t(f | d),
 //                which needs no chain posterior (gamma_t(d) is a common factor)
 //   k_em_prep    the chain's log evidence ll - max_d ll per frame
-//   k_em_chain   the forward-backward in log space: ln gamma_t(d), ln P(V), and the
-//                pairwise marginals xi_t(i, j) summed over t in log space, which give
-//                A' ~ sum_t xi_t (rows normalised) and pi' = gamma_0
+//   k_em_chain   the two sweeps of the forward-backward in log space, side by side
+//                (one wavefront each): the forward messages and ln P(V), the
+//                backward messages
+//   k_em_post    ln gamma_t(d) from the two messages, one wavefront per frame
+//   k_em_xi      the pairwise marginals xi_t(i, j) summed over the frames of a
+//                chunk in log space (running maximum and scaled sum), per (chunk,
+//                row i), lane = column j
+//   k_em_xi_reduce  the chunks' sums in order: A' ~ sum_t xi_t (rows normalised),
+//                pi' = gamma_0, and the largest ln gamma of each state
 //   k_em_beta    partial sums over frame chunks of
 //                sum_t gamma_t(d) theta_t(d, z) V_tf / P_t(f | d)
 //   k_em_beta_reduce  beta'(d, z, f) ~ beta(d, z, f) times that sum, normalised over f
@@ -114,31 +120,30 @@ __device__ __forceinline__ float lse_lanes(float x, bool live) {
   return mx + __logf(wave_sum(live ? __expf(x - mx) : 0.0f));
 }
 
-// The forward-backward of the source chain in log space, one wavefront, lane r =
-// state r, messages normalised per frame (no value is flushed: the smallest
-// probabilities the iterations need are far below the float32 range).
+// The forward-backward of the source chain in log space: block 0 sweeps forward,
+// block 1 backward, each one wavefront with lane r = state r and messages
+// normalised per frame (no value is flushed: the smallest probabilities the
+// iterations need are far below the float32 range).
 //   forward   la_t(n) = x_t(n) + lse_m(la_{t-1}(m) + ln A(m, n)), la_0 = ln pi + x_0;
 //             ln Z = the sum of the frames' normalisers
-//   backward  lb_{t-1}(i) = lse_j(ln A(i, j) + x_t(j) + lb_t(j)), lb_{T-1} = 0;
-//             gamma_{t-1}(i) from la + lb, and with q_t(i, j) = the transition
-//             posterior given D_{t-1} = i, ln xi_t(i, j) = ln gamma_{t-1}(i) + ln q_t(i, j),
-//             summed over t per (i, j) as a running maximum and a scaled sum.
-// Lane r holds column r of ln A for the forward and row r for the backward (row r
-// of the new ln A is its own accumulators).
+//   backward  s_{t-1}(i) = lse_j(ln A(i, j) + x_t(j) + lb_t(j)), lb_{t-1} = s_{t-1}
+//             normalised, lb_{T-1} = 0; both are stored, s for the pairwise
+//             marginals: ln xi_t(i, j) = ln gamma_{t-1}(i) + ln A(i, j) + x_t(j) +
+//             lb_t(j) - s_{t-1}(i).
+// Lane r holds column r of ln A forward and row r backward.
 template <int NR>
 __global__ __launch_bounds__(64) void k_em_chain(EmDesc E, int it) {
   const int r = threadIdx.x, N = E.N, T = E.T;
   const bool live = r < N;
   __shared__ float buf[64];
-  float la;
-  double z = 0.0;
-  {
+  if (blockIdx.x == 0) {
     float col[NR];
 #pragma unroll
     for (int m = 0; m < NR; ++m) col[m] = (live && m < N) ? E.lnA[(size_t)m * N + r] : -INFINITY;
+    double z = 0.0;
     const float l0 = live ? E.lnpi[r] + E.x[r] : -INFINITY;
     float c = lse_lanes(l0, live);
-    la = (live && c > -INFINITY) ? l0 - c : -INFINITY;
+    float la = (live && c > -INFINITY) ? l0 - c : -INFINITY;
     E.la[r] = la;
     z += (double)c;
     for (int t = 1; t < T; ++t) {
@@ -159,85 +164,101 @@ __global__ __launch_bounds__(64) void k_em_chain(EmDesc E, int it) {
       E.la[(size_t)t * 64 + r] = la;
       z += (double)c;
     }
-  }
-  // ln P(V) = sum_t off_t + ln Z of the relative evidence
-  double off = 0.0;
-  for (int t = r; t < T; t += 64) off += E.off[t];
-  off = wave_sum_d(off);
-  if (r == 0) E.trace[it] = off + z;
-  // backward, gamma and the transition counts
-  float row[NR], M[NR], S[NR];
+    // ln P(V) = sum_t off_t + ln Z of the relative evidence
+    double off = 0.0;
+    for (int t = r; t < T; t += 64) off += E.off[t];
+    off = wave_sum_d(off);
+    if (r == 0) E.trace[it] = off + z;
+  } else {
+    float row[NR];
 #pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    row[j] = (live && j < N) ? E.lnA[(size_t)r * N + j] : -INFINITY;
-    M[j] = -INFINITY;
-    S[j] = 0.0f;
-  }
-  float lb = live ? 0.0f : -INFINITY;
-  float lgam;
-  {
-    const float g = la + lb;
-    const float cg = lse_lanes(g, live);   // every lane: the reduction reads lane 63
-    lgam = (live && cg > -INFINITY) ? g - cg : -INFINITY;
-    if (live) E.lgam[(size_t)(T - 1) * N + r] = lgam;
-  }
-  float gmx = lgam;
-  for (int t = T - 1; t >= 1; --t) {
-    buf[r] = live ? E.x[(size_t)t * 64 + r] + lb : -INFINITY;
-    __syncthreads();
-    float mx = -INFINITY;
+    for (int j = 0; j < NR; ++j) row[j] = (live && j < N) ? E.lnA[(size_t)r * N + j] : -INFINITY;
+    float lb = live ? 0.0f : -INFINITY;
+    E.lbn[(size_t)(T - 1) * 64 + r] = lb;
+    for (int t = T - 1; t >= 1; --t) {
+      buf[r] = live ? E.x[(size_t)t * 64 + r] + lb : -INFINITY;
+      __syncthreads();
+      float mx = -INFINITY;
 #pragma unroll
-    for (int j = 0; j < NR; ++j) mx = fmaxf(mx, row[j] + buf[j]);
-    float s = 0.0f;
-    if (mx > -INFINITY) {
+      for (int j = 0; j < NR; ++j) mx = fmaxf(mx, row[j] + buf[j]);
+      float s = 0.0f;
+      if (mx > -INFINITY) {
 #pragma unroll
-      for (int j = 0; j < NR; ++j) s += __expf(row[j] + buf[j] - mx);
-    }
-    const float sI = (live && mx > -INFINITY) ? mx + __logf(s) : -INFINITY;   // lb_{t-1}(r), unnormalised
-    const float lap = live ? E.la[(size_t)(t - 1) * 64 + r] : -INFINITY;
-    const float g = lap + sI;
-    const float cg = lse_lanes(g, live);
-    lgam = (live && cg > -INFINITY) ? g - cg : -INFINITY;
-    if (live) E.lgam[(size_t)(t - 1) * N + r] = lgam;
-    gmx = fmaxf(gmx, lgam);
-    if (lgam >= kEmLogTiny) {
-#pragma unroll
-      for (int j = 0; j < NR; ++j) {
-        const float v = lgam + row[j] + buf[j] - sI;   // ln xi_t(r, j)
-        if (v >= kEmLogTiny) {
-          const float d = v - M[j];
-          const float e = __expf(-fabsf(d));
-          S[j] = d > 0.0f ? fmaf(S[j], e, 1.0f) : S[j] + e;
-          M[j] = fmaxf(M[j], v);
-        }
+        for (int j = 0; j < NR; ++j) s += __expf(row[j] + buf[j] - mx);
       }
+      __syncthreads();
+      const float sI = (live && mx > -INFINITY) ? mx + __logf(s) : -INFINITY;
+      const float cb = lse_lanes(sI, live);
+      lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
+      E.sI[(size_t)(t - 1) * 64 + r] = sI;
+      E.lbn[(size_t)(t - 1) * 64 + r] = lb;
     }
-    __syncthreads();
-    const float cb = lse_lanes(sI, live);
-    lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
   }
-  // pi' = gamma_0; row r of A' from its accumulators (kept if it received nothing)
-  if (live) {
-    E.lnpi_new[r] = lgam >= kEmLogTiny ? lgam : -INFINITY;
-    E.gmax[r] = gmx;
+}
+
+// ln gamma_t = la_t + lb_t normalised over the states: one wavefront per frame.
+__global__ __launch_bounds__(64) void k_em_post(EmDesc E) {
+  const int t = blockIdx.x, r = threadIdx.x;
+  const bool live = r < E.N;
+  const float g = live ? E.la[(size_t)t * 64 + r] + E.lbn[(size_t)t * 64 + r] : -INFINITY;
+  const float cg = lse_lanes(g, live);   // every lane: the reduction reads lane 63
+  if (live) E.lgam[(size_t)t * E.N + r] = (cg > -INFINITY) ? g - cg : -INFINITY;
+}
+
+// sum over the frames t of chunk c (t >= 1) of xi_t(i, j), as a running maximum M
+// and a sum S scaled by exp(-M): block (c, i), lane j.  Terms and sums below
+// kEmLogTiny count as zero, as in a double-precision evaluation.  Lane 0 also
+// keeps the chunk's largest ln gamma_t(i).
+__global__ __launch_bounds__(64) void k_em_xi(EmDesc E) {
+  const int c = blockIdx.x, i = blockIdx.y, j = threadIdx.x, N = E.N;
+  const bool live = j < N;
+  const float aij = live ? E.lnA[(size_t)i * N + j] : -INFINITY;
+  const int t0 = c * kEmChunk, t1 = min(E.T, t0 + kEmChunk);
+  float M = -INFINITY, S = 0.0f, gmx = -INFINITY;
+  for (int t = t0; t < t1; ++t) {
+    gmx = fmaxf(gmx, E.lgam[(size_t)t * N + i]);
+    if (t == 0) continue;
+    const float lg = E.lgam[(size_t)(t - 1) * N + i];
+    if (!(lg >= kEmLogTiny)) continue;   // uniform over the block
+    const float v = lg + aij + E.x[(size_t)t * 64 + j] + E.lbn[(size_t)t * 64 + j] - E.sI[(size_t)(t - 1) * 64 + i];
+    if (live && v >= kEmLogTiny) {
+      const float d = v - M;
+      const float e = __expf(-fabsf(d));
+      S = d > 0.0f ? fmaf(S, e, 1.0f) : S + e;
+      M = fmaxf(M, v);
+    }
   }
-  float lr[NR];
-  float rmx = -INFINITY;
-#pragma unroll
-  for (int j = 0; j < NR; ++j) {
-    lr[j] = (S[j] > 0.0f) ? M[j] + __logf(S[j]) : -INFINITY;
-    if (lr[j] < kEmLogTiny) lr[j] = -INFINITY;   // an expected count that underflows a double
-    rmx = fmaxf(rmx, lr[j]);
+  E.xpart[((size_t)c * N + i) * 64 + j] = make_float2(M, S);
+  if (j == 0) E.gpart[(size_t)c * N + i] = gmx;
+}
+
+// Row i of the new ln A from the chunks' sums (merged in chunk order; kept if the
+// row received nothing), ln pi'(i) = ln gamma_0(i), and gmax(i).  One wavefront
+// per row, lane j.
+__global__ __launch_bounds__(64) void k_em_xi_reduce(EmDesc E) {
+  const int i = blockIdx.x, j = threadIdx.x, N = E.N;
+  const bool live = j < N;
+  float M = -INFINITY, S = 0.0f, gmx = -INFINITY;
+  for (int c = 0; c < E.nchunk; ++c) {
+    const float2 p = E.xpart[((size_t)c * N + i) * 64 + j];
+    if (p.y > 0.0f) {
+      const float d = p.x - M;
+      if (d > 0.0f) { S = fmaf(S, __expf(-d), p.y); M = p.x; }
+      else S = fmaf(p.y, __expf(d), S);
+    }
+    gmx = fmaxf(gmx, E.gpart[(size_t)c * N + i]);
   }
-  float rs = 0.0f;
-  if (rmx > -INFINITY) {
-#pragma unroll
-    for (int j = 0; j < NR; ++j) rs += __expf(lr[j] - rmx);
-  }
+  float lr = (live && S > 0.0f) ? M + __logf(S) : -INFINITY;
+  if (lr < kEmLogTiny) lr = -INFINITY;   // an expected count that underflows a double
+  const float rmx = wave_max(lr);
+  const float rs = wave_sum(rmx > -INFINITY && lr > -INFINITY ? __expf(lr - rmx) : 0.0f);
   const float lrs = rmx + __logf(rs);
-#pragma unroll
-  for (int j = 0; j < NR; ++j)
-    if (live && j < N) E.lnA_new[(size_t)r * N + j] = rmx > -INFINITY ? lr[j] - lrs : row[j];
+  if (live) E.lnA_new[(size_t)i * N + j] = rmx > -INFINITY ? lr - lrs : E.lnA[(size_t)i * N + j];
+  if (j == 0) {
+    const float g0 = E.lgam[i];
+    E.lnpi_new[i] = g0 >= kEmLogTiny ? g0 : -INFINITY;
+    E.gmax[i] = gmx;
+  }
 }
 
 // Partial sums of the beta update over one chunk of frames: lane = bin f of a
@@ -343,12 +364,15 @@ hipError_t launch_em_frames(const EmDesc &E, hipStream_t st) {
 hipError_t launch_em_chain(const EmDesc &E, int it, hipStream_t st) {
   const int nr = (E.N + 15) & ~15;
   switch (nr) {
-    case 16: k_em_chain<16><<<1, 64, 0, st>>>(E, it); break;
-    case 32: k_em_chain<32><<<1, 64, 0, st>>>(E, it); break;
-    case 48: k_em_chain<48><<<1, 64, 0, st>>>(E, it); break;
-    case 64: k_em_chain<64><<<1, 64, 0, st>>>(E, it); break;
+    case 16: k_em_chain<16><<<2, 64, 0, st>>>(E, it); break;
+    case 32: k_em_chain<32><<<2, 64, 0, st>>>(E, it); break;
+    case 48: k_em_chain<48><<<2, 64, 0, st>>>(E, it); break;
+    case 64: k_em_chain<64><<<2, 64, 0, st>>>(E, it); break;
     default: return hipErrorInvalidValue;
   }
+  k_em_post<<<E.T, 64, 0, st>>>(E);
+  k_em_xi<<<dim3(E.nchunk, E.N), 64, 0, st>>>(E);
+  k_em_xi_reduce<<<E.N, 64, 0, st>>>(E);
   return hipGetLastError();
 }
 
