@@ -246,7 +246,9 @@ NFHMM_API nfhmm_status nfhmm_learn_nhmm_device(nfhmm_ctx *ctx, const nfhmm_nhmm_
  * admitted first-in-first-out when the device-memory budget and a slot allow; every
  * resident job advances one iteration per round of batched launches, so jobs that
  * arrive while others run join the next round.  The output arrays of *r must stay
- * valid until nfhmm_wait returns for this job.  NFHMM_E_NOMEM if the job can never fit. */
+ * valid until nfhmm_wait returns for this job; those in pinned (page-locked) host
+ * memory are written by a direct device-to-host copy, the others through the
+ * context's pinned staging ring.  NFHMM_E_NOMEM if the job can never fit. */
 NFHMM_API nfhmm_status nfhmm_submit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precision prec,
                           nfhmm_result *r, uint64_t *job_id);
 

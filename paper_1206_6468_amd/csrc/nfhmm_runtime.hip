@@ -315,6 +315,7 @@ struct Job {
   size_t charged = 0;         // bytes counted against the serving budget while admitted
   bool in_slab = false;       // arena carved from the serving slab
   size_t out_pin = ~size_t(0);  // offset of the outputs in the pinned ring (serving)
+  bool out_direct[4] = {};      // alpha, post, sep, elbo: the caller's array is pinned, copied into directly
   int dev_flag = 0;             // the device status word, delivered with the outputs
   JobDesc desc{};
   nfhmm_status status = NFHMM_OK;
@@ -778,14 +779,16 @@ nfhmm_status upload_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
   return NFHMM_OK;
 }
 
-struct OutPiece { void *dst; size_t src, bytes; };
+// The outputs of a host-memory job; a direct piece goes from the arena straight
+// into the caller's pinned array, the others through the pinned ring.
+struct OutPiece { void *dst; size_t src, bytes; bool direct; };
 void out_pieces(Job &j, OutPiece (&p)[5]) {
   const Dims &d = j.d;
-  p[0] = {j.res.alpha, j.L.out_alpha, (size_t)d.T * d.M * 4};
-  p[1] = {j.res.post, j.L.out_post, (size_t)d.S * d.T * d.N * 4};
-  p[2] = {j.res.sep, j.L.out_sep, (size_t)d.S * d.T * d.F * 4};
-  p[3] = {d.iters > 0 ? j.res.elbo : nullptr, j.L.out_elbo, (size_t)d.iters * 8};
-  p[4] = {&j.dev_flag, j.L.status, 4};
+  p[0] = {j.res.alpha, j.L.out_alpha, (size_t)d.T * d.M * 4, j.out_direct[0]};
+  p[1] = {j.res.post, j.L.out_post, (size_t)d.S * d.T * d.N * 4, j.out_direct[1]};
+  p[2] = {j.res.sep, j.L.out_sep, (size_t)d.S * d.T * d.F * 4, j.out_direct[2]};
+  p[3] = {d.iters > 0 ? j.res.elbo : nullptr, j.L.out_elbo, (size_t)d.iters * 8, j.out_direct[3]};
+  p[4] = {&j.dev_flag, j.L.status, 4, false};
 }
 
 nfhmm_status download_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
@@ -793,13 +796,17 @@ nfhmm_status download_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
   out_pieces(j, p);
   size_t total = 0;
   for (auto &q : p)
-    if (q.dst) total += (q.bytes + 255) / 256 * 256;
+    if (q.dst && !q.direct) total += (q.bytes + 255) / 256 * 256;
   const size_t off = pin_reserve(ctx, total, nullptr);
   if (off == ~size_t(0)) return download_outputs(j, st);
   j.out_pin = off;
   size_t o = off;
   for (auto &q : p) {
     if (!q.dst) continue;
+    if (q.direct) {
+      HIP_OK(hipMemcpyAsync(q.dst, j.arena + q.src, q.bytes, hipMemcpyDeviceToHost, st));
+      continue;
+    }
     HIP_OK(hipMemcpyAsync(ctx->pin + o, j.arena + q.src, q.bytes, hipMemcpyDeviceToHost, st));
     o += (q.bytes + 255) / 256 * 256;
   }
@@ -815,7 +822,7 @@ void deliver_staged(nfhmm_ctx *ctx, Job &j) {
   CopyPool::Piece pc[5];
   int n = 0;
   for (auto &q : p) {
-    if (!q.dst) continue;
+    if (!q.dst || q.direct) continue;
     pc[n++] = {q.dst, ctx->pin + o, q.bytes};
     o += (q.bytes + 255) / 256 * 256;
   }
@@ -1034,6 +1041,19 @@ nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t 
   return first;
 }
 
+// Is p in pinned (page-locked) host memory?  A pageable pointer is not known to
+// HIP: the query then fails or reports unregistered memory, and its error is
+// cleared so that no later call reports it.
+bool host_pinned(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeHost;
+}
+
 nfhmm_status make_job(const nfhmm_problem *p, nfhmm_precision prec, const nfhmm_result *r, bool host_in,
                       bool host_out, Job &j) {
   std::string why;
@@ -1045,6 +1065,10 @@ nfhmm_status make_job(const nfhmm_problem *p, nfhmm_precision prec, const nfhmm_
   j.res = *r;
   j.host_in = host_in;
   j.host_out = host_out;
+  if (host_out) {
+    const void *outs[4] = {r->alpha, r->post, r->sep, r->elbo};
+    for (int i = 0; i < 4; ++i) j.out_direct[i] = host_pinned(outs[i]);
+  }
   j.L = plan(j.d, host_in, host_out, p->alpha_init != nullptr);
   return NFHMM_OK;
 }

@@ -199,13 +199,22 @@ def _problem_struct(prob, keep):
 OUTPUTS = ("alpha", "post", "sep", "elbo")
 
 
-def _alloc_outputs(prob, keep, outputs=OUTPUTS):
-    """Output arrays of one problem; those not named in `outputs` are skipped (NULL)."""
+def _alloc_outputs(prob, keep, outputs=OUTPUTS, pinned=False):
+    """Output arrays of one problem; those not named in `outputs` are skipped (NULL).
+    With `pinned` they are views of page-locked host memory (torch's pinned
+    allocator), which the library copies into directly."""
     S, N, K, F, T = (int(prob[k]) for k in ("S", "N", "K", "F", "T"))
     it = int(prob["iters"])
     shapes = dict(alpha=((T, S * N * K), np.float32), post=((S, T, N), np.float32),
                   sep=((S, T, F), np.float32), elbo=((max(it, 0),), np.float64))
-    out = {k: np.empty(*shapes[k]) for k in OUTPUTS if k in outputs}
+    if pinned:
+        import torch
+        tdt = {np.float32: torch.float32, np.float64: torch.float64}
+        ts = {k: torch.empty(shapes[k][0], dtype=tdt[shapes[k][1]], pin_memory=True) for k in OUTPUTS if k in outputs}
+        keep.append(ts)
+        out = {k: t.numpy() for k, t in ts.items()}
+    else:
+        out = {k: np.empty(*shapes[k]) for k in OUTPUTS if k in outputs}
     keep.append(out)
     return out, nfhmm_result(_ptr(out.get("alpha")), _ptr(out.get("post")), _ptr(out.get("sep")),
                              _ptr(out.get("elbo")) if it > 0 else None)
@@ -237,19 +246,20 @@ def fit(ctx: Context, prob, precision="fp32"):
     return fit_batch(ctx, [prob], precision)[0]
 
 
-def fit_batch(ctx: Context, probs, precision="fp32"):
-    """nfhmm_fit_batch on host arrays; returns one result dict per problem."""
+def fit_batch(ctx: Context, probs, precision="fp32", pinned=False):
+    """nfhmm_fit_batch on host arrays; returns one result dict per problem (the
+    arrays in pinned host memory with `pinned`)."""
     keep = []
     n = len(probs)
     ps = (nfhmm_problem * n)(*[_problem_struct(p, keep) for p in probs])
     outs, rs = [], []
     for p in probs:
-        o, r = _alloc_outputs(p, keep)
+        o, r = _alloc_outputs(p, keep, OUTPUTS, pinned)
         outs.append(o)
         rs.append(r)
     rarr = (nfhmm_result * n)(*rs)
     _check(_lib.nfhmm_fit_batch(ctx.handle, n, ps, _PREC[precision], rarr), ctx.handle)
-    return outs
+    return outs   # a pinned array's base is its torch tensor, which keeps the memory
 
 
 class DeviceJob:
@@ -310,11 +320,12 @@ class Submitted:
         self._keep = keep
 
 
-def submit(ctx: Context, prob, precision="bf16", outputs=OUTPUTS) -> Submitted:
-    """nfhmm_submit; `outputs` names the results to bring back (the others are NULL)."""
+def submit(ctx: Context, prob, precision="bf16", outputs=OUTPUTS, pinned=False) -> Submitted:
+    """nfhmm_submit; `outputs` names the results to bring back (the others are NULL),
+    into pinned host arrays with `pinned`."""
     keep = []
     ps = _problem_struct(prob, keep)
-    out, r = _alloc_outputs(prob, keep, outputs)
+    out, r = _alloc_outputs(prob, keep, outputs, pinned)
     jid = C.c_uint64()
     _check(_lib.nfhmm_submit(ctx.handle, C.byref(ps), _PREC[precision], C.byref(r), C.byref(jid)), ctx.handle)
     return Submitted(int(jid.value), out, keep)

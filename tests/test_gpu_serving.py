@@ -80,6 +80,29 @@ def test_serving_with_outputs_skipped(L):
         ctx.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_outputs_into_pinned_arrays(L, precision):
+    """Output arrays in pinned host memory are written by a direct copy instead of
+    through the pinned ring; the results are the same bit for bit, in serving and
+    in the blocking host-array call."""
+    probs = _mix()[:4]
+    ctx = L.Context(0)
+    try:
+        ref = [L.fit(ctx, p, precision) for p in probs]
+        pin = [L.fit_batch(ctx, [p], precision, pinned=True)[0] for p in probs]
+        for a, b in zip(ref, pin):
+            _same(a, b)
+        subs = [L.submit(ctx, p, precision, pinned=True) for p in probs]
+        for s, a in zip(subs, ref):
+            _same(L.wait(ctx, s)[0], a)
+        subs = [L.submit(ctx, p, precision, outputs=("sep", "elbo"), pinned=True) for p in probs]
+        for s, a in zip(subs, ref):
+            out, _ = L.wait(ctx, s)
+            assert np.array_equal(out["sep"], a["sep"]) and np.array_equal(out["elbo"], a["elbo"])
+    finally:
+        ctx.close()
+
+
 def test_serving_poll_and_cancel(L):
     ctx = L.Context(0, max_slots=2)
     try:
