@@ -221,6 +221,24 @@ def serving(L, probs, budget_bytes, max_slots, load=0.8, seed=4):
         t0 = time.perf_counter()
         L.fit_batch(ctx, probs, "bf16")
         t_bh = time.perf_counter() - t0
+
+        # the same with the caller's input and output arrays in pinned host
+        # memory: the library copies them directly (no ring, no copy pool)
+        log("serving: the same blocking batch, inputs and outputs in pinned host arrays")
+
+        def _pin(x):
+            t = torch.empty(x.shape, dtype=torch.float32, pin_memory=True)
+            t.numpy()[...] = x
+            return t.numpy()
+        pprobs = [dict(p, **{k: _pin(p[k]) for k in ("V", "W", "A", "pi")}) for p in probs]
+        warm = []
+        for p in probs:
+            L._alloc_outputs(p, warm, L.OUTPUTS, True)
+        del warm
+        t0 = time.perf_counter()
+        L.fit_batch(ctx, pprobs, "bf16", pinned=True)
+        t_bp = time.perf_counter() - t0
+        del pprobs
         djobs = [L.DeviceJob(p) for p in probs]
         L.fit_batch_device(ctx, djobs, "bf16")          # warm: arenas and tables for these shapes
         torch.cuda.synchronize()
@@ -257,6 +275,8 @@ def serving(L, probs, budget_bytes, max_slots, load=0.8, seed=4):
                     "mean_ms": float(lat_ms.mean()), "max_submit_lag_ms": float(max(lags) * 1e3)},
         "blocking_bf16_host_arrays": {"seconds": t_bh, "frame_iterations_per_s": work / t_bh,
                                       "saturated_serving_over_this": t_bh / t_sat},
+        "blocking_bf16_pinned_arrays": {"seconds": t_bp, "frame_iterations_per_s": work / t_bp,
+                                        "note": "inputs and outputs in pinned host memory, copied directly"},
         "blocking_bf16_resident": {"seconds": t_bd, "frame_iterations_per_s": work / t_bd,
                                    "saturated_serving_over_this": t_bd / t_sat},
         "sequential_fp32": {"seconds": t_seq, "frame_iterations_per_s": work / t_seq,

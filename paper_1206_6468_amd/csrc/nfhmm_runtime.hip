@@ -728,17 +728,17 @@ void pin_release(nfhmm_ctx *ctx, size_t off) {
   pin_pop(ctx);
 }
 
-// Copy a host-input job's arrays into its arena.
-nfhmm_status upload_inputs(Job &j, hipStream_t st) {
-  const Dims &d = j.d;
-  char *a = j.arena;
-  HIP_OK(hipMemcpyAsync(a + j.L.V_in, j.prob.V, (size_t)d.T * d.F * 4, hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemcpyAsync(a + j.L.W_in, j.prob.W, (size_t)d.M * d.F * 4, hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemcpyAsync(a + j.L.A_in, j.prob.A, (size_t)d.S * d.N * d.N * 4, hipMemcpyHostToDevice, st));
-  HIP_OK(hipMemcpyAsync(a + j.L.pi_in, j.prob.pi, (size_t)d.S * d.N * 4, hipMemcpyHostToDevice, st));
-  if (j.prob.alpha_init)
-    HIP_OK(hipMemcpyAsync(a + j.L.alpha_init, j.prob.alpha_init, (size_t)d.T * d.M * 4, hipMemcpyHostToDevice, st));
-  return NFHMM_OK;
+// Is p in pinned (page-locked) host memory?  A pageable pointer is not known to
+// HIP: the query then fails or reports unregistered memory, and its error is
+// cleared so that no later call reports it.
+bool host_pinned(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeHost;
 }
 
 nfhmm_status download_outputs(Job &j, hipStream_t st) {
@@ -761,20 +761,35 @@ nfhmm_status upload_staged(nfhmm_ctx *ctx, Job &j, hipStream_t st) {
                         (size_t)d.S * d.N * 4, j.prob.alpha_init ? (size_t)d.T * d.M * 4 : 0};
   const void *src[5] = {j.prob.V, j.prob.W, j.prob.A, j.prob.pi, j.prob.alpha_init};
   const size_t dst[5] = {j.L.V_in, j.L.W_in, j.L.A_in, j.L.pi_in, j.L.alpha_init};
+  // arrays already in pinned memory go up directly (the blocking calls read the
+  // caller's arrays while they run); the others through the ring
+  bool direct[5];
   size_t total = 0, sub[5];
-  for (int i = 0; i < 5; ++i) { sub[i] = total; total += (nb[i] + 255) / 256 * 256; }
+  for (int i = 0; i < 5; ++i) {
+    direct[i] = nb[i] > 0 && host_pinned(src[i]);
+    sub[i] = total;
+    if (!direct[i]) total += (nb[i] + 255) / 256 * 256;
+  }
+  for (int i = 0; i < 5; ++i)
+    if (direct[i]) HIP_OK(hipMemcpyAsync(j.arena + dst[i], src[i], nb[i], hipMemcpyHostToDevice, st));
+  if (total == 0) return NFHMM_OK;
   hipEvent_t ev = nullptr;
   HIP_OK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
   const size_t off = pin_reserve(ctx, total, ev);
   if (off == ~size_t(0)) {
     (void)hipEventDestroy(ev);
-    return upload_inputs(j, st);
+    for (int i = 0; i < 5; ++i)
+      if (nb[i] && !direct[i]) HIP_OK(hipMemcpyAsync(j.arena + dst[i], src[i], nb[i], hipMemcpyHostToDevice, st));
+    return NFHMM_OK;
   }
   CopyPool::Piece pc[5];
-  for (int i = 0; i < 5; ++i) pc[i] = {ctx->pin + off + sub[i], src[i], nb[i]};
-  ctx->copies->run(pc, 5);
+  int np = 0;
   for (int i = 0; i < 5; ++i)
-    if (nb[i]) HIP_OK(hipMemcpyAsync(j.arena + dst[i], ctx->pin + off + sub[i], nb[i], hipMemcpyHostToDevice, st));
+    if (!direct[i]) pc[np++] = {ctx->pin + off + sub[i], src[i], nb[i]};
+  ctx->copies->run(pc, np);
+  for (int i = 0; i < 5; ++i)
+    if (nb[i] && !direct[i])
+      HIP_OK(hipMemcpyAsync(j.arena + dst[i], ctx->pin + off + sub[i], nb[i], hipMemcpyHostToDevice, st));
   HIP_OK(hipEventRecord(ev, st));
   return NFHMM_OK;
 }
@@ -1039,19 +1054,6 @@ nfhmm_status run_blocking(nfhmm_ctx *ctx, std::vector<Job *> &jobs, hipStream_t 
     }
   }
   return first;
-}
-
-// Is p in pinned (page-locked) host memory?  A pageable pointer is not known to
-// HIP: the query then fails or reports unregistered memory, and its error is
-// cleared so that no later call reports it.
-bool host_pinned(const void *p) {
-  if (!p) return false;
-  hipPointerAttribute_t attr;
-  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return attr.type == hipMemoryTypeHost;
 }
 
 nfhmm_status make_job(const nfhmm_problem *p, nfhmm_precision prec, const nfhmm_result *r, bool host_in,

@@ -103,6 +103,38 @@ def test_outputs_into_pinned_arrays(L, precision):
         ctx.close()
 
 
+def _pinned_copy(x):
+    import torch
+    a = np.asarray(x, dtype=np.float32)
+    t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
+    out = t.numpy()
+    out[...] = a
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_inputs_from_pinned_arrays(L, precision):
+    """Input arrays in pinned host memory are copied to the device directly, the
+    rest through the pinned ring; a blocking host-array call gives the same bits
+    whichever way each array went (all pinned, some pinned, a pinned warm start)."""
+    probs = _mix()[:4]
+    ctx = L.Context(0)
+    try:
+        ref = [L.fit(ctx, p, precision) for p in probs]
+        for p, a in zip(probs, ref):
+            allpin = dict(p, **{k: _pinned_copy(p[k]) for k in ("V", "W", "A", "pi")})
+            _same(L.fit(ctx, allpin, precision), a)
+            some = dict(p, V=_pinned_copy(p["V"]), pi=_pinned_copy(p["pi"]))
+            _same(L.fit_batch(ctx, [some], precision, pinned=True)[0], a)
+        warm = dict(probs[0], alpha_init=ref[0]["alpha"])
+        want = L.fit(ctx, warm, precision)
+        got = L.fit(ctx, dict(warm, alpha_init=_pinned_copy(ref[0]["alpha"]),
+                              W=_pinned_copy(warm["W"])), precision)
+        _same(got, want)
+    finally:
+        ctx.close()
+
+
 def test_serving_poll_and_cancel(L):
     ctx = L.Context(0, max_slots=2)
     try:
