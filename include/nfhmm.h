@@ -147,7 +147,8 @@ NFHMM_API int nfhmm_admission_plan(int n_queued, const size_t *footprints, size_
  * Outputs are written to the host arrays of *r.  Copies go through a pinned host
  * ring of the context (1 GiB, allocated on first use; pageable copies when it has
  * no room), and the device working memory stays cached in the context for the
- * next call of the same shapes. */
+ * next call of the same shapes.  An input or output array that is itself in pinned
+ * (page-locked) host memory is copied to or from the device directly instead. */
 NFHMM_API nfhmm_status nfhmm_fit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precision prec,
                        nfhmm_result *r);
 
