@@ -36,10 +36,13 @@ constexpr int kMaxSources = 8;
 
 // Block tiles of the two contractions: 2 x 2 wavefronts of 16*W rows x 16*W
 // columns each.  Lambda (spectrum): bins x frames; counts: elements x frames.
-constexpr int kSpecWM = 4, kSpecWN = 2;
-constexpr int kCntWM = 2, kCntWN = 2;
+constexpr int kSpecWM = 4, kSpecWN = 4;
+constexpr int kCntWM = 2, kCntWN = 2;     // FP32 counts
+constexpr int kCntHWM = 4, kCntHWN = 4;   // BF16 counts
 constexpr int kSpecBM = 32 * kSpecWM, kSpecBN = 32 * kSpecWN;
 constexpr int kCntBM = 32 * kCntWM, kCntBN = 32 * kCntWN;
+constexpr int kCntHBM = 32 * kCntHWM, kCntHBN = 32 * kCntHWN;
+constexpr int kBoundRows = 64;            // rows per partial of the bound's counts term
 constexpr int kSpecSmallBM = 64, kSpecSmallBN = 64;   // spectrum tile for small batches
 constexpr float kEvHeadroomLog = 44.3614195558365f;   // 64 ln 2: ev <= 2^64
 

@@ -31,8 +31,8 @@ constexpr int kStartLamBinsPerBlock = 16;
 hipError_t launch_start_ratio(const WorkList &lam, const WorkList &ratio, hipStream_t st);
 // dst[i] = the status word of job i of wl (device memory, wl.njobs ints)
 hipError_t launch_status_gather(const WorkList &wl, int *dst, hipStream_t st);
-// small: 64 x 64 block tiles (work lists built with kSpecSmallBM / BN) instead of
-// kSpecBM x kSpecBN
+// FP32: 64 x 64 block tiles.  BF16: kSpecBM x kSpecBN, or with small 64 x 64 (work
+// lists built with kSpecSmallBM / BN)
 hipError_t launch_spectrum(const WorkList &wl, bool bf16, bool small, hipStream_t st);
 hipError_t launch_counts(const WorkList &wl, bool bf16, hipStream_t st);
 // Chunked forward-backward: rounds 1 and 2 (one block per source, direction and

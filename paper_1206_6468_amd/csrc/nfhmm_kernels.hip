@@ -367,9 +367,20 @@ __device__ void gemm_nt_f32_dma_kmask(const float *__restrict__ A, int lda, int 
   }
 }
 
+// Wait until at most N vector-memory operations of this wavefront are still in
+// flight (gfx9 s_waitcnt encoding: vmcnt in bits 3:0 and 15:14; expcnt and
+// lgkmcnt left at their no-wait maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt is six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
 // bf16 main loop with the same direct-to-LDS scheme: a k-stage of 64 values is
-// again eight 16-byte chunks per row.  kend is a multiple of 32; a final half
-// stage loads the chunks below kend and stores zeros over the rest.
+// again eight 16-byte chunks per row.  kend is a multiple of 32; in a final half
+// stage the chunks at or past kend load the row's last chunk again (in bounds,
+// and every stage is the same loads), and the A rows' copies are then set to
+// zero in LDS.
 template <int ROWS>
 __device__ __forceinline__ void dma_rows_h(const uint16_t *__restrict__ src, int ld, int nrows, int row0, int k,
                                            int kend, uint16_t *lds, int wave, int lane) {
@@ -380,28 +391,28 @@ __device__ __forceinline__ void dma_rows_h(const uint16_t *__restrict__ src, int
     const int r = g * 8 + (lane >> 3);
     const int ch = (lane & 7) ^ (r & 7);
     const int grow = min(row0 + r, nrows - 1);
-    uint16_t *base = lds + g * 8 * kBKh;
-    if (k + ch * 8 < kend)
-      __builtin_amdgcn_global_load_lds((gcvoid *)(src + (size_t)grow * ld + k + ch * 8), (lvoid *)base, 16, 0, 0);
-    else
-      *(uint4 *)(base + lane * 8) = make_uint4(0, 0, 0, 0);
+    const int kk = min(k + ch * 8, kend - 8);
+    __builtin_amdgcn_global_load_lds((gcvoid *)(src + (size_t)grow * ld + kk), (lvoid *)(lds + g * 8 * kBKh), 16,
+                                     0, 0);
   }
 }
 
+// A stage's fragment reads take this lane's offsets within the stage, formed once
+// per block (ao / bo: A and B rows, one per 32-wide half of the stage's k) and
+// hidden from the optimiser, so that every read address is the stage array plus
+// one offset plus a constant: the LDS lowering then still sees which stage array
+// each read belongs to (it follows only a few levels of address arithmetic), and
+// the compiler's wait before the read counts only the loads into that array.
 template <int WM, int WN>
-__device__ __forceinline__ void mma_stage_bf16_dma(const uint16_t *As, const uint16_t *Bs, const Frag &f,
-                                                   floatx4 (&acc)[WM][WN]) {
-  const int sw = f.lr & 7;
+__device__ __forceinline__ void mma_stage_bf16_dma(const uint16_t *As, const uint16_t *Bs, const int (&ao)[2],
+                                                   const int (&bo)[2], floatx4 (&acc)[WM][WN]) {
 #pragma unroll
-  for (int kk = 0; kk < kBKh; kk += 32) {
-    const int chunk = ((kk >> 3) + f.lq) ^ sw;
+  for (int h = 0; h < 2; ++h) {
     bf16x8 a[WM], b[WN];
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
-      a[i] = *(const bf16x8 *)(As + (f.wr * 16 * WM + i * 16 + f.lr) * kBKh + chunk * 8);
+    for (int i = 0; i < WM; ++i) a[i] = *(const bf16x8 *)(As + ao[h] + i * 16 * kBKh);
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
-      b[j] = *(const bf16x8 *)(Bs + (f.wc * 16 * WN + j * 16 + f.lr) * kBKh + chunk * 8);
+    for (int j = 0; j < WN; ++j) b[j] = *(const bf16x8 *)(Bs + bo[h] + j * 16 * kBKh);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -410,46 +421,83 @@ __device__ __forceinline__ void mma_stage_bf16_dma(const uint16_t *As, const uin
 }
 
 template <int WM, int WN>
+struct Bf16Operands {
+  const uint16_t *A, *B;
+  int lda, arows, row0, ldb, bcols, col0, kend, wave, lane;
+  __device__ __forceinline__ void load(int stage, uint16_t *lds) const {
+    dma_rows_h<32 * WM>(A, lda, arows, row0, stage * kBKh, kend, lds, wave, lane);
+    dma_rows_h<32 * WN>(B, ldb, bcols, col0, stage * kBKh, kend, lds + 32 * WM * kBKh, wave, lane);
+  }
+};
+
+// Two stage buffers, one stage in flight.  Before each stage: this wavefront's
+// loads of it have landed (vmcnt 0), then a barrier without a fence shows that
+// every wavefront's part has landed and that every wavefront is done with the
+// other buffer, which the next stage's loads then refill while this one's MFMAs
+// run.  A final half stage runs after the loop, with its zeros set in LDS.
+template <int WM, int WN>
 __device__ void gemm_nt_bf16_dma(const uint16_t *__restrict__ A, int lda, int arows, int row0,
                                  const uint16_t *__restrict__ B, int ldb, int bcols, int col0, int kend,
                                  floatx4 (&acc)[WM][WN]) {
-  constexpr int BM = 32 * WM, BN = 32 * WN;
-  __shared__ __attribute__((aligned(16))) uint16_t As0[BM * kBKh], As1[BM * kBKh];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs0[BN * kBKh], Bs1[BN * kBKh];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int kStage = 32 * (WM + WN) * kBKh;
+  __shared__ __attribute__((aligned(16))) uint16_t L0[kStage], L1[kStage];
+  const int tid = threadIdx.x;
   const Frag f = frag_of(tid);
+  const Bf16Operands<WM, WN> op{A, B, lda, arows, row0, ldb, bcols, col0, kend, tid >> 6, tid & 63};
 #pragma unroll
   for (int i = 0; i < WM; ++i)
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  dma_rows_h<BM>(A, lda, arows, row0, 0, kend, As0, wave, lane);
-  dma_rows_h<BN>(B, ldb, bcols, col0, 0, kend, Bs0, wave, lane);
-  __syncthreads();
-  for (int k = 0; k < kend; k += 2 * kBKh) {
-    if (k + kBKh < kend) {
-      dma_rows_h<BM>(A, lda, arows, row0, k + kBKh, kend, As1, wave, lane);
-      dma_rows_h<BN>(B, ldb, bcols, col0, k + kBKh, kend, Bs1, wave, lane);
-    }
-    mma_stage_bf16_dma<WM, WN>(As0, Bs0, f, acc);
+  int ao[2], bo[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int chunk = (h * 4 + f.lq) ^ (f.lr & 7);   // every fragment row is 16-aligned: row & 7 = lr & 7
+    ao[h] = (f.wr * 16 * WM + f.lr) * kBKh + chunk * 8;
+    bo[h] = (f.wc * 16 * WN + f.lr) * kBKh + chunk * 8;
+  }
+  __asm__ volatile("" : "+v"(ao[0]), "+v"(ao[1]), "+v"(bo[0]), "+v"(bo[1]));
+  const int nst = (kend + kBKh - 1) / kBKh;
+  const bool half = (kend & (kBKh - 1)) != 0;
+  const int nrun = half ? nst - 1 : nst;
+  if (nst > 0) op.load(0, L0);
+  for (int s = 0; s < nrun; s += 2) {
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (s + 1 < nst) op.load(s + 1, L1);
+    mma_stage_bf16_dma<WM, WN>(L0, L0 + 32 * WM * kBKh, ao, bo, acc);
+    // the MFMAs stay before the next stage's wait and barrier
     __builtin_amdgcn_sched_barrier(0);
-    __syncthreads();
-    if (k + kBKh >= kend) break;
-    if (k + 2 * kBKh < kend) {
-      dma_rows_h<BM>(A, lda, arows, row0, k + 2 * kBKh, kend, As0, wave, lane);
-      dma_rows_h<BN>(B, ldb, bcols, col0, k + 2 * kBKh, kend, Bs0, wave, lane);
-    }
-    mma_stage_bf16_dma<WM, WN>(As1, Bs1, f, acc);
+    if (s + 1 >= nrun) break;
+    wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (s + 2 < nst) op.load(s + 2, L0);
+    mma_stage_bf16_dma<WM, WN>(L1, L1 + 32 * WM * kBKh, ao, bo, acc);
     __builtin_amdgcn_sched_barrier(0);
+  }
+  if (half) {
+    uint16_t *cur = ((nst - 1) & 1) ? L1 : L0;
+    wait_vmcnt<0>();
     __syncthreads();
+    // zero in A's rows the chunks at or past kend: B's copies of its last chunk
+    // then meet zeros
+    const int c0 = (kend & (kBKh - 1)) >> 3;
+    for (int idx = tid; idx < 32 * WM * 8; idx += 256) {
+      const int r = idx >> 3, c = idx & 7;
+      if (c >= c0) *(uint4 *)(cur + r * kBKh + ((c ^ (r & 7)) << 3)) = make_uint4(0, 0, 0, 0);
+    }
+    __syncthreads();
+    mma_stage_bf16_dma<WM, WN>(cur, cur + 32 * WM * kBKh, ao, bo, acc);
   }
 }
 
 // ------------------------------------------------------------------ Eq. 7: Lambda, R
 // Rows l (frequency, [0, Fm)), columns t (frames), k over all M elements.
-// Two block tiles: 128 bins x 64 frames for large batches, 64 x 64 when the batch would not
-// fill the chip.  Either way the per-frame partials of sum V ln Lambda go to one
-// slot per 64 bins (nsl slots), so the bound does not depend on the tile chosen.
-// Two blocks of four wavefronts per CU fit the LDS; the registers are held to that.
+// Block tiles: FP32 64 x 64; BF16 128 bins x 128 frames for large batches (its
+// stages wait on the operand requests from L1 to L2, and the larger tile asks for
+// fewer bytes per flop), 64 x 64 when the batch would not fill the chip.  Either
+// way the per-frame partials of sum V ln Lambda go to one slot per 64 bins (nsl
+// slots), so the bound does not depend on the tile chosen.  Two blocks of four
+// wavefronts per CU fit the LDS; the registers are held to that.
 template <bool kBF16, int WM, int WN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_spectrum(WorkList wl) {
   static_assert(WM == 2 || WM == 4, "a wave row covers 32 or 64 bins");
@@ -527,9 +575,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // ------------------------------------------------------------------ Eq. 6 first term: c
 // Rows k (elements), columns t (frames), contraction over the Fm bins, plus the
 // rank-Ft update of the tail bins in the epilogue.
+// Block tiles: FP32 64 x 64; BF16 128 x 128, for the same reason as the spectrum's
+// (half the operand bytes per flop).  Either way the partials of the bound go to
+// one slot per 64 rows.
 template <bool kBF16>
-__global__ __launch_bounds__(256) void k_counts(WorkList wl) {
-  constexpr int WM = kCntWM, WN = kCntWN, BM = 32 * WM, BN = 32 * WN;
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kBF16 ? 2 : 1))) void k_counts(WorkList wl) {
+  constexpr int WM = kBF16 ? kCntHWM : kCntWM, WN = kBF16 ? kCntHWN : kCntWN, BM = 32 * WM, BN = 32 * WN;
+  static_assert(WM == 2 || WM == 4, "a wave row covers 32 or 64 rows");
+  static_assert(kCntBM == kBoundRows, "the FP32 row tile is one partial slot");
   const int b = xcd_remap(blockIdx.x, wl.total);
   const int jb = find_job(wl.start, wl.njobs, b);
   const JobDesc &J = wl.jobs[jb];
@@ -595,13 +648,18 @@ __global__ __launch_bounds__(256) void k_counts(WorkList wl) {
       d.lo = __shfl_xor(cs.lo, o);
       cs = comp_merge(cs, d);
     }
-    if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
-    __syncthreads();
-    if (f.lq == 0 && f.wr == 0 && t < T) {
-      const Comp tot = comp_merge(cs, part[f.wc][j * 16 + f.lr]);
-      clw[(size_t)rt * T + t] = vf2{tot.hi, tot.lo};
+    if constexpr (WM == 4) {   // a wave row is one 64-row slot
+      const int slot = rt * 2 + f.wr;
+      if (f.lq == 0 && t < T && slot * kBoundRows < Mp) clw[(size_t)slot * T + t] = vf2{cs.hi, cs.lo};
+    } else {                   // the two wave rows form one slot
+      if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
+      __syncthreads();
+      if (f.lq == 0 && f.wr == 0 && t < T) {
+        const Comp tot = comp_merge(cs, part[f.wc][j * 16 + f.lr]);
+        clw[(size_t)rt * T + t] = vf2{tot.hi, tot.lo};
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
 }
 
@@ -1216,7 +1274,7 @@ __device__ __forceinline__ UpdPre update_prelude(const JobDesc &J, int t, int la
   u.chain = comp_zero();
   if (msg) {
     if (Ft > 0) u.vtail = vll[(size_t)nsl * T + t];
-    const int nkt = (Mp + kCntBM - 1) / kCntBM;
+    const int nkt = (Mp + kBoundRows - 1) / kBoundRows;
     for (int r = lane; r < nsl; r += 64) {
       const vf2 v = vll[(size_t)r * T + t];
       Comp d; d.hi = v.x; d.lo = v.y;
@@ -1516,7 +1574,7 @@ __device__ __forceinline__ void update_frame_resident(const JobDesc &J, int t, i
   const int SN = S * N;
   float dq[2] = {0.0f, 0.0f}, fq[2] = {0.0f, 0.0f}, shl = 0.0f;
   vf2 vtail = vf2{0.0f, 0.0f}, pv_sl = vf2{0.0f, 0.0f}, pv_kt = vf2{0.0f, 0.0f}, z_s = vf2{0.0f, 0.0f};
-  const int nkt = (Mp + kCntBM - 1) / kCntBM;   // <= 64 here
+  const int nkt = (Mp + kBoundRows - 1) / kBoundRows;   // <= 64 here
   if (msg) {
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -1818,13 +1876,9 @@ hipError_t launch_start_ratio(const WorkList &lam, const WorkList &ratio, hipStr
 
 hipError_t launch_spectrum(const WorkList &wl, bool bf16, bool small, hipStream_t st) {
   if (wl.total <= 0) return last();
-  if (small) {
-    if (bf16) k_spectrum<true, 2, 2><<<wl.total, 256, 0, st>>>(wl);
-    else k_spectrum<false, 2, 2><<<wl.total, 256, 0, st>>>(wl);
-  } else {
-    if (bf16) k_spectrum<true, kSpecWM, kSpecWN><<<wl.total, 256, 0, st>>>(wl);
-    else k_spectrum<false, kSpecWM, kSpecWN><<<wl.total, 256, 0, st>>>(wl);
-  }
+  if (!bf16) k_spectrum<false, 2, 2><<<wl.total, 256, 0, st>>>(wl);
+  else if (small) k_spectrum<true, 2, 2><<<wl.total, 256, 0, st>>>(wl);
+  else k_spectrum<true, kSpecWM, kSpecWN><<<wl.total, 256, 0, st>>>(wl);
   return last();
 }
 

@@ -170,7 +170,7 @@ Layout plan(const Dims &d, bool host_in, bool host_out, bool has_init) {
   L.lnz = take(S * 8);
   L.post = take(S * T * N * 4);
   L.vll = take(nlt * T * 8);
-  L.clw = take((Mp + kCntBM - 1) / kCntBM * T * 8);
+  L.clw = take((Mp + kBoundRows - 1) / kBoundRows * T * 8);
   L.elbo = take(it * T * 8);
   L.sep = take(S * T * Fp * 4);
   L.status = take(4);
@@ -408,8 +408,8 @@ struct HipRingOps {
 };
 constexpr int kTableSlots = 16;
 
-// below this many 128 x 64 blocks the spectrum runs on 64 x 64 tiles (twice
-// the blocks), so that a small batch still spreads over the 256 CUs
+// below this many 128 x 128 blocks the BF16 spectrum runs on 64 x 64 tiles
+// (four times the blocks), so that a small batch still spreads over the 256 CUs
 constexpr int kSmallBatchBlocks = 256;
 
 int spec_blocks(const JobDesc &D, bool small) {
@@ -420,7 +420,8 @@ int spec_blocks(const JobDesc &D, bool small) {
 int blocks_of(ListKind k, const JobDesc &D, bool bf16, int upd_wpb, bool spec_small) {
   const int ct = (D.T + 63) / 64;       // 64-frame tiles (reconstruction)
   const int spec = spec_blocks(D, spec_small);
-  const int cnt = ((D.Mp + kCntBM - 1) / kCntBM) * ((D.T + kCntBN - 1) / kCntBN);
+  const int cnt = bf16 ? ((D.Mp + kCntHBM - 1) / kCntHBM) * ((D.T + kCntHBN - 1) / kCntHBN)
+                       : ((D.Mp + kCntBM - 1) / kCntBM) * ((D.T + kCntBN - 1) / kCntBN);
   switch (k) {
     case kSpecF: return bf16 ? 0 : spec_blocks(D, true);
     case kSpecH: return bf16 ? spec : 0;
