@@ -335,6 +335,30 @@ def test_batch_mixing_default_and_warm_starts(L, ctx):
             assert np.all(np.isfinite(b["sep"])) and np.all(np.isfinite(b["alpha"])), (prec, j)
 
 
+def test_bf16_large_tiles_equal_alone(L, ctx):
+    """A BF16 batch large enough that each stream lane takes the 128 x 128 spectrum
+    tiles (eight paper-typical jobs per lane), with ragged jobs among them: M off
+    the tile (80, 81, 105; a half k-stage in the spectrum where Mp = 96), F with a
+    tail bin (129) and with a half stage in the counts (70, 96), T off the tile.  Each job equals the
+    same job fitted alone (64 x 64 spectrum tiles) bit for bit in alpha-hat, d-hat
+    and V*, its bound to 1e-12 relative."""
+    paper = [dict(make_problem(1, j), iters=2) for j in range(16)]
+    odd = [dict(make_tiny(S=2, N=5, K=8, F=129, T=333, seed=41, quanta=900), iters=3),
+           dict(make_tiny(S=3, N=5, K=7, F=70, T=150, seed=42, quanta=900), iters=2),
+           dict(make_tiny(S=2, N=4, K=10, F=96, T=77, seed=43, quanta=700), iters=2),
+           dict(make_tiny(S=1, N=9, K=9, F=161, T=260, seed=44, quanta=800), iters=3)]
+    # the engine deals a batch into two lanes by halves: eight paper jobs and two
+    # ragged ones in each
+    probs = paper[:4] + odd[:1] + paper[4:8] + odd[1:2] + paper[8:12] + odd[2:3] + paper[12:] + odd[3:]
+    batch = L.fit_batch(ctx, probs, "bf16")
+    for j in (0, 4, 9, 10, 14, 19):
+        a = L.fit(ctx, probs[j], "bf16")
+        for k in ("alpha", "post", "sep"):
+            assert np.array_equal(a[k], batch[j][k]), (j, k)
+        assert np.allclose(a["elbo"], batch[j]["elbo"], rtol=1e-12, atol=0.0), j
+        assert np.all(np.isfinite(batch[j]["alpha"])) and np.all(np.isfinite(batch[j]["sep"])), j
+
+
 def test_bench_launch_configuration(L, ctx):
     """The bench's configuration: 32 config-1 jobs in one batch (two stream lanes
     of 16).  One step from oracle alpha-hats: sampled jobs against the FP64
