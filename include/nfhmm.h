@@ -235,6 +235,18 @@ typedef struct {
  * NFHMM_E_INVALID.  Inputs are copied; outputs are written on return. */
 NFHMM_API nfhmm_status nfhmm_learn_nhmm(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_result *r);
 
+/* EM of n independent source models in one run (Section 5 learns one model per
+ * speaker), on host arrays checked and copied as for nfhmm_learn_nhmm: every
+ * iteration's kernels cover all problems still iterating in the same launches, so
+ * the sequential forward and backward sweeps of the n chains run side by side.
+ * Problems may differ in every size and iteration count; each problem's results
+ * are bitwise identical to learning it alone.  1 <= n <= 65535; NFHMM_E_INVALID
+ * (naming the problem) if any problem fails the checks, or if the batch's largest
+ * N, F and T together exceed the launch limits (split the batch).  Device memory:
+ * the sum of the problems' working sets. */
+NFHMM_API nfhmm_status nfhmm_learn_nhmm_batch(nfhmm_ctx *ctx, int n, const nfhmm_nhmm_problem *ps,
+                                              nfhmm_nhmm_result *rs);
+
 /* The same on device pointers (inputs and outputs; the structs in host memory),
  * ordered on hip_stream (NULL: the context's stream).  Only the sizes are checked.
  * Blocks until the work is done. */

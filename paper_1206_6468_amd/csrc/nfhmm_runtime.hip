@@ -1795,78 +1795,139 @@ nfhmm_status em_check(const nfhmm_nhmm_problem *p, const nfhmm_nhmm_result *r, b
   return NFHMM_OK;
 }
 
-// One EM run: host or device arrays in and out, the work on st.
-nfhmm_status em_run(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_result *r, bool host, hipStream_t st) {
-  const size_t N = p->N, K = p->K, F = p->F, T = p->T, it = p->iters;
+// Where one EM problem's arrays sit in its arena.
+struct EmLayout {
+  size_t V, W32, th32, A32, pi32, b[2], th[2], lA[2], lpi[2], ll, off, x, la, lgam, gmax, lbn, sI, xpart, gpart,
+      bpart, trace, total;
+};
+
+EmLayout em_layout(const nfhmm_nhmm_problem &p, bool host) {
+  const size_t N = p.N, K = p.K, F = p.F, T = p.T, it = p.iters;
   const size_t nchunk = (T + kEmChunk - 1) / kEmChunk;
+  EmLayout L{};
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off += (b + 255) / 256 * 256; return o; };
   // the caller's float32 arrays (host: copies in the arena), then the working ones
-  const size_t o_V = host ? take(T * F * 4) : ~size_t(0);
-  const size_t o_W32 = take(N * K * F * 4), o_th32 = take(T * N * K * 4), o_A32 = take(N * N * 4),
-               o_pi32 = take(N * 4);
-  size_t o_b[2], o_th[2], o_lA[2], o_lpi[2];
+  L.V = host ? take(T * F * 4) : ~size_t(0);
+  L.W32 = take(N * K * F * 4); L.th32 = take(T * N * K * 4); L.A32 = take(N * N * 4); L.pi32 = take(N * 4);
   for (int i = 0; i < 2; ++i) {
-    o_b[i] = take(N * K * F * 8);
-    o_th[i] = take(T * N * K * 8);
-    o_lA[i] = take(N * N * 4);
-    o_lpi[i] = take(N * 4);
+    L.b[i] = take(N * K * F * 8);
+    L.th[i] = take(T * N * K * 8);
+    L.lA[i] = take(N * N * 4);
+    L.lpi[i] = take(N * 4);
   }
-  const size_t o_ll = take(T * N * 8), o_off = take(T * 8), o_x = take(T * 64 * 4), o_la = take(T * 64 * 4);
-  const size_t o_lgam = take(T * N * 4), o_gmax = take(N * 4);
-  const size_t o_lbn = take(T * 64 * 4), o_sI = take(T * 64 * 4);
-  const size_t o_xpart = take(nchunk * N * 64 * 8), o_gpart = take(nchunk * N * 4);
-  const size_t o_bpart = take(nchunk * N * K * F * 8), o_trace = take(it * 8);
-  Job j;   // only its arena is used: allocated and cached like a fit's
-  j.L.total = off;
-  nfhmm_status s = arena_alloc(ctx, j, true);
-  if (s != NFHMM_OK) return s;
-  char *a = j.arena;
-  auto F32 = [&](size_t o) { return reinterpret_cast<float *>(a + o); };
-  auto F64 = [&](size_t o) { return reinterpret_cast<double *>(a + o); };
-  const hipMemcpyKind in = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  L.ll = take(T * N * 8); L.off = take(T * 8); L.x = take(T * 64 * 4); L.la = take(T * 64 * 4);
+  L.lgam = take(T * N * 4); L.gmax = take(N * 4);
+  L.lbn = take(T * 64 * 4); L.sI = take(T * 64 * 4);
+  L.xpart = take(nchunk * N * 64 * 8); L.gpart = take(nchunk * N * 4);
+  L.bpart = take(nchunk * N * K * F * 8); L.trace = take(it * 8);
+  L.total = off;
+  return L;
+}
+
+// The grids of a batch span the largest sizes in it; their product must fit.
+bool em_batch_fits(const nfhmm_nhmm_problem *ps, int n) {
+  int64_t N = 0, F = 0, T = 0, C = 0;
+  for (int i = 0; i < n; ++i) {
+    N = std::max<int64_t>(N, ps[i].N); F = std::max<int64_t>(F, ps[i].F); T = std::max<int64_t>(T, ps[i].T);
+    C = std::max<int64_t>(C, (ps[i].T + kEmChunk - 1) / kEmChunk);
+  }
+  return T * N < ((int64_t)1 << 31) && (F + 63) / 64 * N * C < ((int64_t)1 << 31);
+}
+
+// EM of n independent problems in one run: host or device arrays in and out, the
+// work on st.  Each problem has its own arena; every iteration's kernels cover all
+// problems still iterating in the same launches.
+nfhmm_status em_run(nfhmm_ctx *ctx, int n, const nfhmm_nhmm_problem *ps, nfhmm_nhmm_result *rs, bool host,
+                    hipStream_t st) {
+  std::vector<EmLayout> lay(n);
+  std::vector<Job> jobs(n);   // only their arenas are used: allocated and cached like a fit's
+  nfhmm_status s = NFHMM_OK;
+  int done = 0;
+  for (; done < n && s == NFHMM_OK; ++done) {
+    lay[done] = em_layout(ps[done], host);
+    jobs[done].L.total = lay[done].total;
+    s = arena_alloc(ctx, jobs[done], true);
+  }
+  if (s != NFHMM_OK) {
+    for (int i = 0; i + 1 < done; ++i) arena_release(ctx, jobs[i], true);
+    return s;
+  }
   hipError_t e = hipSuccess;
   auto cp = [&](void *dst, const void *src, size_t b, hipMemcpyKind k) {
     if (e == hipSuccess) e = hipMemcpyAsync(dst, src, b, k, st);
   };
-  const float *V = host ? F32(o_V) : p->V;
-  if (host) cp(F32(o_V), p->V, T * F * 4, in);
-  cp(F32(o_W32), p->W, N * K * F * 4, in);
-  cp(F32(o_th32), p->theta, T * N * K * 4, in);
-  cp(F32(o_A32), p->A, N * N * 4, in);
-  cp(F32(o_pi32), p->pi, N * 4, in);
-  if (e == hipSuccess)
-    e = launch_em_import((int)N, (int)K, (int)F, (int)T, F32(o_W32), F32(o_th32), F32(o_A32), F32(o_pi32), F64(o_b[0]),
-                         F64(o_th[0]), F32(o_lA[0]), F32(o_lpi[0]), st);
-  for (size_t i = 0; i < it && e == hipSuccess; ++i) {
-    const int c = (int)(i & 1), n = c ^ 1;
-    EmDesc E{};
-    E.N = (int)N; E.K = (int)K; E.F = (int)F; E.T = (int)T; E.nchunk = (int)nchunk;
-    E.V = V;
-    E.beta = F64(o_b[c]); E.theta = F64(o_th[c]); E.lnA = F32(o_lA[c]); E.lnpi = F32(o_lpi[c]);
-    E.beta_new = F64(o_b[n]); E.theta_new = F64(o_th[n]); E.lnA_new = F32(o_lA[n]); E.lnpi_new = F32(o_lpi[n]);
-    E.ll = F64(o_ll); E.off = F64(o_off); E.x = F32(o_x); E.la = F32(o_la);
-    E.lgam = F32(o_lgam); E.gmax = F32(o_gmax);
-    E.lbn = F32(o_lbn); E.sI = F32(o_sI);
-    E.xpart = reinterpret_cast<float2 *>(a + o_xpart); E.gpart = F32(o_gpart);
-    E.bpart = F64(o_bpart); E.trace = F64(o_trace);
-    e = launch_em_frames(E, st);
-    if (e == hipSuccess) e = launch_em_chain(E, (int)i, st);
-    if (e == hipSuccess) e = launch_em_beta(E, st);
+  const hipMemcpyKind in = host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  // descriptors of both parities: iteration i reads parity i & 1 and writes the other
+  std::vector<EmDesc> hd(2 * (size_t)n);
+  EmBatch B{};
+  B.n = n;
+  int max_it = 0;
+  for (int i = 0; i < n; ++i) {
+    const nfhmm_nhmm_problem &p = ps[i];
+    const EmLayout &L = lay[i];
+    char *a = jobs[i].arena;
+    auto F32 = [&](size_t o) { return reinterpret_cast<float *>(a + o); };
+    auto F64 = [&](size_t o) { return reinterpret_cast<double *>(a + o); };
+    const size_t N = p.N, K = p.K, F = p.F, T = p.T;
+    if (host) cp(F32(L.V), p.V, T * F * 4, in);
+    cp(F32(L.W32), p.W, N * K * F * 4, in);
+    cp(F32(L.th32), p.theta, T * N * K * 4, in);
+    cp(F32(L.A32), p.A, N * N * 4, in);
+    cp(F32(L.pi32), p.pi, N * 4, in);
+    if (e == hipSuccess)
+      e = launch_em_import((int)N, (int)K, (int)F, (int)T, F32(L.W32), F32(L.th32), F32(L.A32), F32(L.pi32),
+                           F64(L.b[0]), F64(L.th[0]), F32(L.lA[0]), F32(L.lpi[0]), st);
+    for (int c = 0; c < 2; ++c) {
+      const int nx = c ^ 1;
+      EmDesc &E = hd[(size_t)c * n + i];
+      E.N = (int)N; E.K = (int)K; E.F = (int)F; E.T = (int)T; E.nchunk = (int)((T + kEmChunk - 1) / kEmChunk);
+      E.iters = p.iters;
+      E.V = host ? F32(L.V) : p.V;
+      E.beta = F64(L.b[c]); E.theta = F64(L.th[c]); E.lnA = F32(L.lA[c]); E.lnpi = F32(L.lpi[c]);
+      E.beta_new = F64(L.b[nx]); E.theta_new = F64(L.th[nx]); E.lnA_new = F32(L.lA[nx]); E.lnpi_new = F32(L.lpi[nx]);
+      E.ll = F64(L.ll); E.off = F64(L.off); E.x = F32(L.x); E.la = F32(L.la);
+      E.lgam = F32(L.lgam); E.gmax = F32(L.gmax);
+      E.lbn = F32(L.lbn); E.sI = F32(L.sI);
+      E.xpart = reinterpret_cast<float2 *>(a + L.xpart); E.gpart = F32(L.gpart);
+      E.bpart = F64(L.bpart); E.trace = F64(L.trace);
+    }
+    B.maxN = std::max(B.maxN, (int)N); B.maxK = std::max(B.maxK, (int)K); B.maxF = std::max(B.maxF, (int)F);
+    B.maxT = std::max(B.maxT, (int)T); B.maxChunk = std::max(B.maxChunk, hd[i].nchunk);
+    max_it = std::max(max_it, p.iters);
   }
-  // the learned parameters, as float32, into the staging arrays, then out
-  const int fin = (int)(it & 1);
-  if (e == hipSuccess)
-    e = launch_em_export((int)N, (int)K, (int)F, (int)T, F64(o_b[fin]), F64(o_th[fin]), F32(o_lA[fin]),
-                         F32(o_lpi[fin]), F32(o_W32), F32(o_th32), F32(o_A32), F32(o_pi32), st);
+  EmDesc *dd = nullptr;
+  if (e == hipSuccess) e = hipMallocAsync((void **)&dd, hd.size() * sizeof(EmDesc), st);
+  cp(dd, hd.data(), hd.size() * sizeof(EmDesc), hipMemcpyHostToDevice);
+  for (int it = 0; it < max_it && e == hipSuccess; ++it) {
+    B.d = dd + (size_t)(it & 1) * n;
+    e = launch_em_frames(B, it, st);
+    if (e == hipSuccess) e = launch_em_chain(B, it, st);
+    if (e == hipSuccess) e = launch_em_beta(B, it, st);
+  }
+  // each problem's learned parameters, as float32, into its staging arrays, then out
   const hipMemcpyKind out = host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
-  if (r->W) cp(r->W, F32(o_W32), N * K * F * 4, out);
-  if (r->theta) cp(r->theta, F32(o_th32), T * N * K * 4, out);
-  if (r->A) cp(r->A, F32(o_A32), N * N * 4, out);
-  if (r->pi) cp(r->pi, F32(o_pi32), N * 4, out);
-  if (r->loglik) cp(r->loglik, a + o_trace, it * 8, out);
+  for (int i = 0; i < n; ++i) {
+    const nfhmm_nhmm_problem &p = ps[i];
+    const nfhmm_nhmm_result &r = rs[i];
+    const EmLayout &L = lay[i];
+    char *a = jobs[i].arena;
+    auto F32 = [&](size_t o) { return reinterpret_cast<float *>(a + o); };
+    auto F64 = [&](size_t o) { return reinterpret_cast<double *>(a + o); };
+    const size_t N = p.N, K = p.K, F = p.F, T = p.T;
+    const int fin = p.iters & 1;
+    if (e == hipSuccess)
+      e = launch_em_export((int)N, (int)K, (int)F, (int)T, F64(L.b[fin]), F64(L.th[fin]), F32(L.lA[fin]),
+                           F32(L.lpi[fin]), F32(L.W32), F32(L.th32), F32(L.A32), F32(L.pi32), st);
+    if (r.W) cp(r.W, F32(L.W32), N * K * F * 4, out);
+    if (r.theta) cp(r.theta, F32(L.th32), T * N * K * 4, out);
+    if (r.A) cp(r.A, F32(L.A32), N * N * 4, out);
+    if (r.pi) cp(r.pi, F32(L.pi32), N * 4, out);
+    if (r.loglik) cp(r.loglik, a + L.trace, (size_t)p.iters * 8, out);
+  }
+  if (dd) (void)hipFreeAsync(dd, st);
   const hipError_t es = hipStreamSynchronize(st);
-  arena_release(ctx, j, true);
+  for (int i = 0; i < n; ++i) arena_release(ctx, jobs[i], true);
   HIP_OK(e);
   HIP_OK(es);
   return NFHMM_OK;
@@ -1877,12 +1938,22 @@ nfhmm_status em_run(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_resu
 extern "C" {
 
 nfhmm_status nfhmm_learn_nhmm(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *p, nfhmm_nhmm_result *r) {
+  return nfhmm_learn_nhmm_batch(ctx, 1, p, r);
+}
+
+nfhmm_status nfhmm_learn_nhmm_batch(nfhmm_ctx *ctx, int n, const nfhmm_nhmm_problem *ps, nfhmm_nhmm_result *rs) {
   if (!ctx) return fail(NFHMM_E_INVALID, "ctx is NULL");
+  if (n < 1 || n > kEmMaxBatch || !ps || !rs) return fail(NFHMM_E_INVALID, "bad batch arguments");
   std::string m;
-  if (em_check(p, r, true, &m) != NFHMM_OK) return fail(NFHMM_E_INVALID, "%s", m.c_str());
+  for (int i = 0; i < n; ++i)
+    if (em_check(&ps[i], &rs[i], true, &m) != NFHMM_OK) {
+      if (n == 1) return fail(NFHMM_E_INVALID, "%s", m.c_str());
+      return fail(NFHMM_E_INVALID, "problem %d: %s", i, m.c_str());
+    }
+  if (!em_batch_fits(ps, n)) return fail(NFHMM_E_INVALID, "the batch's largest sizes together are too large: split it");
   HIP_OK(hipSetDevice(ctx->device));
   std::lock_guard<std::mutex> eng(ctx->engine_mu);
-  return em_run(ctx, p, r, true, ctx->stream);
+  return em_run(ctx, n, ps, rs, true, ctx->stream);
 }
 
 nfhmm_status nfhmm_learn_nhmm_device(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *dev_p, nfhmm_nhmm_result *dev_r,
@@ -1892,7 +1963,7 @@ nfhmm_status nfhmm_learn_nhmm_device(nfhmm_ctx *ctx, const nfhmm_nhmm_problem *d
   if (em_check(dev_p, dev_r, false, &m) != NFHMM_OK) return fail(NFHMM_E_INVALID, "%s", m.c_str());
   HIP_OK(hipSetDevice(ctx->device));
   std::lock_guard<std::mutex> eng(ctx->engine_mu);
-  return em_run(ctx, dev_p, dev_r, false, hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream);
+  return em_run(ctx, 1, dev_p, dev_r, false, hip_stream ? reinterpret_cast<hipStream_t>(hip_stream) : ctx->stream);
 }
 
 nfhmm_status nfhmm_chain_posterior(nfhmm_ctx *ctx, int N, int64_t T, const float *logev, const float *A,

@@ -1,5 +1,5 @@
-// EM learning of one source's N-HMM (Section 2.1): descriptor and launchers of
-// the kernels in nhmm_em_kernels.hip.
+// EM learning of a source's N-HMM (Section 2.1), for one source or a batch of
+// independent ones: descriptor and launchers of the kernels in nhmm_em_kernels.hip.
 //
 // Shapes: V [T][F] counts; beta [N][K][F] (each row of F values a distribution);
 // theta [T][N][K] per-frame weights of each state's elements (rows over K sum to
@@ -22,6 +22,7 @@
 namespace nfhmm {
 
 constexpr int kEmMaxK = 32;      // elements per state
+constexpr int kEmMaxBatch = 65535;   // problems per batch (grid y)
 constexpr int kEmChunk = 32;     // frames per partial sum of the beta update's and the xi sums over t
 // ln of the smallest normal double: probabilities (marginals, pairwise marginals,
 // transitions, initial probabilities) below it count as zero, as they are in a
@@ -31,6 +32,7 @@ constexpr float kEmLogTiny = -708.3964185322641f;
 
 struct EmDesc {
   int N, K, F, T, nchunk;
+  int iters;                // the problem's iteration count: later iterations skip it
   const float *V;           // [T][F]
   const double *beta;       // [N][K][F]   parameters this iteration starts from
   const double *theta;      // [T][N][K]
@@ -54,15 +56,25 @@ struct EmDesc {
   double *trace;            // [iters]     ln P(V) of the parameters each iteration started from
 };
 
+// A batch of independent problems: their descriptors for one iteration (device
+// memory, n of them) and the largest sizes among them, which set the grids (grid
+// y is the problem; blocks past a problem's own extent return at once) and the
+// register tiles (KR >= K, NR >= N: the extra terms are exact zeros, so a
+// problem's results do not depend on what else is in the batch).
+struct EmBatch {
+  const EmDesc *d;
+  int n, maxN, maxK, maxF, maxT, maxChunk;
+};
+
 // E-step per (frame, state) -- frame log-likelihoods and the theta update, which
 // needs no chain posterior -- and the chain's log-evidence rows.
-hipError_t launch_em_frames(const EmDesc &E, hipStream_t st);
+hipError_t launch_em_frames(const EmBatch &B, int it, hipStream_t st);
 // The chain in log space (the two sweeps side by side, then gamma and the pairwise
 // marginals over frame chunks): gamma, the new ln A and ln pi, and ln P(V) for
 // iteration `it`.
-hipError_t launch_em_chain(const EmDesc &E, int it, hipStream_t st);
+hipError_t launch_em_chain(const EmBatch &B, int it, hipStream_t st);
 // The beta update (after the chain).
-hipError_t launch_em_beta(const EmDesc &E, hipStream_t st);
+hipError_t launch_em_beta(const EmBatch &B, int it, hipStream_t st);
 // Conversions between the ABI's float32 parameters and the working ones.
 hipError_t launch_em_import(int N, int K, int F, int T, const float *W, const float *theta, const float *A,
                             const float *pi, double *beta, double *th, float *lnA, float *lnpi, hipStream_t st);

@@ -5,7 +5,7 @@
 // weights as nuisance parameters; the steps below are derived from that model.
 //
 // One iteration, from parameters (beta, theta, A, pi):
-//   k_em_frame   per (frame t, state d): P_t(f | d) = sum_z theta_t(d, z) beta(d, z, f),
+//   k_em_frame   per (frame t, state d), one wavefront: P_t(f | d) = sum_z theta_t(d, z) beta(d, z, f),
 //                the frame log-likelihood ll[t][d] = sum_f V_tf ln P_t(f | d) (the
 //                multinomial constant dropped), and the theta update
 //                theta'_t(d, z) ~ theta_t(d, z) sum_f beta(d, z, f) V_tf / P_t(f | d),
@@ -37,72 +37,92 @@
 
 namespace nfhmm {
 
+// The descriptors are read from device memory, so the pointers in them would be
+// generic (flat) to the compiler; every access below goes through these
+// global-memory views instead.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ const gdouble *gptr(const double *p) { return (const gdouble *)p; }
+__device__ __forceinline__ gdouble *gptr(double *p) { return (gdouble *)p; }
+
 __device__ __forceinline__ double wave_sum_d(double x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
   return x;   // the butterfly leaves the same value in every lane
 }
 
-// One block of 256 threads per (frame t, state d); KR >= K elements in registers.
+// One wavefront per (frame t, state d), four per block; KR >= K elements in
+// registers.  In every kernel below grid y is the problem of the batch and `it`
+// the iteration: a problem whose iterations are done, and blocks or wavefronts
+// past its own extent, return.
 template <int KR>
-__global__ __launch_bounds__(256) void k_em_frame(EmDesc E) {
-  const int b = blockIdx.x;
-  const int t = b / E.N, d = b - (b / E.N) * E.N;
-  const int K = E.K, F = E.F, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double th[KR];
-  __shared__ double red[4][KR];
-  __shared__ double redl[4];
+__global__ __launch_bounds__(256) void k_em_frame(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
+  // the wavefront's (frame, state) as a scalar: theta's row then sits in scalar registers
+  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  if (it >= E.iters || w >= E.T * E.N) return;
+  const int t = w / E.N, d = w - (w / E.N) * E.N;
+  const int K = E.K, F = E.F;
   const size_t row = ((size_t)t * E.N + d) * K;
-  if (tid < K) th[tid] = E.theta[row + tid];
-  __syncthreads();
-  const double *bd = E.beta + (size_t)d * K * F;
-  const float *v = E.V + (size_t)t * F;
+  const gdouble *theta = gptr(E.theta);
+  double th[KR];
+#pragma unroll
+  for (int z = 0; z < KR; ++z) th[z] = z < K ? theta[row + z] : 0.0;
+  const gdouble *bd = gptr(E.beta) + (size_t)d * K * F;
+  const gfloat *v = gptr(E.V) + (size_t)t * F;
   double nt[KR];
 #pragma unroll
   for (int z = 0; z < KR; ++z) nt[z] = 0.0;
   double ll = 0.0;
-  for (int f = tid; f < F; f += 256) {
-    const float vv = v[f];
-    if (!(vv > 0.0f)) continue;   // V = 0: no term in ll, no counts to share
+  // the next bin's column of beta and its count are loaded while this bin's are
+  // used (the loads of a bin past F read bin F - 1 and are not used)
+  double bn[KR];
+  float vn;
+  {
+    const int f0 = min(lane, F - 1);
+#pragma unroll
+    for (int z = 0; z < KR; ++z) bn[z] = z < K ? bd[(size_t)z * F + f0] : 0.0;
+    vn = v[f0];
+  }
+  for (int f = lane; f < F; f += 64) {
     double bz[KR];
+#pragma unroll
+    for (int z = 0; z < KR; ++z) bz[z] = bn[z];
+    const float vv = vn;
+    const int fn = min(f + 64, F - 1);
+#pragma unroll
+    for (int z = 0; z < KR; ++z) bn[z] = z < K ? bd[(size_t)z * F + fn] : 0.0;
+    vn = v[fn];
+    if (!(vv > 0.0f)) continue;   // V = 0: no term in ll, no counts to share
     double P = 0.0;
 #pragma unroll
-    for (int z = 0; z < KR; ++z) {
-      bz[z] = z < K ? bd[(size_t)z * F + f] : 0.0;
-      P = fma(z < K ? th[z] : 0.0, bz[z], P);
-    }
+    for (int z = 0; z < KR; ++z) P = fma(th[z], bz[z], P);
     ll += (double)vv * log(P);
     const double R = (double)vv / P;
 #pragma unroll
     for (int z = 0; z < KR; ++z) nt[z] = fma(bz[z], R, nt[z]);
   }
   ll = wave_sum_d(ll);
-  if (lane == 0) redl[wave] = ll;
+  // every lane holds the sums; lane z writes element z of the new weights
+  double tot = 0.0, mine = 0.0;
 #pragma unroll
   for (int z = 0; z < KR; ++z) {
     if (z < K) {
-      const double s = wave_sum_d(nt[z]);
-      if (lane == 0) red[wave][z] = s;
+      const double sz = th[z] * wave_sum_d(nt[z]);
+      tot += sz;
+      if (lane == z) mine = sz;
     }
   }
-  __syncthreads();
-  if (tid == 0) {
-    E.ll[(size_t)t * E.N + d] = ((redl[0] + redl[1]) + redl[2]) + redl[3];
-    double tot = 0.0;
-    for (int z = 0; z < K; ++z) {
-      const double s = th[z] * (((red[0][z] + red[1][z]) + red[2][z]) + red[3][z]);
-      red[0][z] = s;
-      tot += s;
-    }
-    for (int z = 0; z < K; ++z) E.theta_new[row + z] = tot > 0.0 ? red[0][z] / tot : th[z];
-  }
+  if (lane == 0) gptr(E.ll)[(size_t)t * E.N + d] = ll;
+  if (lane < K) gptr(E.theta_new)[row + lane] = tot > 0.0 ? mine / tot : theta[row + lane];
 }
 
 // The chain's log evidence of frame t (one wavefront, lane = state): the frame's
 // log-likelihoods relative to their largest, which off[t] keeps (in double) for
 // ln P(V).
-__global__ __launch_bounds__(64) void k_em_prep(EmDesc E) {
+__global__ __launch_bounds__(64) void k_em_prep(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
   const int t = blockIdx.x, lane = threadIdx.x;
+  if (it >= E.iters || t >= E.T) return;
   const bool live = lane < E.N;
   const double x = live ? E.ll[(size_t)t * E.N + lane] : -INFINITY;
   double m = x;
@@ -131,8 +151,19 @@ __device__ __forceinline__ float lse_lanes(float x, bool live) {
 //             marginals: ln xi_t(i, j) = ln gamma_{t-1}(i) + ln A(i, j) + x_t(j) +
 //             lb_t(j) - s_{t-1}(i).
 // Lane r holds column r of ln A forward and row r backward.
+constexpr int kAhead = 8;   // frames of evidence loaded ahead of the sweep
+
+// The chain's block is one wavefront, and LDS executes a wavefront's operations in
+// issue order, so a read sees every lane's earlier write to buf and a write cannot
+// pass an earlier read: only the compiler must not move them across each other.
+// (A barrier would also wait for every global access in flight -- the evidence
+// loaded ahead and the stored messages.)
+__device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
+
 template <int NR>
-__global__ __launch_bounds__(64) void k_em_chain(EmDesc E, int it) {
+__global__ __launch_bounds__(64) void k_em_chain(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
+  if (it >= E.iters) return;
   const int r = threadIdx.x, N = E.N, T = E.T;
   const bool live = r < N;
   __shared__ float buf[64];
@@ -146,24 +177,46 @@ __global__ __launch_bounds__(64) void k_em_chain(EmDesc E, int it) {
     float la = (live && c > -INFINITY) ? l0 - c : -INFINITY;
     E.la[r] = la;
     z += (double)c;
-    for (int t = 1; t < T; ++t) {
+    // each frame's evidence row is loaded kAhead frames before its step (clamped
+    // to the last frame: always in bounds), in whole rounds of kAhead steps; the
+    // last few steps load their own
+    const gfloat *x = gptr(E.x);
+    gfloat *lag = gptr(E.la);
+    auto step = [&](int t, float xt) {
       buf[r] = la;
-      __syncthreads();
-      float mx = -INFINITY;
+      lds_order();
+      // four independent partial maxima and sums: the dependent chains are NR/4 long
+      float m4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
-      for (int m = 0; m < NR; ++m) mx = fmaxf(mx, buf[m] + col[m]);
+      for (int m = 0; m < NR; ++m) m4[m & 3] = fmaxf(m4[m & 3], buf[m] + col[m]);
+      const float mx = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
       float s = 0.0f;
       if (mx > -INFINITY) {
+        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int m = 0; m < NR; ++m) s += __expf(buf[m] + col[m] - mx);
+        for (int m = 0; m < NR; ++m) s4[m & 3] += __expf(buf[m] + col[m] - mx);
+        s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
       }
-      __syncthreads();
-      const float l = (live && mx > -INFINITY) ? E.x[(size_t)t * 64 + r] + mx + __logf(s) : -INFINITY;
+      lds_order();
+      const float l = (live && mx > -INFINITY) ? xt + mx + __logf(s) : -INFINITY;
       c = lse_lanes(l, live);
       la = (live && c > -INFINITY) ? l - c : -INFINITY;
-      E.la[(size_t)t * 64 + r] = la;
+      lag[(size_t)t * 64 + r] = la;
       z += (double)c;
+    };
+    float xq[kAhead];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) xq[q] = x[(size_t)min(1 + q, T - 1) * 64 + r];
+    int t0 = 1;
+    for (; t0 + kAhead <= T; t0 += kAhead) {
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) {
+        const float xt = xq[q];
+        xq[q] = x[(size_t)min(t0 + q + kAhead, T - 1) * 64 + r];
+        step(t0 + q, xt);
+      }
     }
+    for (; t0 < T; ++t0) step(t0, x[(size_t)t0 * 64 + r]);
     // ln P(V) = sum_t off_t + ln Z of the relative evidence
     double off = 0.0;
     for (int t = r; t < T; t += 64) off += E.off[t];
@@ -175,30 +228,50 @@ __global__ __launch_bounds__(64) void k_em_chain(EmDesc E, int it) {
     for (int j = 0; j < NR; ++j) row[j] = (live && j < N) ? E.lnA[(size_t)r * N + j] : -INFINITY;
     float lb = live ? 0.0f : -INFINITY;
     E.lbn[(size_t)(T - 1) * 64 + r] = lb;
-    for (int t = T - 1; t >= 1; --t) {
-      buf[r] = live ? E.x[(size_t)t * 64 + r] + lb : -INFINITY;
-      __syncthreads();
-      float mx = -INFINITY;
+    const gfloat *x = gptr(E.x);
+    gfloat *sIg = gptr(E.sI), *lbg = gptr(E.lbn);
+    auto step = [&](int t, float xt) {
+      buf[r] = live ? xt + lb : -INFINITY;
+      lds_order();
+      float m4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
-      for (int j = 0; j < NR; ++j) mx = fmaxf(mx, row[j] + buf[j]);
+      for (int j = 0; j < NR; ++j) m4[j & 3] = fmaxf(m4[j & 3], row[j] + buf[j]);
+      const float mx = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
       float s = 0.0f;
       if (mx > -INFINITY) {
+        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int j = 0; j < NR; ++j) s += __expf(row[j] + buf[j] - mx);
+        for (int j = 0; j < NR; ++j) s4[j & 3] += __expf(row[j] + buf[j] - mx);
+        s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
       }
-      __syncthreads();
+      lds_order();
       const float sI = (live && mx > -INFINITY) ? mx + __logf(s) : -INFINITY;
       const float cb = lse_lanes(sI, live);
       lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
-      E.sI[(size_t)(t - 1) * 64 + r] = sI;
-      E.lbn[(size_t)(t - 1) * 64 + r] = lb;
+      sIg[(size_t)(t - 1) * 64 + r] = sI;
+      lbg[(size_t)(t - 1) * 64 + r] = lb;
+    };
+    float xq[kAhead];
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) xq[q] = x[(size_t)max(T - 1 - q, 0) * 64 + r];
+    int t0 = T - 1;
+    for (; t0 - kAhead >= 0; t0 -= kAhead) {
+#pragma unroll
+      for (int q = 0; q < kAhead; ++q) {
+        const float xt = xq[q];
+        xq[q] = x[(size_t)max(t0 - q - kAhead, 0) * 64 + r];
+        step(t0 - q, xt);
+      }
     }
+    for (; t0 >= 1; --t0) step(t0, x[(size_t)t0 * 64 + r]);
   }
 }
 
 // ln gamma_t = la_t + lb_t normalised over the states: one wavefront per frame.
-__global__ __launch_bounds__(64) void k_em_post(EmDesc E) {
+__global__ __launch_bounds__(64) void k_em_post(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
   const int t = blockIdx.x, r = threadIdx.x;
+  if (it >= E.iters || t >= E.T) return;
   const bool live = r < E.N;
   const float g = live ? E.la[(size_t)t * 64 + r] + E.lbn[(size_t)t * 64 + r] : -INFINITY;
   const float cg = lse_lanes(g, live);   // every lane: the reduction reads lane 63
@@ -209,8 +282,11 @@ __global__ __launch_bounds__(64) void k_em_post(EmDesc E) {
 // and a sum S scaled by exp(-M): block (c, i), lane j.  Terms and sums below
 // kEmLogTiny count as zero, as in a double-precision evaluation.  Lane 0 also
 // keeps the chunk's largest ln gamma_t(i).
-__global__ __launch_bounds__(64) void k_em_xi(EmDesc E) {
-  const int c = blockIdx.x, i = blockIdx.y, j = threadIdx.x, N = E.N;
+__global__ __launch_bounds__(64) void k_em_xi(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
+  const int N = E.N;
+  if (it >= E.iters || (int)blockIdx.x >= E.nchunk * N) return;
+  const int c = blockIdx.x / N, i = blockIdx.x - c * N, j = threadIdx.x;
   const bool live = j < N;
   const float aij = live ? E.lnA[(size_t)i * N + j] : -INFINITY;
   const int t0 = c * kEmChunk, t1 = min(E.T, t0 + kEmChunk);
@@ -235,8 +311,10 @@ __global__ __launch_bounds__(64) void k_em_xi(EmDesc E) {
 // Row i of the new ln A from the chunks' sums (merged in chunk order; kept if the
 // row received nothing), ln pi'(i) = ln gamma_0(i), and gmax(i).  One wavefront
 // per row, lane j.
-__global__ __launch_bounds__(64) void k_em_xi_reduce(EmDesc E) {
+__global__ __launch_bounds__(64) void k_em_xi_reduce(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
   const int i = blockIdx.x, j = threadIdx.x, N = E.N;
+  if (it >= E.iters || i >= N) return;
   const bool live = j < N;
   float M = -INFINITY, S = 0.0f, gmx = -INFINITY;
   for (int c = 0; c < E.nchunk; ++c) {
@@ -265,21 +343,27 @@ __global__ __launch_bounds__(64) void k_em_xi_reduce(EmDesc E) {
 // 64-bin tile, block (tile, state d, chunk).  theta_t(d, .) and gamma_t(d) are the
 // same for every lane.  KR >= K elements in registers.
 template <int KR>
-__global__ __launch_bounds__(64) void k_em_beta(EmDesc E) {
-  const int f = blockIdx.x * 64 + threadIdx.x, d = blockIdx.y, c = blockIdx.z;
-  const int K = E.K, F = E.F, N = E.N;
+__global__ __launch_bounds__(64) void k_em_beta(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
+  const int K = E.K, F = E.F, N = E.N, ftiles = (F + 63) / 64;
+  if (it >= E.iters || (int)blockIdx.x >= ftiles * N * E.nchunk) return;
+  // block = (bin tile, state d, frame chunk c)
+  const int ft = blockIdx.x % ftiles, dc = blockIdx.x / ftiles, d = dc % N, c = dc / N;
+  const int f = ft * 64 + threadIdx.x;
   const bool in = f < F;
-  const float gmx = E.gmax[d];
+  const float gmx = gptr(E.gmax)[d];
+  const gdouble *beta = gptr(E.beta), *theta = gptr(E.theta);
+  const gfloat *V = gptr(E.V), *lgam = gptr(E.lgam);
   double bz[KR], acc[KR];
 #pragma unroll
   for (int z = 0; z < KR; ++z) {
-    bz[z] = (in && z < K) ? E.beta[((size_t)d * K + z) * F + f] : 0.0;
+    bz[z] = (in && z < K) ? beta[((size_t)d * K + z) * F + f] : 0.0;
     acc[z] = 0.0;
   }
   const int t0 = c * kEmChunk, t1 = min(E.T, t0 + kEmChunk);
   for (int t = t0; t < t1; ++t) {
-    const float vv = in ? E.V[(size_t)t * F + f] : 0.0f;
-    const double *th = E.theta + ((size_t)t * N + d) * K;
+    const float vv = in ? V[(size_t)t * F + f] : 0.0f;
+    const gdouble *th = theta + ((size_t)t * N + d) * K;
     double tz[KR];
     double P = 0.0;
 #pragma unroll
@@ -289,31 +373,33 @@ __global__ __launch_bounds__(64) void k_em_beta(EmDesc E) {
     }
     // gamma_t(d) relative to the state's largest: the row is normalised over f,
     // so the per-state scale cancels, and frames far below the largest still count
-    const float lg = E.lgam[(size_t)t * N + d];
+    const float lg = lgam[(size_t)t * N + d];
     const double g = lg >= kEmLogTiny ? exp((double)(lg - gmx)) : 0.0;
     const double gr = (vv > 0.0f && g > 0.0) ? g * ((double)vv / P) : 0.0;
 #pragma unroll
     for (int z = 0; z < KR; ++z) acc[z] = fma(tz[z], gr, acc[z]);
   }
   if (in) {
-    double *out = E.bpart + ((size_t)c * N + d) * K * F;
+    gdouble *out = gptr(E.bpart) + ((size_t)c * N + d) * K * F;
     for (int z = 0; z < K; ++z) out[(size_t)z * F + f] = acc[z];
   }
 }
 
 // beta'(d, z, .) for one row (d, z): the chunks' partial sums in order, times
 // beta(d, z, f), normalised over f (the row is kept if it received nothing).
-__global__ __launch_bounds__(256) void k_em_beta_reduce(EmDesc E) {
+__global__ __launch_bounds__(256) void k_em_beta_reduce(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
   const int rw = blockIdx.x, F = E.F, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (it >= E.iters || rw >= E.N * E.K) return;
   const size_t NKF = (size_t)E.N * E.K * F;
   __shared__ double red[4];
   __shared__ double total;
-  const double *brow = E.beta + (size_t)rw * F;
-  double *nrow = E.beta_new + (size_t)rw * F;
+  const gdouble *brow = gptr(E.beta) + (size_t)rw * F, *bpart = gptr(E.bpart);
+  gdouble *nrow = gptr(E.beta_new) + (size_t)rw * F;
   double s = 0.0;
   for (int f = tid; f < F; f += 256) {
     double acc = 0.0;
-    for (int c = 0; c < E.nchunk; ++c) acc += E.bpart[(size_t)c * NKF + (size_t)rw * F + f];
+    for (int c = 0; c < E.nchunk; ++c) acc += bpart[(size_t)c * NKF + (size_t)rw * F + f];
     const double x = brow[f] * acc;
     nrow[f] = x;
     s += x;
@@ -352,37 +438,42 @@ __global__ void k_em_export(int N, int K, int F, int T, const double *beta, cons
   }
 }
 
-hipError_t launch_em_frames(const EmDesc &E, hipStream_t st) {
-  if (E.K <= 4) k_em_frame<4><<<E.T * E.N, 256, 0, st>>>(E);
-  else if (E.K <= 8) k_em_frame<8><<<E.T * E.N, 256, 0, st>>>(E);
-  else if (E.K <= 16) k_em_frame<16><<<E.T * E.N, 256, 0, st>>>(E);
-  else k_em_frame<kEmMaxK><<<E.T * E.N, 256, 0, st>>>(E);
-  k_em_prep<<<E.T, 64, 0, st>>>(E);
+hipError_t launch_em_frames(const EmBatch &B, int it, hipStream_t st) {
+  const dim3 g((unsigned)((B.maxT * B.maxN + 3) / 4), (unsigned)B.n);
+  if (B.maxK <= 4) k_em_frame<4><<<g, 256, 0, st>>>(B.d, it);
+  else if (B.maxK <= 8) k_em_frame<8><<<g, 256, 0, st>>>(B.d, it);
+  else if (B.maxK <= 12) k_em_frame<12><<<g, 256, 0, st>>>(B.d, it);
+  else if (B.maxK <= 16) k_em_frame<16><<<g, 256, 0, st>>>(B.d, it);
+  else if (B.maxK <= 24) k_em_frame<24><<<g, 256, 0, st>>>(B.d, it);
+  else k_em_frame<kEmMaxK><<<g, 256, 0, st>>>(B.d, it);
+  k_em_prep<<<dim3((unsigned)B.maxT, (unsigned)B.n), 64, 0, st>>>(B.d, it);
   return hipGetLastError();
 }
 
-hipError_t launch_em_chain(const EmDesc &E, int it, hipStream_t st) {
-  const int nr = (E.N + 15) & ~15;
-  switch (nr) {
-    case 16: k_em_chain<16><<<2, 64, 0, st>>>(E, it); break;
-    case 32: k_em_chain<32><<<2, 64, 0, st>>>(E, it); break;
-    case 48: k_em_chain<48><<<2, 64, 0, st>>>(E, it); break;
-    case 64: k_em_chain<64><<<2, 64, 0, st>>>(E, it); break;
+hipError_t launch_em_chain(const EmBatch &B, int it, hipStream_t st) {
+  const dim3 g2(2, (unsigned)B.n);
+  switch ((B.maxN + 15) & ~15) {
+    case 16: k_em_chain<16><<<g2, 64, 0, st>>>(B.d, it); break;
+    case 32: k_em_chain<32><<<g2, 64, 0, st>>>(B.d, it); break;
+    case 48: k_em_chain<48><<<g2, 64, 0, st>>>(B.d, it); break;
+    case 64: k_em_chain<64><<<g2, 64, 0, st>>>(B.d, it); break;
     default: return hipErrorInvalidValue;
   }
-  k_em_post<<<E.T, 64, 0, st>>>(E);
-  k_em_xi<<<dim3(E.nchunk, E.N), 64, 0, st>>>(E);
-  k_em_xi_reduce<<<E.N, 64, 0, st>>>(E);
+  k_em_post<<<dim3((unsigned)B.maxT, (unsigned)B.n), 64, 0, st>>>(B.d, it);
+  k_em_xi<<<dim3((unsigned)(B.maxChunk * B.maxN), (unsigned)B.n), 64, 0, st>>>(B.d, it);
+  k_em_xi_reduce<<<dim3((unsigned)B.maxN, (unsigned)B.n), 64, 0, st>>>(B.d, it);
   return hipGetLastError();
 }
 
-hipError_t launch_em_beta(const EmDesc &E, hipStream_t st) {
-  const dim3 g((E.F + 63) / 64, E.N, E.nchunk);
-  if (E.K <= 4) k_em_beta<4><<<g, 64, 0, st>>>(E);
-  else if (E.K <= 8) k_em_beta<8><<<g, 64, 0, st>>>(E);
-  else if (E.K <= 16) k_em_beta<16><<<g, 64, 0, st>>>(E);
-  else k_em_beta<kEmMaxK><<<g, 64, 0, st>>>(E);
-  k_em_beta_reduce<<<E.N * E.K, 256, 0, st>>>(E);
+hipError_t launch_em_beta(const EmBatch &B, int it, hipStream_t st) {
+  const dim3 g((unsigned)((B.maxF + 63) / 64 * B.maxN * B.maxChunk), (unsigned)B.n);
+  if (B.maxK <= 4) k_em_beta<4><<<g, 64, 0, st>>>(B.d, it);
+  else if (B.maxK <= 8) k_em_beta<8><<<g, 64, 0, st>>>(B.d, it);
+  else if (B.maxK <= 12) k_em_beta<12><<<g, 64, 0, st>>>(B.d, it);
+  else if (B.maxK <= 16) k_em_beta<16><<<g, 64, 0, st>>>(B.d, it);
+  else if (B.maxK <= 24) k_em_beta<24><<<g, 64, 0, st>>>(B.d, it);
+  else k_em_beta<kEmMaxK><<<g, 64, 0, st>>>(B.d, it);
+  k_em_beta_reduce<<<dim3((unsigned)(B.maxN * B.maxK), (unsigned)B.n), 256, 0, st>>>(B.d, it);
   return hipGetLastError();
 }
 

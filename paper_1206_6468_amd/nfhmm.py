@@ -41,7 +41,7 @@ SYMBOLS = [
     "nfhmm_wait", "nfhmm_cancel", "nfhmm_chain_posterior", "nfhmm_special_functions",
     "nfhmm_profile_enable", "nfhmm_profile_read", "nfhmm_profile_select", "nfhmm_set_lanes",
     "nfhmm_stft_frames", "nfhmm_stft", "nfhmm_istft", "nfhmm_stft_device", "nfhmm_istft_device",
-    "nfhmm_learn_nhmm", "nfhmm_learn_nhmm_device",
+    "nfhmm_learn_nhmm", "nfhmm_learn_nhmm_batch", "nfhmm_learn_nhmm_device",
 ]
 K_SPECTRUM, K_COUNTS, K_CHAINS, K_UPDATE, K_POSTERIOR = 0, 1, 2, 3, 4
 KERNEL_KINDS = {"spectrum": K_SPECTRUM, "counts": K_COUNTS, "chains": K_CHAINS, "update": K_UPDATE,
@@ -135,6 +135,8 @@ _lib.nfhmm_profile_read.argtypes = [C.c_void_p, C.c_int, _P(C.c_int64), _P(C.c_d
 _lib.nfhmm_profile_read.restype = C.c_int
 _lib.nfhmm_learn_nhmm.argtypes = [C.c_void_p, _P(nfhmm_nhmm_problem), _P(nfhmm_nhmm_result)]
 _lib.nfhmm_learn_nhmm.restype = C.c_int
+_lib.nfhmm_learn_nhmm_batch.argtypes = [C.c_void_p, C.c_int, _P(nfhmm_nhmm_problem), _P(nfhmm_nhmm_result)]
+_lib.nfhmm_learn_nhmm_batch.restype = C.c_int
 _lib.nfhmm_learn_nhmm_device.argtypes = [C.c_void_p, _P(nfhmm_nhmm_problem), _P(nfhmm_nhmm_result), C.c_void_p]
 _lib.nfhmm_learn_nhmm_device.restype = C.c_int
 
@@ -460,20 +462,39 @@ def profile_read(ctx: Context, kind):
     return int(n.value), float(ms.value)
 
 
-def learn_nhmm(ctx: Context, prob, iters=None):
-    """nfhmm_learn_nhmm on host arrays.  prob: V [T][F], W [N][K][F], theta [T][N][K],
-    A [N][N], pi [N] (the starting parameters) and iters; returns dict(W, theta, A, pi,
-    loglik)."""
+def _nhmm_structs(prob, iters, keep):
+    """Host nfhmm_nhmm_problem / result and the output dict of one EM problem."""
     V, W, th, A, pi = (_f32(prob[k]) for k in ("V", "W", "theta", "A", "pi"))
     T, F = V.shape
     N, K = W.shape[0], W.shape[1]
     it = int(prob["iters"] if iters is None else iters)
     out = dict(W=np.empty_like(W), theta=np.empty_like(th), A=np.empty_like(A), pi=np.empty_like(pi),
                loglik=np.empty(it, np.float64))
+    keep.extend([V, W, th, A, pi])
     p = nfhmm_nhmm_problem(N, K, F, T, _ptr(V), _ptr(W), _ptr(th), _ptr(A), _ptr(pi), it)
     r = nfhmm_nhmm_result(*(_ptr(out[k]) for k in ("W", "theta", "A", "pi", "loglik")))
+    return p, r, out
+
+
+def learn_nhmm(ctx: Context, prob, iters=None):
+    """nfhmm_learn_nhmm on host arrays.  prob: V [T][F], W [N][K][F], theta [T][N][K],
+    A [N][N], pi [N] (the starting parameters) and iters; returns dict(W, theta, A, pi,
+    loglik)."""
+    keep = []
+    p, r, out = _nhmm_structs(prob, iters, keep)
     _check(_lib.nfhmm_learn_nhmm(ctx.handle, C.byref(p), C.byref(r)), ctx.handle)
     return out
+
+
+def learn_nhmm_batch(ctx: Context, probs, iters=None):
+    """nfhmm_learn_nhmm_batch on host arrays: one result dict per problem."""
+    keep = []
+    st = [_nhmm_structs(q, iters, keep) for q in probs]
+    n = len(st)
+    ps = (nfhmm_nhmm_problem * n)(*[a for a, _, _ in st])
+    rs = (nfhmm_nhmm_result * n)(*[b for _, b, _ in st])
+    _check(_lib.nfhmm_learn_nhmm_batch(ctx.handle, n, ps, rs), ctx.handle)
+    return [o for _, _, o in st]
 
 
 class DeviceNhmm:

@@ -1,5 +1,5 @@
-"""EM learning of one source's N-HMM on the GPU (nfhmm_learn_nhmm through the C
-ABI) against the FP64 reference of oracle/nhmm_em_oracle.py (the steps derived
+"""EM learning of a source's N-HMM on the GPU (nfhmm_learn_nhmm and its batch form
+through the C ABI) against the FP64 reference of oracle/nhmm_em_oracle.py (the steps derived
 from the model of Section 2.1; the reference is pinned in tests/test_nhmm_em_pins.py).
 
 Both start from the same float32 parameters and run the same number of
@@ -126,3 +126,34 @@ def test_em_rejects_invalid_starts(L, ctx):
             L.learn_nhmm(ctx, bad)
         assert e.value.status == L.E_INVALID and needle in str(e.value)
     assert np.all(np.isfinite(L.learn_nhmm(ctx, p)["loglik"]))
+
+
+def test_em_batch_equals_alone(L, ctx):
+    """A batch of problems that differ in every size and in their iteration counts
+    (states 1 to 40, so the chain's register tile spans all four widths; K from 3
+    to 32): each problem's learned parameters and trace equal learning it alone,
+    bit for bit, and one problem of the batch matches the FP64 reference."""
+    probs = [make_nhmm_problem(0, 11, N=4, K=3, F=24, T=40, iters=8),
+             make_nhmm_problem(1, 12, N=40, K=10, T=300, iters=3),
+             make_nhmm_problem(0, 13, N=7, K=32, F=70, T=131, iters=5),
+             make_nhmm_problem(0, 14, N=1, K=6, F=33, T=50, iters=4),
+             make_nhmm_problem(0, 15, N=20, K=5, F=129, T=77, iters=6)]
+    batch = L.learn_nhmm_batch(ctx, probs)
+    for i, (p, b) in enumerate(zip(probs, batch)):
+        a = L.learn_nhmm(ctx, p)
+        for k in ("W", "theta", "A", "pi", "loglik"):
+            assert np.array_equal(a[k], b[k]), (i, k)
+    e = _errs(batch[2], _oracle(probs[2], probs[2]["iters"]))
+    print(f"\nbatch problem 2 x{probs[2]['iters']}: {_fmt(e)}")
+    for k, tol in TOL.items():
+        assert e[k] <= tol, (k, e[k])
+
+
+def test_em_batch_rejects_a_bad_problem(L, ctx):
+    probs = [make_nhmm_problem(0, 16, N=3, K=2, F=16, T=20, iters=2) for _ in range(3)]
+    bad = dict(probs[2], theta=probs[2]["theta"].copy())
+    bad["theta"][4, 1] = [1.0, 0.0]
+    with pytest.raises(L.NfhmmError) as e:
+        L.learn_nhmm_batch(ctx, probs[:2] + [bad])
+    assert e.value.status == L.E_INVALID and "problem 2" in str(e.value)
+    assert all(np.all(np.isfinite(r["loglik"])) for r in L.learn_nhmm_batch(ctx, probs))
