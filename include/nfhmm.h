@@ -153,12 +153,11 @@ NFHMM_API nfhmm_status nfhmm_fit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_p
                        nfhmm_result *r);
 
 /* Blocking fit of n independent problems (host memory) that run together: every
- * iteration's kernels cover all n jobs in the same launches.  Each job's alpha, post
- * and sep are bitwise identical to fitting it alone.  Its elbo trace may differ in
- * the last bits (relative 1e-12 at most) in BF16: a batch that fills the chip takes
- * the BF16 spectrum contraction in larger tiles, which sums the bound's per-bin
- * terms in another order.  Returns the first failing job's status; the other jobs'
- * outputs are complete. */
+ * iteration's kernels cover all n jobs in the same launches.  Each job's results
+ * (alpha, post, sep and the elbo trace) are bitwise identical to fitting it alone:
+ * a batch that fills the chip takes the BF16 spectrum contraction in larger tiles,
+ * but every tile sums the bound's per-bin terms in the same order.  Returns the
+ * first failing job's status; the other jobs' outputs are complete. */
 NFHMM_API nfhmm_status nfhmm_fit_batch(nfhmm_ctx *ctx, int n, const nfhmm_problem *ps,
                              nfhmm_precision prec, nfhmm_result *rs);
 

@@ -523,7 +523,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
   for (int j = 0; j < WN; ++j) {
     const int t = col0 + f.wc * 16 * WN + j * 16 + f.lr;
-    Comp cs = comp_zero();
+    // one partial per 32 bins (i / 2), so that a 64-bin slot is summed in the same
+    // order whichever tile covers it: the bound does not depend on the batch
+    Comp cs2[WM / 2];
+#pragma unroll
+    for (int h = 0; h < WM / 2; ++h) cs2[h] = comp_zero();
     if (t < T) {
 #pragma unroll
       for (int i = 0; i < WM; ++i) {
@@ -536,7 +540,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             rr[r] = vv[r] > 0.0f ? vv[r] * fast_rcp(lam[r]) : 0.0f;
-            if (vv[r] > 0.0f) comp_add(cs, vv[r] * ln_pos(lam[r]));
+            if (vv[r] > 0.0f) comp_add(cs2[i >> 1], vv[r] * ln_pos(lam[r]));
           }
           if constexpr (kBF16) {
             vu2 h;
@@ -551,15 +555,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
     // reduce over the 4 lane groups that share column t
 #pragma unroll
-    for (int o = 16; o < 64; o <<= 1) {
-      Comp d;
-      d.hi = __shfl_xor(cs.hi, o);
-      d.lo = __shfl_xor(cs.lo, o);
-      cs = comp_merge(cs, d);
-    }
-    if constexpr (WM == 4) {   // a wave row is one 64-bin slot
+    for (int h = 0; h < WM / 2; ++h)
+#pragma unroll
+      for (int o = 16; o < 64; o <<= 1) {
+        Comp d;
+        d.hi = __shfl_xor(cs2[h].hi, o);
+        d.lo = __shfl_xor(cs2[h].lo, o);
+        cs2[h] = comp_merge(cs2[h], d);
+      }
+    const Comp cs = cs2[0];
+    if constexpr (WM == 4) {   // a wave row is one 64-bin slot: its two halves merged as two wave rows are
       const int slot = rt * 2 + f.wr;
-      if (f.lq == 0 && t < T && slot < nsl) vll[(size_t)slot * T + t] = vf2{cs.hi, cs.lo};
+      const Comp tot = comp_merge(cs2[0], cs2[WM / 2 - 1]);
+      if (f.lq == 0 && t < T && slot < nsl) vll[(size_t)slot * T + t] = vf2{tot.hi, tot.lo};
     } else {                   // the two wave rows form one slot
       if (f.lq == 0 && f.wr == 1) part[f.wc][j * 16 + f.lr] = cs;
       __syncthreads();

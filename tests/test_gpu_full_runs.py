@@ -102,9 +102,8 @@ def test_batch_of_jobs_ending_in_different_rounds(L, ctx):
     batch = L.fit_batch(ctx, probs)
     for i, p in enumerate(probs):
         alone = L.fit(ctx, p)
-        for k in ("alpha", "post", "sep"):
+        for k in ("alpha", "post", "sep", "elbo"):
             assert np.array_equal(alone[k], batch[i][k]), (i, k)
-        assert np.allclose(alone["elbo"], batch[i]["elbo"], rtol=1e-12, atol=0.0), i
 
 
 # ------------------------------------------------------------------ a job whose bound is -inf

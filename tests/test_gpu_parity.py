@@ -329,9 +329,8 @@ def test_batch_mixing_default_and_warm_starts(L, ctx):
         batch = L.fit_batch(ctx, probs, prec)
         for j, (p, b) in enumerate(zip(probs, batch)):
             a = L.fit(ctx, p, prec)
-            for k in ("alpha", "post", "sep"):
+            for k in ("alpha", "post", "sep", "elbo"):
                 assert np.array_equal(a[k], b[k]), (prec, j, k)
-            assert np.allclose(a["elbo"], b["elbo"], rtol=1e-12, atol=0.0), (prec, j)
             assert np.all(np.isfinite(b["sep"])) and np.all(np.isfinite(b["alpha"])), (prec, j)
 
 
@@ -340,8 +339,8 @@ def test_bf16_large_tiles_equal_alone(L, ctx):
     tiles (eight paper-typical jobs per lane), with ragged jobs among them: M off
     the tile (80, 81, 105; a half k-stage in the spectrum where Mp = 96), F with a
     tail bin (129) and with a half stage in the counts (70, 96), T off the tile.  Each job equals the
-    same job fitted alone (64 x 64 spectrum tiles) bit for bit in alpha-hat, d-hat
-    and V*, its bound to 1e-12 relative."""
+    same job fitted alone (64 x 64 spectrum tiles) bit for bit: alpha-hat, d-hat, V*
+    and the bound (every tile sums the bound's per-bin terms in the same order)."""
     paper = [dict(make_problem(1, j), iters=2) for j in range(16)]
     odd = [dict(make_tiny(S=2, N=5, K=8, F=129, T=333, seed=41, quanta=900), iters=3),
            dict(make_tiny(S=3, N=5, K=7, F=70, T=150, seed=42, quanta=900), iters=2),
@@ -353,18 +352,17 @@ def test_bf16_large_tiles_equal_alone(L, ctx):
     batch = L.fit_batch(ctx, probs, "bf16")
     for j in (0, 4, 9, 10, 14, 19):
         a = L.fit(ctx, probs[j], "bf16")
-        for k in ("alpha", "post", "sep"):
+        for k in ("alpha", "post", "sep", "elbo"):
             assert np.array_equal(a[k], batch[j][k]), (j, k)
-        assert np.allclose(a["elbo"], batch[j]["elbo"], rtol=1e-12, atol=0.0), j
         assert np.all(np.isfinite(batch[j]["alpha"])) and np.all(np.isfinite(batch[j]["sep"])), j
 
 
 def test_bench_launch_configuration(L, ctx):
     """The bench's configuration: 32 config-1 jobs in one batch (two stream lanes
     of 16).  One step from oracle alpha-hats: sampled jobs against the FP64
-    oracle at the FP32 bounds, and every job bitwise equal to the same job fitted
-    alone (one lane); the bound is held to 1e-12 relative (in BF16 a full batch
-    takes larger spectrum tiles, which sum its per-bin terms in another order)."""
+    oracle at the FP32 bounds, and sampled jobs bitwise equal to the same job
+    fitted alone (one lane), in FP32 and in BF16 (where the full batch takes the
+    larger spectrum tiles)."""
     probs = [make_problem(1, j) for j in range(32)]
     starts = {0: _start_alpha(probs[0], 1), 31: _start_alpha(probs[31], 1)}
     qs = [dict(p, iters=1, alpha_init=starts.get(j, _start_alpha(p, 0))) for j, p in enumerate(probs)]
@@ -380,9 +378,13 @@ def test_bench_launch_configuration(L, ctx):
         assert ea < TOL_A and ed < TOL_D and es < TOL_SEP and el < TOL_L
     for j in (0, 5, 31):
         alone = L.fit(ctx, qs[j])
-        for k in ("alpha", "post", "sep"):
+        for k in ("alpha", "post", "sep", "elbo"):
             assert np.array_equal(alone[k], batch[j][k]), (j, k)
-        assert np.allclose(alone["elbo"], batch[j]["elbo"], rtol=1e-12, atol=0.0)
+    batch = L.fit_batch(ctx, qs, "bf16")
+    for j in (0, 31):
+        alone = L.fit(ctx, qs[j], "bf16")
+        for k in ("alpha", "post", "sep", "elbo"):
+            assert np.array_equal(alone[k], batch[j][k]), ("bf16", j, k)
 
 
 def test_device_path_equals_host_path(L, ctx):
