@@ -66,7 +66,10 @@ __global__ __launch_bounds__(256) void k_em_frame(const EmDesc *__restrict__ Es,
   const gdouble *theta = gptr(E.theta);
   double th[KR];
 #pragma unroll
-  for (int z = 0; z < KR; ++z) th[z] = z < K ? theta[row + z] : 0.0;
+  for (int z = 0; z < KR; ++z) {
+    const double x = theta[row + min(z, K - 1)];
+    th[z] = z < K ? x : 0.0;
+  }
   const gdouble *bd = gptr(E.beta) + (size_t)d * K * F;
   const gfloat *v = gptr(E.V) + (size_t)t * F;
   double nt[KR];
@@ -75,12 +78,14 @@ __global__ __launch_bounds__(256) void k_em_frame(const EmDesc *__restrict__ Es,
   double ll = 0.0;
   // the next bin's column of beta and its count are loaded while this bin's are
   // used (the loads of a bin past F read bin F - 1 and are not used)
+  // rows z >= K load row K - 1 again (no branches around the loads); their theta
+  // is 0, so they add exact zeros to P, and their sums are not used
   double bn[KR];
   float vn;
   {
     const int f0 = min(lane, F - 1);
 #pragma unroll
-    for (int z = 0; z < KR; ++z) bn[z] = z < K ? bd[(size_t)z * F + f0] : 0.0;
+    for (int z = 0; z < KR; ++z) bn[z] = bd[(size_t)min(z, K - 1) * F + f0];
     vn = v[f0];
   }
   for (int f = lane; f < F; f += 64) {
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(256) void k_em_frame(const EmDesc *__restrict__ Es,
     const float vv = vn;
     const int fn = min(f + 64, F - 1);
 #pragma unroll
-    for (int z = 0; z < KR; ++z) bn[z] = z < K ? bd[(size_t)z * F + fn] : 0.0;
+    for (int z = 0; z < KR; ++z) bn[z] = bd[(size_t)min(z, K - 1) * F + fn];
     vn = v[fn];
     if (!(vv > 0.0f)) continue;   // V = 0: no term in ll, no counts to share
     double P = 0.0;
@@ -357,7 +362,9 @@ __global__ __launch_bounds__(64) void k_em_beta(const EmDesc *__restrict__ Es, i
   double bz[KR], acc[KR];
 #pragma unroll
   for (int z = 0; z < KR; ++z) {
-    bz[z] = (in && z < K) ? beta[((size_t)d * K + z) * F + f] : 0.0;
+    // rows z >= K load row K - 1 again (no branches around the loads); theta is 0
+    // for those rows, and their sums are not stored
+    bz[z] = in ? beta[((size_t)d * K + min(z, K - 1)) * F + f] : 0.0;
     acc[z] = 0.0;
   }
   const int t0 = c * kEmChunk, t1 = min(E.T, t0 + kEmChunk);
@@ -368,7 +375,8 @@ __global__ __launch_bounds__(64) void k_em_beta(const EmDesc *__restrict__ Es, i
     double P = 0.0;
 #pragma unroll
     for (int z = 0; z < KR; ++z) {
-      tz[z] = z < K ? th[z] : 0.0;
+      const double x = th[min(z, K - 1)];
+      tz[z] = z < K ? x : 0.0;
       P = fma(tz[z], bz[z], P);
     }
     // gamma_t(d) relative to the state's largest: the row is normalised over f,
