@@ -389,7 +389,7 @@ struct Table {
   WorkList lists[kNumLists];
   int nmax = 1, mpmax = 32, upd_stride = 32;
   // spectrum block tiles: FP32 always 64 x 64 (four blocks per CU; measured 1 %
-  // faster than 128 x 64 for the paper-typical batch); BF16 128 x 64, or 64 x 64
+  // faster than 128 x 64 for the paper-typical batch); BF16 128 x 128, or 64 x 64
   // when the batch would not fill the chip
   bool spec_small = false;
   char *dev = nullptr, *host = nullptr;
