@@ -450,6 +450,7 @@ hipError_t launch_em_frames(const EmBatch &B, int it, hipStream_t st) {
   const dim3 g((unsigned)((B.maxT * B.maxN + 3) / 4), (unsigned)B.n);
   if (B.maxK <= 4) k_em_frame<4><<<g, 256, 0, st>>>(B.d, it);
   else if (B.maxK <= 8) k_em_frame<8><<<g, 256, 0, st>>>(B.d, it);
+  else if (B.maxK <= 10) k_em_frame<10><<<g, 256, 0, st>>>(B.d, it);   // the paper's K
   else if (B.maxK <= 12) k_em_frame<12><<<g, 256, 0, st>>>(B.d, it);
   else if (B.maxK <= 16) k_em_frame<16><<<g, 256, 0, st>>>(B.d, it);
   else if (B.maxK <= 24) k_em_frame<24><<<g, 256, 0, st>>>(B.d, it);
@@ -477,6 +478,7 @@ hipError_t launch_em_beta(const EmBatch &B, int it, hipStream_t st) {
   const dim3 g((unsigned)((B.maxF + 63) / 64 * B.maxN * B.maxChunk), (unsigned)B.n);
   if (B.maxK <= 4) k_em_beta<4><<<g, 64, 0, st>>>(B.d, it);
   else if (B.maxK <= 8) k_em_beta<8><<<g, 64, 0, st>>>(B.d, it);
+  else if (B.maxK <= 10) k_em_beta<10><<<g, 64, 0, st>>>(B.d, it);
   else if (B.maxK <= 12) k_em_beta<12><<<g, 64, 0, st>>>(B.d, it);
   else if (B.maxK <= 16) k_em_beta<16><<<g, 64, 0, st>>>(B.d, it);
   else if (B.maxK <= 24) k_em_beta<24><<<g, 64, 0, st>>>(B.d, it);
