@@ -500,8 +500,13 @@ struct nfhmm_ctx {
   bool pin_tried = false;
   std::deque<PinRegion> pin_regs;
   // host copies (serving inputs at submit; the ring on both sides), made on the
-  // first submit or host-array fit
-  static constexpr int kCopyWorkers = 7;
+  // first submit or host-array fit: eleven workers beside the calling thread
+  // (measured: 7 -> 11 raised saturated serving from pageable arrays by about
+  // 10 %, 15 no further), fewer on a host with fewer cores
+  static int copy_workers() {
+    const int hc = (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(11, hc > 2 ? hc - 2 : 1));
+  }
   std::unique_ptr<CopyPool> copies;
 
   // measurement: (kind, start, end) event triples of timed launches
@@ -1396,7 +1401,7 @@ nfhmm_status nfhmm_fit_batch(nfhmm_ctx *ctx, int n, const nfhmm_problem *ps, nfh
   }
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (!ctx->copies) ctx->copies.reset(new CopyPool(nfhmm_ctx::kCopyWorkers));
+    if (!ctx->copies) ctx->copies.reset(new CopyPool(nfhmm_ctx::copy_workers()));
   }
   std::lock_guard<std::mutex> eng(ctx->engine_mu);
   nfhmm_status s = NFHMM_OK;
@@ -1522,7 +1527,7 @@ nfhmm_status nfhmm_submit(nfhmm_ctx *ctx, const nfhmm_problem *p, nfhmm_precisio
   const Dims &d = j->d;
   {
     std::lock_guard<std::mutex> lk(ctx->mu);
-    if (!ctx->copies) ctx->copies.reset(new CopyPool(nfhmm_ctx::kCopyWorkers));
+    if (!ctx->copies) ctx->copies.reset(new CopyPool(nfhmm_ctx::copy_workers()));
   }
   // the caller may reuse its arrays once submit returns: take copies
   const size_t nV = (size_t)d.T * d.F, nW = (size_t)d.M * d.F, nA = (size_t)d.S * d.N * d.N,
