@@ -236,10 +236,14 @@ NFHMM_API nfhmm_status nfhmm_learn_nhmm(nfhmm_ctx *ctx, const nfhmm_nhmm_problem
 
 /* EM of n independent source models in one run (Section 5 learns one model per
  * speaker), on host arrays checked and copied as for nfhmm_learn_nhmm: every
- * iteration's kernels cover all problems still iterating in the same launches, so
- * the sequential forward and backward sweeps of the n chains run side by side.
- * Problems may differ in every size and iteration count; each problem's results
- * are bitwise identical to learning it alone.  1 <= n <= 65535; NFHMM_E_INVALID
+ * iteration's kernels cover all problems still iterating in the same launches.
+ * The forward-backward of a chain of T >= 98 frames runs time-parallel (chunks of
+ * 32 frames, N times the work) while the batch holds at most 2^19 state-frames
+ * (sum of N * T); in larger batches every chain takes the sequential sweeps, side
+ * by side.  Problems may differ in every size and iteration count; each problem's
+ * results are bitwise identical to learning it alone when the batch and the
+ * problem alone fall on the same side of that line, and equal up to rounding
+ * otherwise.  1 <= n <= 65535; NFHMM_E_INVALID
  * (naming the problem) if any problem fails the checks, or if the batch's largest
  * N, F and T together exceed the launch limits (split the batch).  Device memory:
  * the sum of the problems' working sets. */

@@ -1803,10 +1803,29 @@ nfhmm_status em_check(const nfhmm_nhmm_problem *p, const nfhmm_nhmm_result *r, b
 // Where one EM problem's arrays sit in its arena.
 struct EmLayout {
   size_t V, W32, th32, A32, pi32, b[2], th[2], lA[2], lpi[2], ll, off, x, la, lgam, gmax, lbn, sI, xpart, gpart,
-      bpart, trace, total;
+      bpart, trace, tm, tz, ts, total;
+  int nsw;
 };
 
-EmLayout em_layout(const nfhmm_nhmm_problem &p, bool host) {
+// The forward-backward runs time-parallel (in chunks of kEmSweepChunk frames) for
+// chains of at least four chunks, when the whole batch's chains are too few to
+// fill the GPU: it costs N times the sequential sweep's work, spread over N times
+// as many wavefronts.  Past about 2^19 state-frames the sequential sweeps of the
+// batch's problems, side by side, take less time.  The choice depends on the
+// batch (a problem's results then agree with learning it alone to rounding, not
+// bit for bit, when a batch crosses that line and the problem alone does not).
+constexpr int64_t kEmSweepWork = (int64_t)1 << 19;
+int em_sweep_chunks(const nfhmm_nhmm_problem &p, int64_t batch_work) {
+  const int c = (p.T - 1 + kEmSweepChunk - 1) / kEmSweepChunk;
+  return (batch_work <= kEmSweepWork && c >= 4) ? c : 0;
+}
+int64_t em_batch_work(const nfhmm_nhmm_problem *ps, int n) {
+  int64_t w = 0;
+  for (int i = 0; i < n; ++i) w += (int64_t)ps[i].N * ps[i].T;
+  return w;
+}
+
+EmLayout em_layout(const nfhmm_nhmm_problem &p, bool host, int nsw) {
   const size_t N = p.N, K = p.K, F = p.F, T = p.T, it = p.iters;
   const size_t nchunk = (T + kEmChunk - 1) / kEmChunk;
   EmLayout L{};
@@ -1826,6 +1845,9 @@ EmLayout em_layout(const nfhmm_nhmm_problem &p, bool host) {
   L.lbn = take(T * 64 * 4); L.sI = take(T * 64 * 4);
   L.xpart = take(nchunk * N * 64 * 8); L.gpart = take(nchunk * N * 4);
   L.bpart = take(nchunk * N * K * F * 8); L.trace = take(it * 8);
+  const size_t C = (size_t)nsw;
+  L.nsw = nsw;
+  L.tm = take(2 * C * N * 64 * 8); L.tz = take(2 * C * 64 * 8); L.ts = take(2 * C * 64 * 4);
   L.total = off;
   return L;
 }
@@ -1849,8 +1871,9 @@ nfhmm_status em_run(nfhmm_ctx *ctx, int n, const nfhmm_nhmm_problem *ps, nfhmm_n
   std::vector<Job> jobs(n);   // only their arenas are used: allocated and cached like a fit's
   nfhmm_status s = NFHMM_OK;
   int done = 0;
+  const int64_t work = em_batch_work(ps, n);
   for (; done < n && s == NFHMM_OK; ++done) {
-    lay[done] = em_layout(ps[done], host);
+    lay[done] = em_layout(ps[done], host, em_sweep_chunks(ps[done], work));
     jobs[done].L.total = lay[done].total;
     s = arena_alloc(ctx, jobs[done], true);
   }
@@ -1896,9 +1919,11 @@ nfhmm_status em_run(nfhmm_ctx *ctx, int n, const nfhmm_nhmm_problem *ps, nfhmm_n
       E.lbn = F32(L.lbn); E.sI = F32(L.sI);
       E.xpart = reinterpret_cast<float2 *>(a + L.xpart); E.gpart = F32(L.gpart);
       E.bpart = F64(L.bpart); E.trace = F64(L.trace);
+      E.nsw = L.nsw; E.tm = F64(L.tm); E.tz = F64(L.tz); E.ts = F32(L.ts);
     }
     B.maxN = std::max(B.maxN, (int)N); B.maxK = std::max(B.maxK, (int)K); B.maxF = std::max(B.maxF, (int)F);
     B.maxT = std::max(B.maxT, (int)T); B.maxChunk = std::max(B.maxChunk, hd[i].nchunk);
+    B.maxSw = std::max(B.maxSw, L.nsw); B.anySeq = B.anySeq || L.nsw == 0;
     max_it = std::max(max_it, p.iters);
   }
   EmDesc *dd = nullptr;

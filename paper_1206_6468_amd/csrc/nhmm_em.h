@@ -24,6 +24,7 @@ namespace nfhmm {
 constexpr int kEmMaxK = 32;      // elements per state
 constexpr int kEmMaxBatch = 65535;   // problems per batch (grid y)
 constexpr int kEmChunk = 32;     // frames per partial sum of the beta update's and the xi sums over t
+constexpr int kEmSweepChunk = 32;   // frames per chunk of the time-parallel forward-backward
 // ln of the smallest normal double: probabilities (marginals, pairwise marginals,
 // transitions, initial probabilities) below it count as zero, as they are in a
 // double-precision evaluation of the same updates -- where a state or a
@@ -32,6 +33,7 @@ constexpr float kEmLogTiny = -708.3964185322641f;
 
 struct EmDesc {
   int N, K, F, T, nchunk;
+  int nsw;                  // chunks of the time-parallel forward-backward (0: the sequential one)
   int iters;                // the problem's iteration count: later iterations skip it
   const float *V;           // [T][F]
   const double *beta;       // [N][K][F]   parameters this iteration starts from
@@ -54,6 +56,9 @@ struct EmDesc {
   float *gpart;             // [nchunk][N] per frame chunk: max ln gamma_t(i)
   double *bpart;            // [nchunk][N][K][F] partial sums over frame chunks of the beta update
   double *trace;            // [iters]     ln P(V) of the parameters each iteration started from
+  double *tm;               // [2][nsw][N][64] per direction and chunk: transfer columns (linear, each sums to 1)
+  double *tz;               // [2][nsw][64]    their log scales
+  float *ts;                // [2][nsw][64]    each chunk's start message
 };
 
 // A batch of independent problems: their descriptors for one iteration (device
@@ -64,14 +69,16 @@ struct EmDesc {
 struct EmBatch {
   const EmDesc *d;
   int n, maxN, maxK, maxF, maxT, maxChunk;
+  int maxSw;     // the most sweep chunks of a problem (0: none is time-parallel)
+  bool anySeq;   // some problem takes the sequential forward-backward
 };
 
 // E-step per (frame, state) -- frame log-likelihoods and the theta update, which
 // needs no chain posterior -- and the chain's log-evidence rows.
 hipError_t launch_em_frames(const EmBatch &B, int it, hipStream_t st);
-// The chain in log space (the two sweeps side by side, then gamma and the pairwise
-// marginals over frame chunks): gamma, the new ln A and ln pi, and ln P(V) for
-// iteration `it`.
+// The chain (the forward-backward, sequential or time-parallel per problem, then
+// gamma and the pairwise marginals over frame chunks): gamma, the new ln A and
+// ln pi, and ln P(V) for iteration `it`.
 hipError_t launch_em_chain(const EmBatch &B, int it, hipStream_t st);
 // The beta update (after the chain).
 hipError_t launch_em_beta(const EmBatch &B, int it, hipStream_t st);

@@ -11,9 +11,10 @@
 //                theta'_t(d, z) ~ theta_t(d, z) sum_f beta(d, z, f) V_tf / P_t(f | d),
 //                which needs no chain posterior (gamma_t(d) is a common factor)
 //   k_em_prep    the chain's log evidence ll - max_d ll per frame
-//   k_em_chain   the two sweeps of the forward-backward in log space, side by side
-//                (one wavefront each): the forward messages and ln P(V), the
-//                backward messages
+//   k_em_chain   the two sweeps of the forward-backward, side by side (one
+//                wavefront each): the forward messages and ln P(V), the backward
+//                messages; or the same, time-parallel: k_em_sweep_cols,
+//                k_em_sweep_scan, k_em_sweep_fin
 //   k_em_post    ln gamma_t(d) from the two messages, one wavefront per frame
 //   k_em_xi      the pairwise marginals xi_t(i, j) summed over the frames of a
 //                chunk in log space (running maximum and scaled sum), per (chunk,
@@ -145,130 +146,322 @@ __device__ __forceinline__ float lse_lanes(float x, bool live) {
   return mx + __logf(wave_sum(live ? __expf(x - mx) : 0.0f));
 }
 
-// The forward-backward of the source chain in log space: block 0 sweeps forward,
-// block 1 backward, each one wavefront with lane r = state r and messages
-// normalised per frame (no value is flushed: the smallest probabilities the
-// iterations need are far below the float32 range).
-//   forward   la_t(n) = x_t(n) + lse_m(la_{t-1}(m) + ln A(m, n)), la_0 = ln pi + x_0;
+// The forward-backward of the source chain, lane r = state r, messages kept as
+// logarithms normalised per frame (the smallest probabilities the iterations
+// need are far below the float32 range):
+//   forward   la_t(n) = x_t(n) + ln sum_m exp(la_{t-1}(m)) A(m, n), la_0 = ln pi + x_0;
 //             ln Z = the sum of the frames' normalisers
-//   backward  s_{t-1}(i) = lse_j(ln A(i, j) + x_t(j) + lb_t(j)), lb_{t-1} = s_{t-1}
+//   backward  s_{t-1}(i) = ln sum_j A(i, j) exp(x_t(j) + lb_t(j)), lb_{t-1} = s_{t-1}
 //             normalised, lb_{T-1} = 0; both are stored, s for the pairwise
 //             marginals: ln xi_t(i, j) = ln gamma_{t-1}(i) + ln A(i, j) + x_t(j) +
 //             lb_t(j) - s_{t-1}(i).
-// Lane r holds column r of ln A forward and row r backward.
+// Each step takes the messages out of log space for its sums: one double
+// exponential per lane, the N products with A in double by FMAs, then one
+// logarithm.  A term counts as zero only below e^-708 of the largest, as in a
+// double evaluation.
+//
+// Two schedules.  k_em_chain runs the two sweeps side by side, one wavefront each,
+// T dependent steps.  The time-parallel one cuts each sweep into chunks of
+// kEmSweepChunk frames and uses that a sweep is linear in its message:
+//   k_em_sweep_cols  wavefront (direction, chunk, state m) sweeps the chunk from
+//                    the unit message of m: the chunk's transfer column (end
+//                    message, normalised, linear) and its log scale
+//   k_em_sweep_scan  one wavefront per direction carries the true message across
+//                    the chunks with those columns, storing each chunk's start
+//                    message (and ln P(V))
+//   k_em_sweep_fin   wavefront (direction, chunk) sweeps its chunk again from that
+//                    start, storing the messages
+// The critical path is about 2 kEmSweepChunk + T / kEmSweepChunk steps instead of
+// T, for N times the work; the runtime picks it for batches too small to fill the
+// GPU.  Both give the same messages up to rounding: no term is dropped that a
+// double evaluation keeps.
 constexpr int kAhead = 8;   // frames of evidence loaded ahead of the sweep
 
-// The chain's block is one wavefront, and LDS executes a wavefront's operations in
+// A sweep's block is one wavefront, and LDS executes a wavefront's operations in
 // issue order, so a read sees every lane's earlier write to buf and a write cannot
 // pass an earlier read: only the compiler must not move them across each other.
 // (A barrier would also wait for every global access in flight -- the evidence
 // loaded ahead and the stored messages.)
 __device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
 
+// Forward steps t = t0 .. t1-1 from la, the normalised message of frame t0-1 (its
+// largest entry is at least -ln N, so its exponentials need no shift).  ac is
+// column r of A.  Returns the sum of the normalisers; STORE keeps the messages.
+// Each frame's evidence row is loaded kAhead frames before its step (clamped to
+// the last frame: always in bounds), in whole rounds of kAhead steps; the last
+// few steps load their own.
+template <int NR, bool STORE>
+__device__ __forceinline__ double fwd_steps(const gfloat *x, gfloat *lag, const double (&ac)[NR], double *pbuf,
+                                            bool live, int r, int t0, int t1, int T, float &la) {
+  double z = 0.0;
+  auto step = [&](int t, float xt) {
+    pbuf[r] = (live && la > -INFINITY) ? exp((double)la) : 0.0;
+    lds_order();
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < NR; ++m) s4[m & 3] = fma(pbuf[m], ac[m], s4[m & 3]);
+    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    lds_order();
+    const float l = (live && s > 0.0) ? xt + (float)log(s) : -INFINITY;
+    const float c = lse_lanes(l, live);
+    la = (live && c > -INFINITY) ? l - c : -INFINITY;
+    if (STORE) lag[(size_t)t * 64 + r] = la;
+    z += (double)c;
+  };
+  float xq[kAhead];
+#pragma unroll
+  for (int q = 0; q < kAhead; ++q) xq[q] = x[(size_t)min(t0 + q, T - 1) * 64 + r];
+  int t = t0;
+  for (; t + kAhead <= t1; t += kAhead) {
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      const float xt = xq[q];
+      xq[q] = x[(size_t)min(t + q + kAhead, T - 1) * 64 + r];
+      step(t + q, xt);
+    }
+  }
+  for (; t < t1; ++t) step(t, x[(size_t)t * 64 + r]);
+  return z;
+}
+
+// Backward steps t = t0, t0-1, .., t1+1 from lb, the message of frame t0; each
+// gives s_{t-1} and lb_{t-1}.  ar is row r of A.  Returns the sum of the
+// normalisers; STORE keeps s and the messages.  Evidence is loaded ahead as above
+// (clamped to frame 0).
+template <int NR, bool STORE>
+__device__ __forceinline__ double bwd_steps(const gfloat *x, gfloat *sIg, gfloat *lbg, const double (&ar)[NR],
+                                            double *pbuf, bool live, int r, int t0, int t1, float &lb) {
+  double z = 0.0;
+  auto step = [&](int t, float xt) {
+    // evidence times message, relative to its largest entry (the evidence alone
+    // can lie far below the range of an exponential)
+    const float q = live ? xt + lb : -INFINITY;
+    const float mq = wave_max(q);
+    pbuf[r] = (q > -INFINITY) ? exp((double)(q - mq)) : 0.0;
+    lds_order();
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < NR; ++j) s4[j & 3] = fma(ar[j], pbuf[j], s4[j & 3]);
+    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    lds_order();
+    const float sI = (live && s > 0.0 && mq > -INFINITY) ? mq + (float)log(s) : -INFINITY;
+    const float cb = lse_lanes(sI, live);
+    lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
+    if (STORE) {
+      sIg[(size_t)(t - 1) * 64 + r] = sI;
+      lbg[(size_t)(t - 1) * 64 + r] = lb;
+    }
+    z += (double)cb;
+  };
+  float xq[kAhead];
+#pragma unroll
+  for (int q = 0; q < kAhead; ++q) xq[q] = x[(size_t)max(t0 - q, 0) * 64 + r];
+  int t = t0;
+  for (; t - kAhead >= t1; t -= kAhead) {
+#pragma unroll
+    for (int q = 0; q < kAhead; ++q) {
+      const float xt = xq[q];
+      xq[q] = x[(size_t)max(t - q - kAhead, 0) * 64 + r];
+      step(t - q, xt);
+    }
+  }
+  for (; t > t1; --t) step(t, x[(size_t)t * 64 + r]);
+  return z;
+}
+
+// Column r (forward) or row r (backward) of A, in double; zero past N.
+template <int NR>
+__device__ __forceinline__ void a_lane(const float *lnA, int N, int r, bool col, double (&a)[NR]) {
+  const bool live = r < N;
+#pragma unroll
+  for (int j = 0; j < NR; ++j)
+    a[j] = (live && j < N) ? exp((double)lnA[col ? (size_t)j * N + r : (size_t)r * N + j]) : 0.0;
+}
+
+// The normalised first forward message, and its normaliser.
+__device__ __forceinline__ float fwd_first(const EmDesc &E, bool live, int r, double &z) {
+  const float l0 = live ? E.lnpi[r] + E.x[r] : -INFINITY;
+  const float c = lse_lanes(l0, live);
+  z = (double)c;
+  return (live && c > -INFINITY) ? l0 - c : -INFINITY;
+}
+
+// ln P(V) = sum_t off_t + ln Z of the relative evidence
+__device__ __forceinline__ void put_trace(const EmDesc &E, int it, int r, double z) {
+  double off = 0.0;
+  for (int t = r; t < E.T; t += 64) off += E.off[t];
+  off = wave_sum_d(off);
+  if (r == 0) E.trace[it] = off + z;
+}
+
+// The sequential schedule: block 0 sweeps forward, block 1 backward (problems on
+// the time-parallel one return).
 template <int NR>
 __global__ __launch_bounds__(64) void k_em_chain(const EmDesc *__restrict__ Es, int it) {
   const EmDesc &E = Es[blockIdx.y];
-  if (it >= E.iters) return;
+  if (it >= E.iters || E.nsw > 0) return;
   const int r = threadIdx.x, N = E.N, T = E.T;
   const bool live = r < N;
-  __shared__ float buf[64];
+  __shared__ double pbuf[64];
+  double a[NR];
   if (blockIdx.x == 0) {
-    float col[NR];
-#pragma unroll
-    for (int m = 0; m < NR; ++m) col[m] = (live && m < N) ? E.lnA[(size_t)m * N + r] : -INFINITY;
-    double z = 0.0;
-    const float l0 = live ? E.lnpi[r] + E.x[r] : -INFINITY;
-    float c = lse_lanes(l0, live);
-    float la = (live && c > -INFINITY) ? l0 - c : -INFINITY;
+    a_lane<NR>(E.lnA, N, r, true, a);
+    double z;
+    float la = fwd_first(E, live, r, z);
     E.la[r] = la;
-    z += (double)c;
-    // each frame's evidence row is loaded kAhead frames before its step (clamped
-    // to the last frame: always in bounds), in whole rounds of kAhead steps; the
-    // last few steps load their own
-    const gfloat *x = gptr(E.x);
-    gfloat *lag = gptr(E.la);
-    auto step = [&](int t, float xt) {
-      buf[r] = la;
-      lds_order();
-      // four independent partial maxima and sums: the dependent chains are NR/4 long
-      float m4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-#pragma unroll
-      for (int m = 0; m < NR; ++m) m4[m & 3] = fmaxf(m4[m & 3], buf[m] + col[m]);
-      const float mx = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
-      float s = 0.0f;
-      if (mx > -INFINITY) {
-        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int m = 0; m < NR; ++m) s4[m & 3] += __expf(buf[m] + col[m] - mx);
-        s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-      }
-      lds_order();
-      const float l = (live && mx > -INFINITY) ? xt + mx + __logf(s) : -INFINITY;
-      c = lse_lanes(l, live);
-      la = (live && c > -INFINITY) ? l - c : -INFINITY;
-      lag[(size_t)t * 64 + r] = la;
-      z += (double)c;
-    };
-    float xq[kAhead];
-#pragma unroll
-    for (int q = 0; q < kAhead; ++q) xq[q] = x[(size_t)min(1 + q, T - 1) * 64 + r];
-    int t0 = 1;
-    for (; t0 + kAhead <= T; t0 += kAhead) {
-#pragma unroll
-      for (int q = 0; q < kAhead; ++q) {
-        const float xt = xq[q];
-        xq[q] = x[(size_t)min(t0 + q + kAhead, T - 1) * 64 + r];
-        step(t0 + q, xt);
-      }
-    }
-    for (; t0 < T; ++t0) step(t0, x[(size_t)t0 * 64 + r]);
-    // ln P(V) = sum_t off_t + ln Z of the relative evidence
-    double off = 0.0;
-    for (int t = r; t < T; t += 64) off += E.off[t];
-    off = wave_sum_d(off);
-    if (r == 0) E.trace[it] = off + z;
+    z += fwd_steps<NR, true>(gptr(E.x), gptr(E.la), a, pbuf, live, r, 1, T, T, la);
+    put_trace(E, it, r, z);
   } else {
-    float row[NR];
-#pragma unroll
-    for (int j = 0; j < NR; ++j) row[j] = (live && j < N) ? E.lnA[(size_t)r * N + j] : -INFINITY;
+    a_lane<NR>(E.lnA, N, r, false, a);
     float lb = live ? 0.0f : -INFINITY;
     E.lbn[(size_t)(T - 1) * 64 + r] = lb;
-    const gfloat *x = gptr(E.x);
-    gfloat *sIg = gptr(E.sI), *lbg = gptr(E.lbn);
-    auto step = [&](int t, float xt) {
-      buf[r] = live ? xt + lb : -INFINITY;
-      lds_order();
-      float m4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    bwd_steps<NR, true>(gptr(E.x), gptr(E.sI), gptr(E.lbn), a, pbuf, live, r, T - 1, 0, lb);
+  }
+}
+
+// Forward chunk c covers the steps t = 1 + c L .. min(1 + (c + 1) L, T) - 1, and
+// backward chunk c the steps t = T - 1 - c L down to max(T - 1 - (c + 1) L, 0) + 1
+// (L = kEmSweepChunk).
+__device__ __forceinline__ int fwd_chunk_begin(int c) { return 1 + c * kEmSweepChunk; }
+__device__ __forceinline__ int bwd_chunk_begin(int T, int c) { return T - 1 - c * kEmSweepChunk; }
+
+// Block (direction, chunk c, state m): the chunk swept from the unit message of
+// m.  tm[dir][c][m][n] = exp of the normalised end message (lane n), tz[dir][c][m]
+// = the sum of its normalisers.
+template <int NR>
+__global__ __launch_bounds__(64) void k_em_sweep_cols(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
+  const int N = E.N, C = E.nsw, T = E.T;
+  if (it >= E.iters || (int)blockIdx.x >= 2 * C * N) return;
+  const int dir = blockIdx.x / (C * N), rem = blockIdx.x - dir * C * N, c = rem / N, m = rem - c * N;
+  const int r = threadIdx.x;
+  const bool live = r < N;
+  __shared__ double pbuf[64];
+  double a[NR];
+  float msg = (r == m) ? 0.0f : -INFINITY;
+  double z;
+  if (dir == 0) {
+    a_lane<NR>(E.lnA, N, r, true, a);
+    const int t0 = fwd_chunk_begin(c);
+    z = fwd_steps<NR, false>(gptr(E.x), nullptr, a, pbuf, live, r, t0, min(t0 + kEmSweepChunk, T), T, msg);
+  } else {
+    a_lane<NR>(E.lnA, N, r, false, a);
+    const int t0 = bwd_chunk_begin(T, c);
+    z = bwd_steps<NR, false>(gptr(E.x), nullptr, nullptr, a, pbuf, live, r, t0, max(t0 - kEmSweepChunk, 0), msg);
+  }
+  const size_t col = (size_t)(dir * C + c) * N + m;
+  gptr(E.tm)[col * 64 + r] = (msg > -INFINITY) ? exp((double)msg) : 0.0;
+  if (r == 0) gptr(E.tz)[(size_t)(dir * C + c) * 64 + m] = z;
+}
+
+// One chunk's transfer columns as lane r sees them: tm(m, r) for the N states m
+// (clamped past N: their weights are zero) and the log scale of column r.
+template <int NR>
+struct ScanCols {
+  double t[NR];
+  double h;
+};
+template <int NR>
+__device__ __forceinline__ void load_cols(const gdouble *tm, const gdouble *tz, int N, int r, ScanCols<NR> &k) {
 #pragma unroll
-      for (int j = 0; j < NR; ++j) m4[j & 3] = fmaxf(m4[j & 3], row[j] + buf[j]);
-      const float mx = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
-      float s = 0.0f;
-      if (mx > -INFINITY) {
-        float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int m = 0; m < NR; ++m) k.t[m] = tm[(size_t)min(m, N - 1) * 64 + r];
+  k.h = tz[r];
+}
+
+// The message v at a chunk's start (normalised logs) carried across it:
+// v'(n) = ln sum_m exp(v(m) + h(m)) tm(m, n), returned normalised, its normaliser
+// added to z.
+template <int NR>
+__device__ __forceinline__ float scan_step(const ScanCols<NR> &k, double *pbuf, bool live, int r, float v,
+                                           double &z) {
+  const double w = (live && v > -INFINITY) ? (double)v + k.h : -INFINITY;
+  const double mw = (double)wave_max((float)w);   // the shift: any value near the largest
+  pbuf[r] = (w > -INFINITY) ? exp(w - mw) : 0.0;
+  lds_order();
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < NR; ++j) s4[j & 3] += __expf(row[j] + buf[j] - mx);
-        s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-      }
-      lds_order();
-      const float sI = (live && mx > -INFINITY) ? mx + __logf(s) : -INFINITY;
-      const float cb = lse_lanes(sI, live);
-      lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
-      sIg[(size_t)(t - 1) * 64 + r] = sI;
-      lbg[(size_t)(t - 1) * 64 + r] = lb;
-    };
-    float xq[kAhead];
-#pragma unroll
-    for (int q = 0; q < kAhead; ++q) xq[q] = x[(size_t)max(T - 1 - q, 0) * 64 + r];
-    int t0 = T - 1;
-    for (; t0 - kAhead >= 0; t0 -= kAhead) {
-#pragma unroll
-      for (int q = 0; q < kAhead; ++q) {
-        const float xt = xq[q];
-        xq[q] = x[(size_t)max(t0 - q - kAhead, 0) * 64 + r];
-        step(t0 - q, xt);
-      }
+  for (int m = 0; m < NR; ++m) s4[m & 3] = fma(pbuf[m], k.t[m], s4[m & 3]);
+  const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  lds_order();
+  const float e = (live && s > 0.0) ? (float)log(s) : -INFINITY;
+  const float c = lse_lanes(e, live);
+  z = (mw > -INFINITY && c > -INFINITY) ? z + (mw + (double)c) : -INFINITY;
+  return (live && c > -INFINITY) ? e - c : -INFINITY;
+}
+
+// Block dir: the scan over the chunks, each chunk's columns loaded one chunk
+// ahead.  ts[dir][c] = the message at chunk c's start (c >= 1); forward also
+// ln P(V).
+template <int NR>
+__global__ __launch_bounds__(64) void k_em_sweep_scan(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
+  const int N = E.N, C = E.nsw, dir = blockIdx.x;
+  if (it >= E.iters || C == 0) return;
+  const int r = threadIdx.x;
+  const bool live = r < N;
+  __shared__ double pbuf[64];
+  const gdouble *tm = gptr(E.tm) + (size_t)dir * C * N * 64;
+  const gdouble *tz = gptr(E.tz) + (size_t)dir * C * 64;
+  gfloat *ts = gptr(E.ts) + (size_t)dir * C * 64;
+  double z = 0.0;
+  float v = live ? 0.0f : -INFINITY;   // backward: lb_{T-1}
+  if (dir == 0) v = fwd_first(E, live, r, z);
+  const int steps = dir == 0 ? C : C - 1;   // forward carries on to the end, for ln Z
+  auto load = [&](int c, ScanCols<NR> &k) {
+    c = min(c, steps - 1);
+    load_cols<NR>(tm + (size_t)c * N * 64, tz + (size_t)c * 64, N, r, k);
+  };
+  auto step = [&](int c, const ScanCols<NR> &k) {
+    v = scan_step<NR>(k, pbuf, live, r, v, z);
+    if (c + 1 < C) ts[(size_t)(c + 1) * 64 + r] = v;
+  };
+  ScanCols<NR> ka, kb;
+  load(0, ka);
+  int c = 0;
+  for (; c + 2 <= steps; c += 2) {
+    load(c + 1, kb);
+    step(c, ka);
+    load(c + 2, ka);
+    step(c + 1, kb);
+  }
+  if (c < steps) step(c, ka);
+  if (dir == 0) put_trace(E, it, r, z);
+}
+
+// Block (direction, chunk): the chunk swept again from its true start, storing
+// the messages as k_em_chain does.
+template <int NR>
+__global__ __launch_bounds__(64) void k_em_sweep_fin(const EmDesc *__restrict__ Es, int it) {
+  const EmDesc &E = Es[blockIdx.y];
+  const int N = E.N, C = E.nsw, T = E.T;
+  if (it >= E.iters || (int)blockIdx.x >= 2 * C) return;
+  const int dir = blockIdx.x / C, c = blockIdx.x - dir * C, r = threadIdx.x;
+  const bool live = r < N;
+  __shared__ double pbuf[64];
+  double a[NR];
+  if (dir == 0) {
+    a_lane<NR>(E.lnA, N, r, true, a);
+    float la;
+    if (c == 0) {
+      double z;
+      la = fwd_first(E, live, r, z);
+      E.la[r] = la;
+    } else {
+      la = E.ts[(size_t)c * 64 + r];
     }
-    for (; t0 >= 1; --t0) step(t0, x[(size_t)t0 * 64 + r]);
+    const int t0 = fwd_chunk_begin(c);
+    fwd_steps<NR, true>(gptr(E.x), gptr(E.la), a, pbuf, live, r, t0, min(t0 + kEmSweepChunk, T), T, la);
+  } else {
+    a_lane<NR>(E.lnA, N, r, false, a);
+    float lb;
+    if (c == 0) {
+      lb = live ? 0.0f : -INFINITY;
+      E.lbn[(size_t)(T - 1) * 64 + r] = lb;
+    } else {
+      lb = E.ts[(size_t)(C + c) * 64 + r];
+    }
+    const int t0 = bwd_chunk_begin(T, c);
+    bwd_steps<NR, true>(gptr(E.x), gptr(E.sI), gptr(E.lbn), a, pbuf, live, r, t0, max(t0 - kEmSweepChunk, 0), lb);
   }
 }
 
@@ -460,14 +653,25 @@ hipError_t launch_em_frames(const EmBatch &B, int it, hipStream_t st) {
 }
 
 hipError_t launch_em_chain(const EmBatch &B, int it, hipStream_t st) {
-  const dim3 g2(2, (unsigned)B.n);
+  const dim3 g2(2, (unsigned)B.n), gc((unsigned)(2 * B.maxSw * B.maxN), (unsigned)B.n),
+      gf((unsigned)(2 * B.maxSw), (unsigned)B.n);
+#define NFHMM_EM_SWEEPS(NR)                                                 \
+  do {                                                                      \
+    if (B.anySeq) k_em_chain<NR><<<g2, 64, 0, st>>>(B.d, it);               \
+    if (B.maxSw > 0) {                                                      \
+      k_em_sweep_cols<NR><<<gc, 64, 0, st>>>(B.d, it);                      \
+      k_em_sweep_scan<NR><<<g2, 64, 0, st>>>(B.d, it);                      \
+      k_em_sweep_fin<NR><<<gf, 64, 0, st>>>(B.d, it);                       \
+    }                                                                       \
+  } while (0)
   switch ((B.maxN + 15) & ~15) {
-    case 16: k_em_chain<16><<<g2, 64, 0, st>>>(B.d, it); break;
-    case 32: k_em_chain<32><<<g2, 64, 0, st>>>(B.d, it); break;
-    case 48: k_em_chain<48><<<g2, 64, 0, st>>>(B.d, it); break;
-    case 64: k_em_chain<64><<<g2, 64, 0, st>>>(B.d, it); break;
+    case 16: NFHMM_EM_SWEEPS(16); break;
+    case 32: NFHMM_EM_SWEEPS(32); break;
+    case 48: NFHMM_EM_SWEEPS(48); break;
+    case 64: NFHMM_EM_SWEEPS(64); break;
     default: return hipErrorInvalidValue;
   }
+#undef NFHMM_EM_SWEEPS
   k_em_post<<<dim3((unsigned)B.maxT, (unsigned)B.n), 64, 0, st>>>(B.d, it);
   k_em_xi<<<dim3((unsigned)(B.maxChunk * B.maxN), (unsigned)B.n), 64, 0, st>>>(B.d, it);
   k_em_xi_reduce<<<dim3((unsigned)B.maxN, (unsigned)B.n), 64, 0, st>>>(B.d, it);

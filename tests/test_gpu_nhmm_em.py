@@ -5,9 +5,12 @@ from the model of Section 2.1; the reference is pinned in tests/test_nhmm_em_pin
 Both start from the same float32 parameters and run the same number of
 iterations; every learned parameter and the log-likelihood trace are compared
 element by element.  The GPU keeps beta and theta in double between iterations
-and runs the chain in float32 log space (A and pi as logarithms), treating as zero
-what underflows a double, as the reference does; the differences are the chain's
-float32 rounding carried through the updates.  Tolerances: dictionaries
+and keeps the chain's messages as float32 logarithms (A and pi too), with each
+step's sums in double, treating as zero what underflows a double, as the reference
+does; the differences are the chain's float32 rounding carried through the
+updates.  Chains of T >= 98 frames take the time-parallel forward-backward when
+the batch is small (one problem always is), the others and every chain of a batch
+past 2^19 state-frames the sequential one: both are checked here.  Tolerances: dictionaries
 |d beta| <= 1e-5 of their row's largest entry, theta |d| <= 1e-6, A |d| <= 2e-5,
 pi |d| <= 1e-5, ln P(V) 1e-9 relative (measured at the paper's shapes: 6.4e-7,
 9e-9, 2.2e-6, 0, 9e-11).
@@ -87,6 +90,26 @@ def test_em_paper_shape(L, ctx):
         assert e[k] <= tol, (k, e[k])
 
 
+def test_em_sequential_sweeps_past_the_line(L, ctx):
+    """Fourteen 1000-frame, 40-state problems (5.6e5 state-frames, past 2^19) take
+    the sequential forward-backward in a batch; alone, each takes the time-parallel
+    one.  Both match the FP64 reference, and each other, to the parity bar."""
+    probs = [make_nhmm_problem(1, 40 + i, K=4, F=64, iters=2) for i in range(14)]
+    assert sum(p["N"] * p["T"] for p in probs) > 1 << 19
+    batch = L.learn_nhmm_batch(ctx, probs)
+    for i in (0, 13):
+        alone = L.learn_nhmm(ctx, probs[i])
+        r = _oracle(probs[i], 2)
+        for tag, g in (("sequential", batch[i]), ("time-parallel", alone)):
+            e = _errs(g, r)
+            print(f"\nproblem {i} {tag} x2: {_fmt(e)}")
+            for k, tol in TOL.items():
+                assert e[k] <= tol, (tag, k, e[k])
+        e = _errs(batch[i], alone)
+        for k, tol in TOL.items():
+            assert e[k] <= tol, ("sequential vs time-parallel", k, e[k])
+
+
 def test_em_likelihood_never_decreases(L, ctx):
     p = make_nhmm_problem(1, 1, N=20, K=8, T=400, iters=25)
     g = L.learn_nhmm(ctx, p)
@@ -131,7 +154,8 @@ def test_em_rejects_invalid_starts(L, ctx):
 def test_em_batch_equals_alone(L, ctx):
     """A batch of problems that differ in every size and in their iteration counts
     (states 1 to 40, so the chain's register tile spans all four widths; K from 3
-    to 32): each problem's learned parameters and trace equal learning it alone,
+    to 32; T = 131 and 300 on the time-parallel forward-backward, the rest on the
+    sequential one): each problem's learned parameters and trace equal learning it alone,
     bit for bit, and one problem of the batch matches the FP64 reference."""
     probs = [make_nhmm_problem(0, 11, N=4, K=3, F=24, T=40, iters=8),
              make_nhmm_problem(1, 12, N=40, K=10, T=300, iters=3),
