@@ -155,10 +155,10 @@ __device__ __forceinline__ float lse_lanes(float x, bool live) {
 //             normalised, lb_{T-1} = 0; both are stored, s for the pairwise
 //             marginals: ln xi_t(i, j) = ln gamma_{t-1}(i) + ln A(i, j) + x_t(j) +
 //             lb_t(j) - s_{t-1}(i).
-// Each step takes the messages out of log space for its sums: one double
-// exponential per lane, the N products with A in double by FMAs, then one
-// logarithm.  A term counts as zero only below e^-708 of the largest, as in a
-// double evaluation.
+// Each step takes the messages out of log space for its sums: one exponential per
+// lane into a double (float precision, as the messages have, over the double
+// range), the N products with A in double by FMAs, then one logarithm.  A term
+// counts as zero only below e^-708 of the largest, as in a double evaluation.
 //
 // Two schedules.  k_em_chain runs the two sweeps side by side, one wavefront each,
 // T dependent steps.  The time-parallel one cuts each sweep into chunks of
@@ -184,6 +184,23 @@ constexpr int kAhead = 8;   // frames of evidence loaded ahead of the sweep
 // loaded ahead and the stored messages.)
 __device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
 
+// e^x in double for a float x (finite, at most a few units above 0): 2^y with y =
+// x log2(e) split into its integer part k and a fraction, whose power of two the
+// hardware takes in float -- float precision over the double range (the messages
+// themselves are float logarithms).  Below e^-1386 the result is 0.
+__device__ __forceinline__ double exp_wide(float x) {
+  const double y = fmax((double)x * 1.4426950408889634, -2000.0);
+  const double k = floor(y);
+  return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)), (int)k);
+}
+// ln s as a float for a double s > 0: its binary exponent exactly, the logarithm of
+// its mantissa (in [1/2, 1)) by the hardware in float.
+__device__ __forceinline__ float log_wide(double s) {
+  int e;
+  const double m = frexp(s, &e);
+  return ((float)e + __builtin_amdgcn_logf((float)m)) * 0.6931471805599453f;
+}
+
 // Forward steps t = t0 .. t1-1 from la, the normalised message of frame t0-1 (its
 // largest entry is at least -ln N, so its exponentials need no shift).  ac is
 // column r of A.  Returns the sum of the normalisers; STORE keeps the messages.
@@ -195,14 +212,14 @@ __device__ __forceinline__ double fwd_steps(const gfloat *x, gfloat *lag, const 
                                             bool live, int r, int t0, int t1, int T, float &la) {
   double z = 0.0;
   auto step = [&](int t, float xt) {
-    pbuf[r] = (live && la > -INFINITY) ? exp((double)la) : 0.0;
+    pbuf[r] = (live && la > -INFINITY) ? exp_wide(la) : 0.0;
     lds_order();
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < NR; ++m) s4[m & 3] = fma(pbuf[m], ac[m], s4[m & 3]);
     const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     lds_order();
-    const float l = (live && s > 0.0) ? xt + (float)log(s) : -INFINITY;
+    const float l = (live && s > 0.0) ? xt + log_wide(s) : -INFINITY;
     const float c = lse_lanes(l, live);
     la = (live && c > -INFINITY) ? l - c : -INFINITY;
     if (STORE) lag[(size_t)t * 64 + r] = la;
@@ -237,14 +254,14 @@ __device__ __forceinline__ double bwd_steps(const gfloat *x, gfloat *sIg, gfloat
     // can lie far below the range of an exponential)
     const float q = live ? xt + lb : -INFINITY;
     const float mq = wave_max(q);
-    pbuf[r] = (q > -INFINITY) ? exp((double)(q - mq)) : 0.0;
+    pbuf[r] = (q > -INFINITY) ? exp_wide(q - mq) : 0.0;
     lds_order();
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int j = 0; j < NR; ++j) s4[j & 3] = fma(ar[j], pbuf[j], s4[j & 3]);
     const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     lds_order();
-    const float sI = (live && s > 0.0 && mq > -INFINITY) ? mq + (float)log(s) : -INFINITY;
+    const float sI = (live && s > 0.0 && mq > -INFINITY) ? mq + log_wide(s) : -INFINITY;
     const float cb = lse_lanes(sI, live);
     lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
     if (STORE) {
@@ -376,14 +393,14 @@ __device__ __forceinline__ float scan_step(const ScanCols<NR> &k, double *pbuf, 
                                            double &z) {
   const double w = (live && v > -INFINITY) ? (double)v + k.h : -INFINITY;
   const double mw = (double)wave_max((float)w);   // the shift: any value near the largest
-  pbuf[r] = (w > -INFINITY) ? exp(w - mw) : 0.0;
+  pbuf[r] = (w > -INFINITY) ? exp_wide((float)(w - mw)) : 0.0;
   lds_order();
   double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < NR; ++m) s4[m & 3] = fma(pbuf[m], k.t[m], s4[m & 3]);
   const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   lds_order();
-  const float e = (live && s > 0.0) ? (float)log(s) : -INFINITY;
+  const float e = (live && s > 0.0) ? log_wide(s) : -INFINITY;
   const float c = lse_lanes(e, live);
   z = (mw > -INFINITY && c > -INFINITY) ? z + (mw + (double)c) : -INFINITY;
   return (live && c > -INFINITY) ? e - c : -INFINITY;
