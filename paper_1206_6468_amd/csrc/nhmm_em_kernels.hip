@@ -556,7 +556,9 @@ __global__ __launch_bounds__(64) void k_em_xi_reduce(const EmDesc *__restrict__ 
 
 // Partial sums of the beta update over one chunk of frames: lane = bin f of a
 // 64-bin tile, block (tile, state d, chunk).  theta_t(d, .) and gamma_t(d) are the
-// same for every lane.  KR >= K elements in registers.
+// same for every lane: the chunk's are staged in LDS first, and each lane's counts
+// of the chunk's frames loaded at once, so that the frames' loads overlap instead
+// of each frame waiting for its own.  KR >= K elements in registers.
 template <int KR>
 __global__ __launch_bounds__(64) void k_em_beta(const EmDesc *__restrict__ Es, int it) {
   const EmDesc &E = Es[blockIdx.y];
@@ -564,11 +566,27 @@ __global__ __launch_bounds__(64) void k_em_beta(const EmDesc *__restrict__ Es, i
   if (it >= E.iters || (int)blockIdx.x >= ftiles * N * E.nchunk) return;
   // block = (bin tile, state d, frame chunk c)
   const int ft = blockIdx.x % ftiles, dc = blockIdx.x / ftiles, d = dc % N, c = dc / N;
-  const int f = ft * 64 + threadIdx.x;
+  const int lane = threadIdx.x, f = ft * 64 + lane;
   const bool in = f < F;
   const float gmx = gptr(E.gmax)[d];
   const gdouble *beta = gptr(E.beta), *theta = gptr(E.theta);
   const gfloat *V = gptr(E.V), *lgam = gptr(E.lgam);
+  const int t0 = c * kEmChunk, nt = min(E.T, t0 + kEmChunk) - t0;
+  __shared__ double ths[kEmChunk][KR];   // theta_t(d, z) of the chunk's frames (0 for z >= K)
+  __shared__ double gs[kEmChunk];        // gamma_t(d) relative to the state's largest
+  for (int i = lane; i < kEmChunk * KR; i += 64) {
+    const int tt = i / KR, z = i - tt * KR;
+    ths[tt][z] = (tt < nt && z < K) ? theta[((size_t)(t0 + tt) * N + d) * K + z] : 0.0;
+  }
+  if (lane < kEmChunk) {
+    // gamma relative to the state's largest: the row is normalised over f, so the
+    // per-state scale cancels, and frames far below the largest still count
+    const float lg = lane < nt ? lgam[(size_t)(t0 + lane) * N + d] : -INFINITY;
+    gs[lane] = lg >= kEmLogTiny ? exp((double)(lg - gmx)) : 0.0;
+  }
+  float vq[kEmChunk];
+#pragma unroll
+  for (int i = 0; i < kEmChunk; ++i) vq[i] = (in && i < nt) ? V[(size_t)(t0 + i) * F + f] : 0.0f;
   double bz[KR], acc[KR];
 #pragma unroll
   for (int z = 0; z < KR; ++z) {
@@ -577,29 +595,28 @@ __global__ __launch_bounds__(64) void k_em_beta(const EmDesc *__restrict__ Es, i
     bz[z] = in ? beta[((size_t)d * K + min(z, K - 1)) * F + f] : 0.0;
     acc[z] = 0.0;
   }
-  const int t0 = c * kEmChunk, t1 = min(E.T, t0 + kEmChunk);
-  for (int t = t0; t < t1; ++t) {
-    const float vv = in ? V[(size_t)t * F + f] : 0.0f;
-    const gdouble *th = theta + ((size_t)t * N + d) * K;
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kEmChunk; ++i) {
+    if (i >= nt) continue;   // uniform over the block
     double tz[KR];
     double P = 0.0;
 #pragma unroll
     for (int z = 0; z < KR; ++z) {
-      const double x = th[min(z, K - 1)];
-      tz[z] = z < K ? x : 0.0;
+      tz[z] = ths[i][z];
       P = fma(tz[z], bz[z], P);
     }
-    // gamma_t(d) relative to the state's largest: the row is normalised over f,
-    // so the per-state scale cancels, and frames far below the largest still count
-    const float lg = lgam[(size_t)t * N + d];
-    const double g = lg >= kEmLogTiny ? exp((double)(lg - gmx)) : 0.0;
+    const double g = gs[i];
+    const float vv = vq[i];
     const double gr = (vv > 0.0f && g > 0.0) ? g * ((double)vv / P) : 0.0;
 #pragma unroll
     for (int z = 0; z < KR; ++z) acc[z] = fma(tz[z], gr, acc[z]);
   }
   if (in) {
     gdouble *out = gptr(E.bpart) + ((size_t)c * N + d) * K * F;
-    for (int z = 0; z < K; ++z) out[(size_t)z * F + f] = acc[z];
+#pragma unroll
+    for (int z = 0; z < KR; ++z)
+      if (z < K) out[(size_t)z * F + f] = acc[z];
   }
 }
 
