@@ -634,6 +634,9 @@ __global__ __launch_bounds__(256) void k_em_beta_reduce(const EmDesc *__restrict
   double s = 0.0;
   for (int f = tid; f < F; f += 256) {
     double acc = 0.0;
+    // unrolled so that eight chunks' loads are in flight together; the sum keeps
+    // its order
+#pragma unroll 8
     for (int c = 0; c < E.nchunk; ++c) acc += bpart[(size_t)c * NKF + (size_t)rw * F + f];
     const double x = brow[f] * acc;
     nrow[f] = x;
