@@ -58,10 +58,15 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 template <int KR>
 __global__ __launch_bounds__(256) void k_em_frame(const EmDesc *__restrict__ Es, int it) {
   const EmDesc &E = Es[blockIdx.y];
-  // the wavefront's (frame, state) as a scalar: theta's row then sits in scalar registers
-  const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6)), lane = threadIdx.x & 63;
-  if (it >= E.iters || w >= E.T * E.N) return;
-  const int t = w / E.N, d = w - (w / E.N) * E.N;
+  // block = (state d, four consecutive frames), one frame per wavefront: the four
+  // read the same rows of beta together, so three of them find them in the L1
+  // cache.  The wavefront's (frame, state) is a scalar: theta's row then sits in
+  // scalar registers.
+  const int G = (E.T + 3) / 4;
+  if (it >= E.iters || (int)blockIdx.x >= G * E.N) return;
+  const int d = blockIdx.x / G, lane = threadIdx.x & 63;
+  const int t = __builtin_amdgcn_readfirstlane((blockIdx.x - d * G) * 4 + (threadIdx.x >> 6));
+  if (t >= E.T) return;
   const int K = E.K, F = E.F;
   const size_t row = ((size_t)t * E.N + d) * K;
   const gdouble *theta = gptr(E.theta);
@@ -677,7 +682,7 @@ __global__ void k_em_export(int N, int K, int F, int T, const double *beta, cons
 }
 
 hipError_t launch_em_frames(const EmBatch &B, int it, hipStream_t st) {
-  const dim3 g((unsigned)((B.maxT * B.maxN + 3) / 4), (unsigned)B.n);
+  const dim3 g((unsigned)((B.maxT + 3) / 4 * B.maxN), (unsigned)B.n);
   if (B.maxK <= 4) k_em_frame<4><<<g, 256, 0, st>>>(B.d, it);
   else if (B.maxK <= 8) k_em_frame<8><<<g, 256, 0, st>>>(B.d, it);
   else if (B.maxK <= 10) k_em_frame<10><<<g, 256, 0, st>>>(B.d, it);   // the paper's K
