@@ -1847,7 +1847,7 @@ EmLayout em_layout(const nfhmm_nhmm_problem &p, bool host, int nsw) {
   L.bpart = take(nchunk * N * K * F * 8); L.trace = take(it * 8);
   const size_t C = (size_t)nsw;
   L.nsw = nsw;
-  L.tm = take(2 * C * N * 64 * 8); L.tz = take(2 * C * 64 * 8); L.ts = take(2 * C * 64 * 4);
+  L.tm = take(2 * C * N * 64 * 4); L.tz = take(2 * C * 64 * 8); L.ts = take(2 * C * 64 * 4);
   L.total = off;
   return L;
 }
@@ -1919,7 +1919,7 @@ nfhmm_status em_run(nfhmm_ctx *ctx, int n, const nfhmm_nhmm_problem *ps, nfhmm_n
       E.lbn = F32(L.lbn); E.sI = F32(L.sI);
       E.xpart = reinterpret_cast<float2 *>(a + L.xpart); E.gpart = F32(L.gpart);
       E.bpart = F64(L.bpart); E.trace = F64(L.trace);
-      E.nsw = L.nsw; E.tm = F64(L.tm); E.tz = F64(L.tz); E.ts = F32(L.ts);
+      E.nsw = L.nsw; E.tm = F32(L.tm); E.tz = F64(L.tz); E.ts = F32(L.ts);
     }
     B.maxN = std::max(B.maxN, (int)N); B.maxK = std::max(B.maxK, (int)K); B.maxF = std::max(B.maxF, (int)F);
     B.maxT = std::max(B.maxT, (int)T); B.maxChunk = std::max(B.maxChunk, hd[i].nchunk);

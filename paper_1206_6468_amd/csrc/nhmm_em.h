@@ -25,11 +25,12 @@ constexpr int kEmMaxK = 32;      // elements per state
 constexpr int kEmMaxBatch = 65535;   // problems per batch (grid y)
 constexpr int kEmChunk = 32;     // frames per partial sum of the beta update's and the xi sums over t
 constexpr int kEmSweepChunk = 32;   // frames per chunk of the time-parallel forward-backward
-// ln of the smallest normal double: probabilities (marginals, pairwise marginals,
-// transitions, initial probabilities) below it count as zero, as they are in a
-// double-precision evaluation of the same updates -- where a state or a
+// ln 2^-1075, below which the exponential of a double rounds to zero (the
+// subnormal doubles above it still count): probabilities (marginals, pairwise
+// marginals, transitions, initial probabilities) below it count as zero, as they
+// do in a double-precision evaluation of the same updates -- where a state or a
 // transition whose every count underflows keeps its previous parameters.
-constexpr float kEmLogTiny = -708.3964185322641f;
+constexpr float kEmLogTiny = -745.1332191019412f;
 
 struct EmDesc {
   int N, K, F, T, nchunk;
@@ -56,7 +57,7 @@ struct EmDesc {
   float *gpart;             // [nchunk][N] per frame chunk: max ln gamma_t(i)
   double *bpart;            // [nchunk][N][K][F] partial sums over frame chunks of the beta update
   double *trace;            // [iters]     ln P(V) of the parameters each iteration started from
-  double *tm;               // [2][nsw][N][64] per direction and chunk: transfer columns (linear, each sums to 1)
+  float *tm;                // [2][nsw][N][64] per direction and chunk: transfer columns (normalised logarithms)
   double *tz;               // [2][nsw][64]    their log scales
   float *ts;                // [2][nsw][64]    each chunk's start message
 };

@@ -151,35 +151,35 @@ __device__ __forceinline__ float lse_lanes(float x, bool live) {
   return mx + __logf(wave_sum(live ? __expf(x - mx) : 0.0f));
 }
 
-// The forward-backward of the source chain, lane r = state r, messages kept as
-// logarithms normalised per frame (the smallest probabilities the iterations
-// need are far below the float32 range):
-//   forward   la_t(n) = x_t(n) + ln sum_m exp(la_{t-1}(m)) A(m, n), la_0 = ln pi + x_0;
+// The forward-backward of the source chain, lane r = state r, in log space with
+// the messages normalised per frame (the smallest probabilities the iterations
+// need are far below the float32 range, and a message entry far below its
+// frame's largest can still carry a marginal when the other direction's message
+// favours it, so no message entry is ever flushed):
+//   forward   la_t(n) = x_t(n) + lse_m(la_{t-1}(m) + ln A(m, n)), la_0 = ln pi + x_0;
 //             ln Z = the sum of the frames' normalisers
-//   backward  s_{t-1}(i) = ln sum_j A(i, j) exp(x_t(j) + lb_t(j)), lb_{t-1} = s_{t-1}
+//   backward  s_{t-1}(i) = lse_j(ln A(i, j) + x_t(j) + lb_t(j)), lb_{t-1} = s_{t-1}
 //             normalised, lb_{T-1} = 0; both are stored, s for the pairwise
 //             marginals: ln xi_t(i, j) = ln gamma_{t-1}(i) + ln A(i, j) + x_t(j) +
 //             lb_t(j) - s_{t-1}(i).
-// Each step takes the messages out of log space for its sums: one exponential per
-// lane into a double (float precision, as the messages have, over the double
-// range), the N products with A in double by FMAs, then one logarithm.  A term
-// counts as zero only below e^-708 of the largest, as in a double evaluation.
+// Each lane's log-sum-exp takes the largest of its N terms and sums the rest
+// relative to it, so only terms negligible against that lane's own sum are lost.
 //
 // Two schedules.  k_em_chain runs the two sweeps side by side, one wavefront each,
 // T dependent steps.  The time-parallel one cuts each sweep into chunks of
 // kEmSweepChunk frames and uses that a sweep is linear in its message:
 //   k_em_sweep_cols  wavefront (direction, chunk, state m) sweeps the chunk from
 //                    the unit message of m: the chunk's transfer column (end
-//                    message, normalised, linear) and its log scale
+//                    message as normalised logarithms) and its log scale
 //   k_em_sweep_scan  one wavefront per direction carries the true message across
-//                    the chunks with those columns, storing each chunk's start
-//                    message (and ln P(V))
+//                    the chunks with those columns (a log-sum-exp per lane over
+//                    the N columns), storing each chunk's start message (and
+//                    ln P(V))
 //   k_em_sweep_fin   wavefront (direction, chunk) sweeps its chunk again from that
 //                    start, storing the messages
 // The critical path is about 2 kEmSweepChunk + T / kEmSweepChunk steps instead of
 // T, for N times the work; the runtime picks it for batches too small to fill the
-// GPU.  Both give the same messages up to rounding: no term is dropped that a
-// double evaluation keeps.
+// GPU.  Both give the same messages up to rounding.
 constexpr int kAhead = 8;   // frames of evidence loaded ahead of the sweep
 
 // A sweep's block is one wavefront, and LDS executes a wavefront's operations in
@@ -189,42 +189,37 @@ constexpr int kAhead = 8;   // frames of evidence loaded ahead of the sweep
 // loaded ahead and the stored messages.)
 __device__ __forceinline__ void lds_order() { __asm__ volatile("" ::: "memory"); }
 
-// e^x in double for a float x (finite, at most a few units above 0): 2^y with y =
-// x log2(e) split into its integer part k and a fraction, whose power of two the
-// hardware takes in float -- float precision over the double range (the messages
-// themselves are float logarithms).  Below e^-1386 the result is 0.
-__device__ __forceinline__ double exp_wide(float x) {
-  const double y = fmax((double)x * 1.4426950408889634, -2000.0);
-  const double k = floor(y);
-  return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)), (int)k);
-}
-// ln s as a float for a double s > 0: its binary exponent exactly, the logarithm of
-// its mantissa (in [1/2, 1)) by the hardware in float.
-__device__ __forceinline__ float log_wide(double s) {
-  int e;
-  const double m = frexp(s, &e);
-  return ((float)e + __builtin_amdgcn_logf((float)m)) * 0.6931471805599453f;
+// lse_m(buf[m] + c[m]) over NR terms for this lane: four independent partial
+// maxima and sums, so that the dependent chains are NR/4 long (-inf if every term
+// is -inf).
+template <int NR>
+__device__ __forceinline__ float lse_terms(const float *buf, const float (&c)[NR]) {
+  float m4[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+  for (int m = 0; m < NR; ++m) m4[m & 3] = fmaxf(m4[m & 3], buf[m] + c[m]);
+  const float mx = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
+  if (!(mx > -INFINITY)) return -INFINITY;
+  float s4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int m = 0; m < NR; ++m) s4[m & 3] += __expf(buf[m] + c[m] - mx);
+  return mx + __logf((s4[0] + s4[1]) + (s4[2] + s4[3]));
 }
 
-// Forward steps t = t0 .. t1-1 from la, the normalised message of frame t0-1 (its
-// largest entry is at least -ln N, so its exponentials need no shift).  ac is
-// column r of A.  Returns the sum of the normalisers; STORE keeps the messages.
-// Each frame's evidence row is loaded kAhead frames before its step (clamped to
-// the last frame: always in bounds), in whole rounds of kAhead steps; the last
-// few steps load their own.
+// Forward steps t = t0 .. t1-1 from la, the normalised message of frame t0-1.  ac
+// is column r of ln A.  Returns the sum of the normalisers; STORE keeps the
+// messages.  Each frame's evidence row is loaded kAhead frames before its step
+// (clamped to the last frame: always in bounds), in whole rounds of kAhead steps;
+// the last few steps load their own.
 template <int NR, bool STORE>
-__device__ __forceinline__ double fwd_steps(const gfloat *x, gfloat *lag, const double (&ac)[NR], double *pbuf,
+__device__ __forceinline__ double fwd_steps(const gfloat *x, gfloat *lag, const float (&ac)[NR], float *buf,
                                             bool live, int r, int t0, int t1, int T, float &la) {
   double z = 0.0;
   auto step = [&](int t, float xt) {
-    pbuf[r] = (live && la > -INFINITY) ? exp_wide(la) : 0.0;
+    buf[r] = la;
     lds_order();
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int m = 0; m < NR; ++m) s4[m & 3] = fma(pbuf[m], ac[m], s4[m & 3]);
-    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    const float s = lse_terms<NR>(buf, ac);
     lds_order();
-    const float l = (live && s > 0.0) ? xt + log_wide(s) : -INFINITY;
+    const float l = (live && s > -INFINITY) ? xt + s : -INFINITY;
     const float c = lse_lanes(l, live);
     la = (live && c > -INFINITY) ? l - c : -INFINITY;
     if (STORE) lag[(size_t)t * 64 + r] = la;
@@ -247,26 +242,19 @@ __device__ __forceinline__ double fwd_steps(const gfloat *x, gfloat *lag, const 
 }
 
 // Backward steps t = t0, t0-1, .., t1+1 from lb, the message of frame t0; each
-// gives s_{t-1} and lb_{t-1}.  ar is row r of A.  Returns the sum of the
+// gives s_{t-1} and lb_{t-1}.  ar is row r of ln A.  Returns the sum of the
 // normalisers; STORE keeps s and the messages.  Evidence is loaded ahead as above
 // (clamped to frame 0).
 template <int NR, bool STORE>
-__device__ __forceinline__ double bwd_steps(const gfloat *x, gfloat *sIg, gfloat *lbg, const double (&ar)[NR],
-                                            double *pbuf, bool live, int r, int t0, int t1, float &lb) {
+__device__ __forceinline__ double bwd_steps(const gfloat *x, gfloat *sIg, gfloat *lbg, const float (&ar)[NR],
+                                            float *buf, bool live, int r, int t0, int t1, float &lb) {
   double z = 0.0;
   auto step = [&](int t, float xt) {
-    // evidence times message, relative to its largest entry (the evidence alone
-    // can lie far below the range of an exponential)
-    const float q = live ? xt + lb : -INFINITY;
-    const float mq = wave_max(q);
-    pbuf[r] = (q > -INFINITY) ? exp_wide(q - mq) : 0.0;
+    buf[r] = live ? xt + lb : -INFINITY;
     lds_order();
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < NR; ++j) s4[j & 3] = fma(ar[j], pbuf[j], s4[j & 3]);
-    const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    const float s = lse_terms<NR>(buf, ar);
     lds_order();
-    const float sI = (live && s > 0.0 && mq > -INFINITY) ? mq + log_wide(s) : -INFINITY;
+    const float sI = live ? s : -INFINITY;
     const float cb = lse_lanes(sI, live);
     lb = (live && cb > -INFINITY) ? sI - cb : -INFINITY;
     if (STORE) {
@@ -291,13 +279,13 @@ __device__ __forceinline__ double bwd_steps(const gfloat *x, gfloat *sIg, gfloat
   return z;
 }
 
-// Column r (forward) or row r (backward) of A, in double; zero past N.
+// Column r (forward) or row r (backward) of ln A; -inf past N.
 template <int NR>
-__device__ __forceinline__ void a_lane(const float *lnA, int N, int r, bool col, double (&a)[NR]) {
+__device__ __forceinline__ void a_lane(const float *lnA, int N, int r, bool col, float (&a)[NR]) {
   const bool live = r < N;
 #pragma unroll
   for (int j = 0; j < NR; ++j)
-    a[j] = (live && j < N) ? exp((double)lnA[col ? (size_t)j * N + r : (size_t)r * N + j]) : 0.0;
+    a[j] = (live && j < N) ? lnA[col ? (size_t)j * N + r : (size_t)r * N + j] : -INFINITY;
 }
 
 // The normalised first forward message, and its normaliser.
@@ -324,20 +312,20 @@ __global__ __launch_bounds__(64) void k_em_chain(const EmDesc *__restrict__ Es, 
   if (it >= E.iters || E.nsw > 0) return;
   const int r = threadIdx.x, N = E.N, T = E.T;
   const bool live = r < N;
-  __shared__ double pbuf[64];
-  double a[NR];
+  __shared__ float buf[64];
+  float a[NR];
   if (blockIdx.x == 0) {
     a_lane<NR>(E.lnA, N, r, true, a);
     double z;
     float la = fwd_first(E, live, r, z);
     E.la[r] = la;
-    z += fwd_steps<NR, true>(gptr(E.x), gptr(E.la), a, pbuf, live, r, 1, T, T, la);
+    z += fwd_steps<NR, true>(gptr(E.x), gptr(E.la), a, buf, live, r, 1, T, T, la);
     put_trace(E, it, r, z);
   } else {
     a_lane<NR>(E.lnA, N, r, false, a);
     float lb = live ? 0.0f : -INFINITY;
     E.lbn[(size_t)(T - 1) * 64 + r] = lb;
-    bwd_steps<NR, true>(gptr(E.x), gptr(E.sI), gptr(E.lbn), a, pbuf, live, r, T - 1, 0, lb);
+    bwd_steps<NR, true>(gptr(E.x), gptr(E.sI), gptr(E.lbn), a, buf, live, r, T - 1, 0, lb);
   }
 }
 
@@ -348,8 +336,8 @@ __device__ __forceinline__ int fwd_chunk_begin(int c) { return 1 + c * kEmSweepC
 __device__ __forceinline__ int bwd_chunk_begin(int T, int c) { return T - 1 - c * kEmSweepChunk; }
 
 // Block (direction, chunk c, state m): the chunk swept from the unit message of
-// m.  tm[dir][c][m][n] = exp of the normalised end message (lane n), tz[dir][c][m]
-// = the sum of its normalisers.
+// m.  tm[dir][c][m][n] = the normalised end message (lane n, logarithms),
+// tz[dir][c][m] = the sum of its normalisers.
 template <int NR>
 __global__ __launch_bounds__(64) void k_em_sweep_cols(const EmDesc *__restrict__ Es, int it) {
   const EmDesc &E = Es[blockIdx.y];
@@ -358,54 +346,54 @@ __global__ __launch_bounds__(64) void k_em_sweep_cols(const EmDesc *__restrict__
   const int dir = blockIdx.x / (C * N), rem = blockIdx.x - dir * C * N, c = rem / N, m = rem - c * N;
   const int r = threadIdx.x;
   const bool live = r < N;
-  __shared__ double pbuf[64];
-  double a[NR];
+  __shared__ float buf[64];
+  float a[NR];
   float msg = (r == m) ? 0.0f : -INFINITY;
   double z;
   if (dir == 0) {
     a_lane<NR>(E.lnA, N, r, true, a);
     const int t0 = fwd_chunk_begin(c);
-    z = fwd_steps<NR, false>(gptr(E.x), nullptr, a, pbuf, live, r, t0, min(t0 + kEmSweepChunk, T), T, msg);
+    z = fwd_steps<NR, false>(gptr(E.x), nullptr, a, buf, live, r, t0, min(t0 + kEmSweepChunk, T), T, msg);
   } else {
     a_lane<NR>(E.lnA, N, r, false, a);
     const int t0 = bwd_chunk_begin(T, c);
-    z = bwd_steps<NR, false>(gptr(E.x), nullptr, nullptr, a, pbuf, live, r, t0, max(t0 - kEmSweepChunk, 0), msg);
+    z = bwd_steps<NR, false>(gptr(E.x), nullptr, nullptr, a, buf, live, r, t0, max(t0 - kEmSweepChunk, 0), msg);
   }
   const size_t col = (size_t)(dir * C + c) * N + m;
-  gptr(E.tm)[col * 64 + r] = (msg > -INFINITY) ? exp((double)msg) : 0.0;
+  gptr(E.tm)[col * 64 + r] = msg;
   if (r == 0) gptr(E.tz)[(size_t)(dir * C + c) * 64 + m] = z;
 }
 
 // One chunk's transfer columns as lane r sees them: tm(m, r) for the N states m
-// (clamped past N: their weights are zero) and the log scale of column r.
+// (clamped past N: their weights are -inf) and the log scale of column r.
 template <int NR>
 struct ScanCols {
-  double t[NR];
+  float t[NR];
   double h;
 };
 template <int NR>
-__device__ __forceinline__ void load_cols(const gdouble *tm, const gdouble *tz, int N, int r, ScanCols<NR> &k) {
+__device__ __forceinline__ void load_cols(const gfloat *tm, const gdouble *tz, int N, int r, ScanCols<NR> &k) {
 #pragma unroll
   for (int m = 0; m < NR; ++m) k.t[m] = tm[(size_t)min(m, N - 1) * 64 + r];
   k.h = tz[r];
 }
 
 // The message v at a chunk's start (normalised logs) carried across it:
-// v'(n) = ln sum_m exp(v(m) + h(m)) tm(m, n), returned normalised, its normaliser
-// added to z.
+// v'(n) = lse_m(v(m) + h(m) + tm(m, n)), returned normalised, its normaliser added
+// to z.  The weights v + h are taken relative to their largest (in double), so
+// that the float log-sum-exp sees values of moderate size.
 template <int NR>
-__device__ __forceinline__ float scan_step(const ScanCols<NR> &k, double *pbuf, bool live, int r, float v,
+__device__ __forceinline__ float scan_step(const ScanCols<NR> &k, float *buf, bool live, int r, int N, float v,
                                            double &z) {
   const double w = (live && v > -INFINITY) ? (double)v + k.h : -INFINITY;
   const double mw = (double)wave_max((float)w);   // the shift: any value near the largest
-  pbuf[r] = (w > -INFINITY) ? exp_wide((float)(w - mw)) : 0.0;
+  buf[r] = (w > -INFINITY) ? (float)(w - mw) : -INFINITY;
   lds_order();
-  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  float cm[NR];
 #pragma unroll
-  for (int m = 0; m < NR; ++m) s4[m & 3] = fma(pbuf[m], k.t[m], s4[m & 3]);
-  const double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+  for (int m = 0; m < NR; ++m) cm[m] = m < N ? k.t[m] : -INFINITY;
+  const float e = live ? lse_terms<NR>(buf, cm) : -INFINITY;
   lds_order();
-  const float e = (live && s > 0.0) ? log_wide(s) : -INFINITY;
   const float c = lse_lanes(e, live);
   z = (mw > -INFINITY && c > -INFINITY) ? z + (mw + (double)c) : -INFINITY;
   return (live && c > -INFINITY) ? e - c : -INFINITY;
@@ -421,8 +409,8 @@ __global__ __launch_bounds__(64) void k_em_sweep_scan(const EmDesc *__restrict__
   if (it >= E.iters || C == 0) return;
   const int r = threadIdx.x;
   const bool live = r < N;
-  __shared__ double pbuf[64];
-  const gdouble *tm = gptr(E.tm) + (size_t)dir * C * N * 64;
+  __shared__ float buf[64];
+  const gfloat *tm = gptr(E.tm) + (size_t)dir * C * N * 64;
   const gdouble *tz = gptr(E.tz) + (size_t)dir * C * 64;
   gfloat *ts = gptr(E.ts) + (size_t)dir * C * 64;
   double z = 0.0;
@@ -434,7 +422,7 @@ __global__ __launch_bounds__(64) void k_em_sweep_scan(const EmDesc *__restrict__
     load_cols<NR>(tm + (size_t)c * N * 64, tz + (size_t)c * 64, N, r, k);
   };
   auto step = [&](int c, const ScanCols<NR> &k) {
-    v = scan_step<NR>(k, pbuf, live, r, v, z);
+    v = scan_step<NR>(k, buf, live, r, N, v, z);
     if (c + 1 < C) ts[(size_t)(c + 1) * 64 + r] = v;
   };
   ScanCols<NR> ka, kb;
@@ -459,8 +447,8 @@ __global__ __launch_bounds__(64) void k_em_sweep_fin(const EmDesc *__restrict__ 
   if (it >= E.iters || (int)blockIdx.x >= 2 * C) return;
   const int dir = blockIdx.x / C, c = blockIdx.x - dir * C, r = threadIdx.x;
   const bool live = r < N;
-  __shared__ double pbuf[64];
-  double a[NR];
+  __shared__ float buf[64];
+  float a[NR];
   if (dir == 0) {
     a_lane<NR>(E.lnA, N, r, true, a);
     float la;
@@ -472,7 +460,7 @@ __global__ __launch_bounds__(64) void k_em_sweep_fin(const EmDesc *__restrict__ 
       la = E.ts[(size_t)c * 64 + r];
     }
     const int t0 = fwd_chunk_begin(c);
-    fwd_steps<NR, true>(gptr(E.x), gptr(E.la), a, pbuf, live, r, t0, min(t0 + kEmSweepChunk, T), T, la);
+    fwd_steps<NR, true>(gptr(E.x), gptr(E.la), a, buf, live, r, t0, min(t0 + kEmSweepChunk, T), T, la);
   } else {
     a_lane<NR>(E.lnA, N, r, false, a);
     float lb;
@@ -483,7 +471,7 @@ __global__ __launch_bounds__(64) void k_em_sweep_fin(const EmDesc *__restrict__ 
       lb = E.ts[(size_t)(C + c) * 64 + r];
     }
     const int t0 = bwd_chunk_begin(T, c);
-    bwd_steps<NR, true>(gptr(E.x), gptr(E.sI), gptr(E.lbn), a, pbuf, live, r, t0, max(t0 - kEmSweepChunk, 0), lb);
+    bwd_steps<NR, true>(gptr(E.x), gptr(E.sI), gptr(E.lbn), a, buf, live, r, t0, max(t0 - kEmSweepChunk, 0), lb);
   }
 }
 

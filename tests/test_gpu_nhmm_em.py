@@ -5,9 +5,9 @@ from the model of Section 2.1; the reference is pinned in tests/test_nhmm_em_pin
 Both start from the same float32 parameters and run the same number of
 iterations; every learned parameter and the log-likelihood trace are compared
 element by element.  The GPU keeps beta and theta in double between iterations
-and keeps the chain's messages as float32 logarithms (A and pi too), with each
-step's sums in double, treating as zero what underflows a double, as the reference
-does; the differences are the chain's float32 rounding carried through the
+and keeps the chain's messages as float32 logarithms (A and pi too), each step a
+log-sum-exp per lane, treating as zero what underflows a double (subnormals
+still count), as the reference does; the differences are the chain's float32 rounding carried through the
 updates.  Chains of T >= 98 frames take the time-parallel forward-backward when
 the batch is small (one problem always is), the others and every chain of a batch
 past 2^19 state-frames the sequential one: both are checked here.  Tolerances: dictionaries
@@ -86,6 +86,21 @@ def test_em_paper_shape(L, ctx):
     r = _oracle(p, 3)
     e = _errs(g, r)
     print(f"\npaper shape x3: {_fmt(e)}")
+    for k, tol in TOL.items():
+        assert e[k] <= tol, (k, e[k])
+
+
+def test_em_far_tails_time_parallel(L, ctx):
+    """A 200-frame, 10-state chain (the time-parallel forward-backward) on which the
+    FP64 reference drives dozens of transitions below the float32 range (42 entries
+    of A between 0 and 1e-38 after the first iteration, 2 after the eighth), the
+    values a later iteration can bring back: the GPU keeps them as the reference
+    does."""
+    p = make_nhmm_problem(1, 5, N=10, K=4, F=40, T=200, iters=8)
+    g = L.learn_nhmm(ctx, p)
+    r = _oracle(p, 8)
+    e = _errs(g, r)
+    print(f"\nfar tails x8: {_fmt(e)}")
     for k, tol in TOL.items():
         assert e[k] <= tol, (k, e[k])
 
