@@ -91,18 +91,20 @@ def test_em_paper_shape(L, ctx):
 
 
 def test_em_far_tails_time_parallel(L, ctx):
-    """A 200-frame, 10-state chain (the time-parallel forward-backward) on which the
-    FP64 reference drives dozens of transitions below the float32 range (42 entries
-    of A between 0 and 1e-38 after the first iteration, 2 after the eighth), the
-    values a later iteration can bring back: the GPU keeps them as the reference
-    does."""
+    """A 200-frame, 10-state chain on which the FP64 reference drives dozens of
+    transitions below the float32 range (42 entries of A between 0 and 1e-38 after
+    the first iteration, 2 after the eighth; some with subnormal counts, one of
+    which comes back to e^-506), the values a later iteration can bring back: the
+    GPU keeps them as the reference does, alone (the time-parallel forward-backward)
+    and in a batch past 2^19 state-frames (the sequential one)."""
     p = make_nhmm_problem(1, 5, N=10, K=4, F=40, T=200, iters=8)
-    g = L.learn_nhmm(ctx, p)
     r = _oracle(p, 8)
-    e = _errs(g, r)
-    print(f"\nfar tails x8: {_fmt(e)}")
-    for k, tol in TOL.items():
-        assert e[k] <= tol, (k, e[k])
+    big = [make_nhmm_problem(1, 60 + i, K=4, F=64, iters=1) for i in range(14)]
+    for tag, g in (("time-parallel", L.learn_nhmm(ctx, p)), ("sequential", L.learn_nhmm_batch(ctx, [p] + big)[0])):
+        e = _errs(g, r)
+        print(f"\nfar tails x8 {tag}: {_fmt(e)}")
+        for k, tol in TOL.items():
+            assert e[k] <= tol, (tag, k, e[k])
 
 
 def test_em_sequential_sweeps_past_the_line(L, ctx):
